@@ -1,0 +1,279 @@
+"""Pins of the oracle's transport steps (gradients, limiter, closure, HLL
+flux, update) against results fixed by the paper's definitions and by
+textbook special cases, independent of the oracle's own formulas."""
+import numpy as np
+import pytest
+
+import oracle
+import rtgen
+from rtgen.configs import CHEM_NONE
+
+
+def small_mesh(dims=(6, 6, 6), h=1.0, jitter=0.2, seed=7, order="hilbert"):
+    return rtgen.jittered_lattice(dims, h, jitter, seed, order)
+
+
+def transport_cfg(mesh, N, Fh, c=1.0, n_sub=1, limiter=1):
+    """Transport-only config (no chemistry, no sources) on a given mesh."""
+    p = rtgen.default_params(1)
+    p.update(chem_mode=CHEM_NONE, c_reduced=c, use_limiter=limiter)
+    st = rtgen.neutral_state(1, mesh.n_cells, 1.0, 1.0e4)
+    st["N"] = np.asarray(N, float).reshape(1, -1).copy()
+    st["F"] = (np.asarray(Fh, float) * c).reshape(1, 3, -1).copy()
+    return dict(name="t", mesh=mesh.as_dict(), params=p, state=st,
+                sources=dict(cell=np.zeros(0, np.int64), rate=np.zeros((1, 0))),
+                n_subcycles=n_sub, precision="fp64", meta=dict(dims=mesh.dims, h=mesh.h))
+
+
+def separations(mesh):
+    """d_ij = s_j - s_i through each face, per face side: list of (i, j, area, d)."""
+    out = []
+    nf = mesh.n_faces
+    for f in range(nf):
+        L, R = mesh.face_cells[:, f]
+        xf = mesh.face_centre[:, f]
+        rL = xf - mesh.centre[:, L]
+        rR = xf - mesh.centre[:, R]
+        rL -= mesh.box * np.round(rL / mesh.box)
+        rR -= mesh.box * np.round(rR / mesh.box)
+        out.append((L, R, mesh.area[f], rL - rR, rL))
+        out.append((R, L, mesh.area[f], rR - rL, rR))
+    return out
+
+
+# --- closure and flux --------------------------------------------------------
+
+def test_levermore_closed_forms():
+    assert oracle.chi(0.0) == pytest.approx(1.0 / 3.0, abs=1e-15)
+    assert oracle.chi(1.0) == pytest.approx(1.0, abs=1e-15)
+    f = np.linspace(0, 1, 101)
+    chi = np.array([oracle.chi(v) for v in f])
+    assert np.all(np.diff(chi) > 0)
+    assert np.all((chi >= 1 / 3 - 1e-15) & (chi <= 1 + 1e-15))
+
+
+@pytest.mark.parametrize("f", [0.0, 0.3, 0.8, 1.0])
+def test_eddington_tensor_trace_and_free_streaming(f):
+    # The physical flux is HLL(U, U): flux of Fh along n is c N D n, so the
+    # columns of D come from the three axis normals.
+    rng = np.random.default_rng(1)
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    N = 2.5
+    U = np.array([N, *(f * N * u)])
+    c = 3.0
+    D = np.zeros((3, 3))
+    for k in range(3):
+        n = np.eye(3)[k]
+        out = oracle.hll_flux(U, U, n, c)
+        assert out[0] == pytest.approx(c * U[1 + k], rel=1e-14, abs=1e-14)
+        D[:, k] = out[1:] / (c * N)
+    assert np.trace(D) == pytest.approx(1.0, abs=1e-14)
+    assert np.allclose(D, D.T, atol=1e-14)
+    if f == 1.0:
+        assert np.allclose(D, np.outer(u, u), atol=1e-14)   # free streaming
+    if f == 0.0:
+        assert np.allclose(D, np.eye(3) / 3, atol=1e-14)    # isotropic
+
+
+def test_m1_wave_speeds_bounded_by_c():
+    """Eigenvalues of the 1-D M1 flux Jacobian lie in [-c, c], so HLL with the
+    bounds -c and +c is a valid (Rusanov) solver."""
+    rng = np.random.default_rng(2)
+    c = 1.0
+    n = np.array([1.0, 0.0, 0.0])
+    for _ in range(200):
+        f = rng.uniform(0, 0.999)
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        U = np.array([1.0, *(f * u)])
+        J = np.zeros((4, 4))
+        eps = 1e-7
+        for k in range(4):
+            e = np.zeros(4)
+            e[k] = eps
+            J[:, k] = (oracle.hll_flux(U + e, U + e, n, c) - oracle.hll_flux(U - e, U - e, n, c)) / (2 * eps)
+        lam = np.linalg.eigvals(J)
+        assert np.max(np.abs(lam.imag)) < 1e-5
+        assert np.max(np.abs(lam.real)) <= c * (1 + 1e-5)
+
+
+def test_hll_flux_is_rusanov_of_physical_flux():
+    rng = np.random.default_rng(3)
+    c = 2.0
+    for _ in range(20):
+        UL = np.array([1.0, *rng.uniform(-0.5, 0.5, 3)])
+        UR = np.array([0.7, *rng.uniform(-0.3, 0.3, 3)])
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        FL = oracle.hll_flux(UL, UL, n, c)
+        FR = oracle.hll_flux(UR, UR, n, c)
+        assert np.allclose(oracle.hll_flux(UL, UR, n, c), 0.5 * (FL + FR) - 0.5 * c * (UR - UL), rtol=1e-13,
+                           atol=1e-13)
+
+
+# --- gradients ----------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(6, 6, 6), (2, 2, 2), (5, 3, 4)])
+def test_gradient_minimises_weighted_least_squares(dims):
+    """Unlimited gradient = argmin of S_tot (Section 2.3.2) solved by numpy's lstsq."""
+    mesh = small_mesh(dims)
+    rng = np.random.default_rng(11)
+    phi = rng.normal(size=mesh.n_cells)
+    g = oracle.gradients(mesh.as_dict(), phi, use_limiter=False)
+    rows = {i: [] for i in range(mesh.n_cells)}
+    for i, j, A, d, _ in separations(mesh):
+        rows[i].append((np.sqrt(A) / np.linalg.norm(d), d, phi[j] - phi[i]))
+    for i in range(mesh.n_cells):
+        W = np.array([w for w, _, _ in rows[i]])
+        Mx = np.array([d for _, d, _ in rows[i]]) * W[:, None]
+        b = np.array([v for _, _, v in rows[i]]) * W
+        ref = np.linalg.lstsq(Mx, b, rcond=None)[0]
+        assert np.allclose(g[:, i], ref, rtol=1e-11, atol=1e-12)
+
+
+def test_gradient_exact_for_linear_field():
+    mesh = small_mesh((8, 8, 8), h=0.5, order="lattice")
+    a = np.array([0.3, -1.2, 2.0])
+    phi = mesh.centre.T @ a + 4.0
+    g = oracle.gradients(mesh.as_dict(), phi, use_limiter=False)
+    ix = mesh.lattice_index
+    interior = np.all((ix >= 1) & (ix <= 6), axis=0)
+    assert np.allclose(g[:, interior], a[:, None], rtol=0, atol=1e-12)
+    # The limiter leaves a linear field alone away from the periodic seam.
+    gl = oracle.gradients(mesh.as_dict(), phi, use_limiter=True)
+    deep = np.all((ix >= 2) & (ix <= 5), axis=0)
+    assert np.allclose(gl[:, deep], a[:, None], rtol=0, atol=1e-12)
+
+
+def test_unjittered_lattice_is_central_differences():
+    h = 0.25
+    mesh = small_mesh((6, 5, 4), h=h, jitter=0.0, order="random")
+    Minv = oracle.geometry_minv(mesh.as_dict())
+    assert np.allclose(Minv[:3], 1 / (2 * h * h), rtol=1e-14)
+    assert np.allclose(Minv[3:], 0, atol=1e-14)
+    rng = np.random.default_rng(5)
+    phi = rng.normal(size=mesh.n_cells)
+    g = oracle.gradients(mesh.as_dict(), phi, use_limiter=False)
+    nx, ny, nz = mesh.dims
+    lex = mesh.lattice_index[0] + nx * (mesh.lattice_index[1] + ny * mesh.lattice_index[2])
+    cell_of = np.empty_like(lex)
+    cell_of[lex] = np.arange(lex.size)
+    P = phi[cell_of].reshape(nz, ny, nx)
+    ref = [(np.roll(P, -1, 2) - np.roll(P, 1, 2)) / (2 * h),
+           (np.roll(P, -1, 1) - np.roll(P, 1, 1)) / (2 * h),
+           (np.roll(P, -1, 0) - np.roll(P, 1, 0)) / (2 * h)]
+    for k in range(3):
+        assert np.allclose(g[k, cell_of], ref[k].reshape(-1), rtol=1e-12, atol=1e-12)
+
+
+def test_limiter_creates_no_new_extrema():
+    mesh = small_mesh((6, 6, 6))
+    rng = np.random.default_rng(9)
+    phi = rng.normal(size=mesh.n_cells)
+    g = oracle.gradients(mesh.as_dict(), phi, use_limiter=True)
+    lo = phi.copy()
+    hi = phi.copy()
+    seps = separations(mesh)
+    for i, j, _, _, _ in seps:
+        lo[i] = min(lo[i], phi[j])
+        hi[i] = max(hi[i], phi[j])
+    for i, _, _, _, r in seps:
+        v = phi[i] + g[:, i] @ r
+        assert lo[i] - 1e-12 <= v <= hi[i] + 1e-12
+
+
+# --- whole transport step -------------------------------------------------------
+
+def muscl_mc_rusanov_1d(N, Fx, h, dt, c, n_sub):
+    """Textbook 1-D scheme: MC-limited linear reconstruction, Rusanov flux with
+    speed c, forward Euler.  Flux of (N, Fx) is c (Fx, chi(|Fx|/N) N)."""
+    chi = np.vectorize(oracle.chi)
+    U = np.stack([N, Fx]).astype(float)
+    for _ in range(n_sub):
+        a = np.roll(U, -1, 1) - U
+        b = U - np.roll(U, 1, 1)
+        s = np.where(a * b > 0, np.sign(a) * np.minimum(np.minimum(np.abs(a + b) / 2, 2 * np.abs(a)),
+                                                        2 * np.abs(b)), 0.0)
+        UL = U + s / 2                      # left state of face i+1/2
+        UR = np.roll(U - s / 2, -1, 1)      # right state of face i+1/2
+
+        def phys(V):
+            return np.stack([c * V[1], c * chi(np.abs(V[1]) / V[0]) * V[0]])
+
+        flux = 0.5 * (phys(UL) + phys(UR)) - 0.5 * c * (UR - UL)
+        U = U - dt / h * (flux - np.roll(flux, 1, 1))
+    return U
+
+
+def test_transport_reduces_to_1d_muscl_mc_rusanov():
+    nx = 32
+    h = 1.0 / nx
+    mesh = rtgen.jittered_lattice((nx, 2, 2), h, 0.0, 0, "random")
+    x = mesh.centre[0]
+    N = 1.0 + 0.5 * np.sin(2 * np.pi * x) + 0.2 * (x > 0.5)
+    Fx = 0.3 * np.cos(2 * np.pi * x) * N
+    Fh = np.stack([Fx, np.zeros_like(x), np.zeros_like(x)])
+    cfg = transport_cfg(mesh, N, Fh, c=1.0, n_sub=12)
+    out = oracle.run(cfg)
+    d = out["diag"]
+    assert d["flux_caps"] == 0 and d["adm_N"] == 0 and d["adm_F"] == 0 and d["guard_N"] == 0
+    # Same problem in 1-D, cells in lattice order.
+    order = np.argsort(mesh.lattice_index[0] + nx * (mesh.lattice_index[1] + 2 * mesh.lattice_index[2]))
+    row = order[:nx]
+    ref = muscl_mc_rusanov_1d(N[row], Fx[row], h, d["dt"], 1.0, 12)
+    got_N = out["N"][0]
+    got_F = out["F"][0] / 1.0
+    for blk in range(4):
+        cells = order[blk * nx:(blk + 1) * nx]
+        assert np.allclose(got_N[cells], ref[0], rtol=1e-13, atol=1e-13)
+        assert np.allclose(got_F[0, cells], ref[1], rtol=1e-13, atol=1e-13)
+        assert np.allclose(got_F[1:, cells], 0.0, atol=1e-13)
+
+
+def test_uniform_state_is_invariant():
+    mesh = small_mesh((6, 6, 6))
+    nc = mesh.n_cells
+    N = np.full(nc, 3.0)
+    Fh = np.tile(np.array([[0.4], [-0.7], [1.1]]), (1, nc))
+    out = oracle.run(transport_cfg(mesh, N, Fh, c=2.0, n_sub=5))
+    assert np.allclose(out["N"][0], 3.0, rtol=1e-14)
+    assert np.allclose(out["F"][0] / 2.0, Fh, rtol=1e-13, atol=1e-14)
+
+
+def travelling_wave_fit(n):
+    """Amplitude and phase of the fundamental after the same physical time at
+    resolution n (n subcycles; dt scales with h)."""
+    cfg = rtgen.travelling_wave(n=n, n_sub=n, amplitude=0.1)
+    out = oracle.run(cfg)
+    t = n * out["diag"]["dt"]
+    x = cfg["mesh"]["centre"]
+    ph = 2 * np.pi * (x[0] + x[1] + x[2])
+    A = np.stack([np.ones_like(ph), np.sin(ph), np.cos(ph)], 1)
+    cf = np.linalg.lstsq(A, out["N"][0], rcond=None)[0]
+    amp = np.hypot(cf[1], cf[2]) / 0.1
+    phase_err = np.arctan2(cf[2], cf[1]) + 2 * np.pi * np.sqrt(3.0) * t
+    return amp, abs(phase_err), cf[0]
+
+
+def test_travelling_wave_converges_to_exact_advection():
+    """The wave moves at c along (1,1,1) (exact free streaming, f = 1).  With
+    forward-Euler subcycles (the paper uses no time extrapolation while
+    subcycling) the limited second-order reconstruction keeps the amplitude
+    bounded while the phase error falls at second order."""
+    res = {n: travelling_wave_fit(n) for n in (8, 16, 32)}
+    for n, (amp, perr, mean) in res.items():
+        assert 0.85 < amp < 1.15
+    assert res[16][1] < res[8][1] / 3
+    assert res[32][1] < res[16][1] / 3
+
+
+def test_travelling_wave_conserves_photons_exactly():
+    cfg = rtgen.travelling_wave(n=12, n_sub=1)
+    V = cfg["mesh"]["volume"]
+    total0 = np.sum(cfg["state"]["N"][0] * V)
+    st = cfg
+    for k in range(8):
+        out = oracle.run(st)
+        assert abs(out["diag"]["photon_sum"][0] - total0) <= 1e-14 * total0 * (k + 1)
+        st = dict(cfg, state=dict(N=out["N"], F=out["F"], n_H=out["n_H"], species=out["species"], T=out["T"]))
