@@ -1,0 +1,225 @@
+"""Benchmark of the M1 radiative-transfer subcycle on one MI355X.
+
+A step is one subcycle (sources, chemistry, gradients, fluxes + update) of
+the throughput workload: a 256^3 jittered periodic lattice (16.8M cells) in
+Peano-Hilbert order, lognormal H+He gas (sigma_ln = 1.5, mean n_H = 2e-4),
+3 frequency bins, 4096 power-law sources, c~ = 0.1 c, 200 subcycles.  The
+headline is the mixed-precision form (FP32 transport, FP64 chemistry and
+sums); the FP64 form and the random cell order are timed beside it, and the
+mixed result is compared with the FP64 one.
+
+    python bench.py [--steps 200] [--warmup 5] [--gpus 1]
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region;
+the timed region is one rt_subcycle call of K subcycles, bracketed by
+device synchronisations.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBS = 8000.0
+KERNELS = ("k_sources", "k_chem", "k_gradient", "k_flux", "k_reduce")
+TRAFFIC_FILE = ROOT / "profiles" / "traffic.json"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel: str, nc: int, nb: int, nf: int, n_sides: int, n_src: int, p: int, g: int) -> float:
+    """Compulsory HBM bytes of one launch: each array element the kernel must
+    read or write, counted once (neighbour gathers and per-bin geometry
+    re-reads assumed to hit cache).  p = bytes per transport value, g = bytes
+    per geometry value, indices 4 bytes."""
+    idx = 8 * n_sides                                   # neighbour + signed face index per face side
+    if kernel == "k_gradient":
+        return nc * nb * (4 + 12) * p + nc * 6 * g + nf * 7 * g + idx
+    if kernel == "k_flux":
+        return nc * nb * (4 + 12 + 4) * p + nc * 2 * g + nf * 10 * g + idx
+    if kernel == "k_chem":
+        return nc * (8 * nb * p + 2 * 5 * 8 + 2 * 8 + 8)
+    if kernel == "k_sources":
+        return n_src * (nb * 8 + 16) + 2 * n_src * nb * p
+    return 0.0
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in sorted((ROOT / "paper_2404_17630_amd" / "csrc").glob("*")):
+        h.update(f.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def timed_run(rt, mesh, cfg, precision, steps, warmup, torch):
+    """Warm up on a clone, then time `steps` subcycles from the initial state."""
+    state = rt.State.from_config(mesh, cfg, precision=precision)
+    stream = torch.cuda.current_stream()
+    if warmup > 0:
+        w = state.clone()
+        w.subcycle(warmup, stream=stream)
+        w.close()
+    rt.rt_profile_enable(state.h, True)
+    rt.rt_profile_reset(state.h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    state.subcycle(steps, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {KERNELS[k]: rt.rt_profile_read(state.h, k) for k in range(len(KERNELS))}
+    return state, t1 - t0, prof
+
+
+def cpu_baseline():
+    """The oracle as it stands, single-threaded, on a bounded sample of the same
+    recipe: a 64^3 lattice (262,144 cells) with 64 sources, 2 subcycles."""
+    import oracle
+    import rtgen
+    cfg = rtgen.cosmological(64, 1.0, 1.5, 64, 0.1, 2, 4, name="throughput_sample")
+    out = oracle.run(cfg)
+    secs = out["diag"]["loop_seconds"]
+    nc, nb = cfg["mesh"]["n_cells"], cfg["params"]["nb"]
+    return dict(value=nc * nb * 2 / secs, unit="cell*bin updates/s", cores=1, kind="oracle",
+                sample="throughput recipe at 64^3 (262,144 cells, sigma_ln=1.5, 64 sources, 3 bins, c~=0.1c), "
+                       f"2 subcycles from the initial state, {secs:.2f} s single-threaded")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256, help="cells per side (256 = the throughput workload)")
+    ap.add_argument("--no-extras", action="store_true", help="time only the mixed Hilbert-order run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the design of one is in "
+              "DESIGN.md); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import rtgen
+    from paper_2404_17630_amd import rt
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    rt.lib()
+    torch.cuda.set_device(0)
+    n_src = max(1, int(round(4096 * (args.n / 256) ** 3)))
+    log(f"generating throughput workload {args.n}^3, {n_src} sources")
+    cfg = rtgen.throughput_16m(n=args.n, n_src=n_src, n_sub=args.steps)
+    nc, nb, nf = cfg["mesh"]["n_cells"], cfg["params"]["nb"], cfg["mesh"]["n_faces"]
+    n_sides = 2 * nf
+    log("creating mesh")
+    mesh = rt.Mesh(cfg["mesh"])
+
+    log(f"mixed, hilbert: {args.steps} subcycles")
+    st_mixed, t_mixed, prof_mixed = timed_run(rt, mesh, cfg, rt.RT_MIXED, args.steps, args.warmup, torch)
+    value = nc * nb * args.steps / t_mixed
+    diag = st_mixed.diagnostics()
+    if diag["status"] != 0:
+        raise SystemExit(f"mixed run status {diag['status']}")
+
+    def kernel_table(prof, p, g):
+        tab = {}
+        for name, (launches, ms) in prof.items():
+            if launches == 0:
+                continue
+            avg = ms / launches
+            algo = algorithmic_bytes(name, nc, nb, nf, n_sides, cfg["sources"]["cell"].size, p, g)
+            tab[name] = dict(launches=launches, avg_ms=avg, algo_bytes=algo,
+                             gbs=algo / (avg * 1e-3) / 1e9 if algo else None)
+        return tab
+
+    kt_mixed = kernel_table(prof_mixed, 4, 4)
+    dominant = max((k for k in kt_mixed if k != "k_reduce"), key=lambda k: kt_mixed[k]["avg_ms"] * kt_mixed[k]["launches"])
+    dk = kt_mixed[dominant]
+
+    traffic = None
+    if TRAFFIC_FILE.exists():
+        rec = json.loads(TRAFFIC_FILE.read_text())
+        ent = rec.get("kernels", {}).get(dominant)
+        if ent and rec.get("source_digest") == kernel_source_digest() and rec.get("workload") == f"throughput_{args.n}":
+            traffic = ent["bytes_per_launch"]
+
+    out = {
+        "metric": "RT cell*bin updates/s per subcycle (mixed precision), with FP64 speedup, error and % HBM peak",
+        "value": value,
+        "unit": "cell*bin updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mixed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"throughput_{args.n}", "cells": nc, "bins": nb, "sources": int(n_src),
+                   "subcycles": args.steps, "order": "hilbert", "precision": "mixed", "c_reduced": "0.1c",
+                   "sigma_ln": 1.5},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic},
+        "kernels_mixed": kt_mixed,
+    }
+
+    if not args.no_extras:
+        fields_mixed = st_mixed.fields()
+        st_mixed.close()
+        log(f"fp64, hilbert: {args.steps} subcycles")
+        st64, t64, prof64 = timed_run(rt, mesh, cfg, rt.RT_FP64, args.steps, args.warmup, torch)
+        f64 = st64.fields()
+        st64.close()
+        v64 = nc * nb * args.steps / t64
+        N64, Nm = f64["N"], fields_mixed["N"]
+        errN = 0.0
+        for b in range(nb):
+            mask = N64[b] > 1e-10 * N64[b].max()
+            errN = max(errN, float((np.abs(Nm[b][mask] - N64[b][mask]) / N64[b][mask]).max()))
+        out["fp64_value"] = v64
+        out["fp64_ms_per_step"] = t64 / args.steps * 1e3
+        out["mixed_speedup_vs_fp64"] = value / v64
+        out["mixed_error_vs_fp64"] = {
+            "N_rel_max(N>1e-10 max)": errN,
+            "x_HII_abs_max": float(np.abs(fields_mixed["species"][1] - f64["species"][1]).max()),
+            "y_HeII_abs_max": float(np.abs(fields_mixed["species"][3] - f64["species"][3]).max()),
+            "T_rel_max": float((np.abs(fields_mixed["T"] - f64["T"]) / f64["T"]).max()),
+        }
+        out["kernels_fp64"] = kernel_table(prof64, 8, 8)
+        del fields_mixed, f64
+        mesh.close()
+        log("random cell order (mixed)")
+        cfg_r = rtgen.random_order(cfg)
+        mesh_r = rt.Mesh(cfg_r["mesh"])
+        st_r, t_r, prof_r = timed_run(rt, mesh_r, cfg_r, rt.RT_MIXED, args.steps, args.warmup, torch)
+        st_r.close()
+        mesh_r.close()
+        out["random_order_value"] = nc * nb * args.steps / t_r
+        out["kernels_mixed_random"] = kernel_table(prof_r, 4, 4)
+    else:
+        st_mixed.close()
+        mesh.close()
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,211 @@
+/*
+ * rt.h -- C ABI of the M1 radiative-transfer subcycle on one MI355X (gfx950).
+ *
+ * The library advances the photon fields and the gas chemistry of a static
+ * mesh by radiative-transfer subcycles, as in Zier et al. (2024), "Adapting
+ * AREPO-RT for Exascale Computing", Sections 2.2-2.3 and 4.1: the M1 moment
+ * equations (eq. E, eq. F) for the photon number density N_b and flux F_b of
+ * each frequency bin, closed by the M1 Eddington tensor (eq. edd) and written
+ * in finite-volume form (eq. RT_flux); the per-cell non-equilibrium H/He
+ * thermochemistry of Section 2.3.1 integrated with the adaptive semi-implicit
+ * scheme of Section 4.1.1.  One subcycle is, in the order of Fig. 1:
+ * point sources, thermochemistry, gradients (Sec. 2.3.2), fluxes and update
+ * (Sec. 2.3.3).
+ *
+ * Conventions
+ *  - Every function returns an int status: RT_OK (0) or a negative RT_E*
+ *    code; rt_last_error() returns a thread-local message for the last
+ *    failure on the calling thread.
+ *  - Arrays are structure-of-arrays in the CALLER's cell and face order
+ *    ("[3][nc]" = three contiguous arrays of nc values).  The library never
+ *    reorders cells: a locality-friendly order (e.g. Peano-Hilbert) is the
+ *    caller's choice.  Units are cgs.
+ *  - Input pointers may be host or device memory (detected per pointer); the
+ *    library copies every input at create time and the caller keeps
+ *    ownership of its buffers.
+ *  - Handles are owned by the caller until destroyed.  A state keeps its mesh
+ *    alive: destroying a mesh that still has states only drops the caller's
+ *    reference.
+ *  - On any error a state is left unchanged.
+ *  - Calls on one state are not thread-safe; distinct states may be used from
+ *    distinct threads.
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define RT_OK        0
+#define RT_EINVAL   -1   /* bad argument (null pointer, size, parameter out of range, dt above the CFL step) */
+#define RT_EMESH    -2   /* bad mesh: index out of range, L == R, V <= 0, A <= 0, |n| != 1 +- 1e-12,
+                            a cell with fewer than 4 faces, or cond(M_i) > 1e12 */
+#define RT_ESTATE   -3   /* state/mesh mismatch, or an operation the state does not support */
+#define RT_EDEVICE  -4   /* HIP runtime error */
+#define RT_ENOMEM   -5   /* allocation failure */
+#define RT_ENUMERIC -6   /* a non-finite value appeared, or a cell hit the chemistry substep cap */
+
+/* ---- enumerations ---------------------------------------------------- */
+#define RT_MAX_BINS 8
+
+#define RT_FP64  0        /* transport, chemistry and sums in FP64 */
+#define RT_MIXED 1        /* transport in FP32 with per-bin power-of-two scaling of N and F;
+                             chemistry, flux sums and photon sums in FP64 (Sec. 6.2) */
+
+#define RT_CHEM_NONE 0    /* transport only (no absorption, no chemistry) */
+#define RT_CHEM_H    1    /* hydrogen only */
+#define RT_CHEM_HHE  2    /* hydrogen and helium */
+
+#define RT_RATES_CASEB_CONST 0   /* constant case-B recombination alpha_B_const, no collisional
+                                    ionisation, no cooling; hydrogen only, isothermal */
+#define RT_RATES_HG97        1   /* Hui & Gnedin (1997) case-B recombination, collisional ionisation
+                                    and their cooling; Cen (1992) dielectronic recombination,
+                                    collisional-excitation cooling and free-free emission */
+
+/* Fields for rt_state_get_field / rt_state_set_field (FP64, caller order). */
+#define RT_FIELD_N       0   /* [nb][nc]    photon number density, cm^-3 */
+#define RT_FIELD_F       1   /* [nb][3][nc] photon flux, cm^-2 s^-1 */
+#define RT_FIELD_NH      2   /* [nc]        hydrogen number density, cm^-3 (get only) */
+#define RT_FIELD_SPECIES 3   /* [5][nc]     x_HI, x_HII, y_HeI, y_HeII, y_HeIII */
+#define RT_FIELD_T       4   /* [nc]        gas temperature, K */
+
+/* Kernel ids for the profiling counters. */
+#define RT_KERNEL_SOURCES  0
+#define RT_KERNEL_CHEM     1
+#define RT_KERNEL_GRADIENT 2
+#define RT_KERNEL_FLUX     3
+#define RT_KERNEL_REDUCE   4
+#define RT_N_KERNELS       5
+
+/* ---- parameters ------------------------------------------------------ */
+/* Every constant the paper leaves open.  rt_params_default fills the values
+ * used throughout (eta = 0.3 per eq. timestep; f_max = 0.1, f_s = 0.05 and the
+ * doubling cap per Sec. 4.1.1). */
+typedef struct rt_params {
+    int32_t nb;                 /* frequency bins, 1..RT_MAX_BINS */
+    int32_t chem_mode;          /* RT_CHEM_* */
+    int32_t isothermal;         /* 1: T fixed at T_iso, no energy equation */
+    int32_t rate_set;           /* RT_RATES_* */
+    int32_t use_limiter;        /* 1: slope limiter on (Sec. 2.3.2) */
+    int32_t chem_max_substeps;  /* attempts per cell and subcycle before RT_ENUMERIC */
+    double c_reduced;           /* reduced speed of light c~, cm/s (Sec. 2.2, RSLA) */
+    double cfl_eta;             /* Courant number eta (eq. timestep) */
+    double T_iso;               /* K, isothermal runs */
+    double Y_He;                /* helium mass fraction (RT_CHEM_HHE) */
+    double alpha_B_const;       /* cm^3/s, RT_RATES_CASEB_CONST */
+    double gamma;               /* adiabatic index */
+    double chem_fmax;           /* reject a chemistry step if the largest relative change exceeds this */
+    double chem_fs;             /* target relative change per step */
+    double chem_growth;         /* largest step growth factor between steps */
+    double chem_xfloor;         /* floor of the fraction in the relative-change denominator */
+    double sigma[RT_MAX_BINS][3];   /* mean cross-section per bin for HI, HeI, HeII, cm^2 */
+    double e_heat[RT_MAX_BINS][3];  /* mean excess energy per absorption, erg */
+} rt_params;
+
+/* Diagnostics of the last rt_subcycle call (sums over its subcycles). */
+typedef struct rt_diag {
+    double dt;                          /* subcycle length used, s */
+    double photon_sum[RT_MAX_BINS];     /* sum_i N_i V_i per bin after the call (FP64) */
+    double scale[RT_MAX_BINS];          /* per-bin FP32 storage scale (RT_MIXED), 1 in RT_FP64 */
+    int64_t guard_N, guard_F;           /* post-update clamps N < 0 and |F|/c~ > N */
+    int64_t adm_N, adm_F;               /* face-state admissibility fixes, counted once per face */
+    int64_t flux_caps;                  /* faces whose outflow cap was active */
+    int64_t substeps;                   /* chemistry step attempts, summed over cells */
+    int64_t max_substeps;               /* largest attempts of one cell in one subcycle */
+    int32_t status;                     /* bit 0: non-finite value, bit 1: substep cap */
+    int32_t n_subcycles;                /* subcycles in the call */
+} rt_diag;
+
+typedef struct rt_mesh rt_mesh;
+typedef struct rt_state rt_state;
+
+/* Message of the last failure on this thread ("" if none). */
+const char* rt_last_error(void);
+
+/* Fill *p with the defaults for nb bins (hydrogen, isothermal 1e4 K, rate set
+ * 0, c~ = 0.01 c, eta = 0.3, limiter on, controller 0.1 / 0.05 / 2 / 1e-6 /
+ * 1e5, gamma = 5/3, zero cross-sections). */
+int rt_params_default(int32_t nb, rt_params* p);
+
+/* Create a static mesh on HIP device `device`.
+ *   volume [nc] cm^3, centre [3][nc] cm (the point gradients are taken about,
+ *   s_i of Sec. 2.3.2), face_cells [2][nf] (L, R) cell indices, area [nf] cm^2,
+ *   normal [3][nf] unit normal pointing from L to R, face_centre [3][nf] cm,
+ *   box[3] periodic box lengths (0 = open axis; offsets use the minimum image).
+ * Precomputes the minimum-image face offsets, the least-squares geometry
+ * matrices M_i = sum_j A_ij n_ji n_ji^T and their inverses (Sec. 2.3.2: the
+ * matrix depends on geometry only and is reused between subcycles), the
+ * per-cell face lists in face-index order (Sec. 4.1.4) and the CFL length
+ * (3V/4pi)^(1/3) (eq. timestep).  Errors: RT_EINVAL, RT_EMESH, RT_EDEVICE,
+ * RT_ENOMEM. */
+int rt_mesh_create(int64_t n_cells, const double* volume, const double* centre,
+                   int64_t n_faces, const int64_t* face_cells, const double* area,
+                   const double* normal, const double* face_centre, const double box[3],
+                   int device, rt_mesh** out);
+int rt_mesh_destroy(rt_mesh* mesh);
+
+/* Create a radiation + gas state on a mesh.
+ *   precision: RT_FP64 or RT_MIXED.
+ *   N [nb][nc] photon number density (cm^-3), F [nb][3][nc] photon flux
+ *   (cm^-2 s^-1; |F| <= c~ N), n_H [nc] (cm^-3), species [5][nc] = x_HI,
+ *   x_HII, y_HeI, y_HeII, y_HeIII (helium fractions of helium), T [nc] (K).
+ *   Sources: src_cell [n_src] cell indices, src_rate [nb][n_src] photons/s.
+ * The subcycle length is the global CFL step eta min_i (3V_i/4pi)^(1/3) / c~
+ * (eq. timestep with v_c = 0), computed here by a device min-reduction.
+ * Errors: RT_EINVAL (parameters or arrays), RT_EDEVICE, RT_ENOMEM. */
+int rt_state_create(const rt_mesh* mesh, const rt_params* params, int precision,
+                    const double* N, const double* F, const double* n_H,
+                    const double* species, const double* T,
+                    int64_t n_src, const int64_t* src_cell, const double* src_rate,
+                    rt_state** out);
+/* Deep copy of a state (same mesh, parameters, sources and fields). */
+int rt_state_clone(const rt_state* state, rt_state** out);
+int rt_state_destroy(rt_state* state);
+
+/* Advance n_subcycles subcycles on `hip_stream` (a hipStream_t; NULL = the
+ * null stream).  dt <= 0 selects the CFL step; dt above it is RT_EINVAL.
+ * Each subcycle: sources, chemistry, gradients, fluxes and update.  The call
+ * synchronises the stream once at the end to read the status word; on
+ * RT_ENUMERIC the state is restored to its value at entry. */
+int rt_subcycle(rt_state* state, int n_subcycles, double dt, void* hip_stream);
+
+/* Reverse-mode derivative of L(x_HI after n_subcycles from `initial`) given
+ * dL/dx_HI [nc] of the final state (host or device):
+ *   dL_dlnQ [n_src]  derivative with respect to the log of each source's rate
+ *                    (all bins of a source scaled together),
+ *   dL_dln_nH [nc]   derivative with respect to the log of the initial n_H.
+ * Outputs may be host or device memory.  The forward pass is recomputed from
+ * checkpoints taken every `checkpoint_every` subcycles; `initial` is not
+ * modified.  FP64 states only (RT_ESTATE otherwise). */
+int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int checkpoint_every,
+                        const double* dL_dxHI_final, double* dL_dlnQ, double* dL_dln_nH,
+                        void* hip_stream);
+
+/* Copy a field out (FP64, caller order) to host or device memory, or set one
+ * (RT_FIELD_N, _F, _SPECIES, _T).  Synchronous. */
+int rt_state_get_field(const rt_state* state, int field, double* out, int out_on_device);
+int rt_state_set_field(rt_state* state, int field, const double* in, int in_on_device);
+
+/* Sizes and the subcycle length of a state. */
+int rt_state_info(const rt_state* state, int64_t* n_cells, int32_t* nb, int64_t* n_src,
+                  int32_t* precision, double* dt_cfl);
+
+/* Diagnostics of the last rt_subcycle call. */
+int rt_state_diagnostics(const rt_state* state, rt_diag* out);
+
+/* Per-kernel timing: when enabled, every kernel launch of rt_subcycle is
+ * bracketed by HIP events on the caller's stream; rt_profile_read returns the
+ * number of launches and the summed duration (ms) of kernel `kernel`
+ * (RT_KERNEL_*) since the last reset. */
+int rt_profile_enable(rt_state* state, int enable);
+int rt_profile_reset(rt_state* state);
+int rt_profile_read(const rt_state* state, int kernel, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_H */

@@ -39,7 +39,7 @@ class Diag(C.Structure):
     _fields_ = [("dt", C.c_double), ("photon_sum", C.c_double * MAX_BINS),
                 ("guard_N", C.c_int64), ("guard_F", C.c_int64), ("adm_N", C.c_int64), ("adm_F", C.c_int64),
                 ("flux_caps", C.c_int64), ("substeps", C.c_int64), ("max_substeps", C.c_int64),
-                ("status", C.c_int32)]
+                ("status", C.c_int32), ("loop_seconds", C.c_double)]
 
     def as_dict(self, nb: int) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "photon_sum"}

@@ -15,6 +15,7 @@
 #include "m1rt_oracle.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -688,7 +689,9 @@ int run(const oracle_mesh* m, const oracle_params* p, State<R>& s, const Sources
     std::memset(&local, 0, sizeof(local));
     local.dt = Dt;
     int rc = 0;
+    auto t0 = std::chrono::steady_clock::now();
     for (int it = 0; it < n_sub && rc == 0; ++it) rc = subcycle(g, p, Dt, s, src, &local);
+    local.loop_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     std::vector<double> nv(s.nc);
     for (int b = 0; b < p->nb; ++b) {
         for (int64_t i = 0; i < s.nc; ++i) nv[i] = val(s.N[(size_t)b * s.nc + i]) * g.V[i];

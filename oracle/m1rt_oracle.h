@@ -61,6 +61,7 @@ typedef struct oracle_diag {
     int64_t flux_caps;                    /* faces with theta < 1 */
     int64_t substeps, max_substeps;       /* chemistry attempts (total, max per cell-subcycle) */
     int32_t status;                       /* 0 ok, -6 substep cap hit */
+    double loop_seconds;                  /* wall time of the subcycle loop (steady clock) */
 } oracle_diag;
 
 /* Global CFL step eta * min (3V/4pi)^(1/3) / c~ (eq. timestep, v_c = 0). */

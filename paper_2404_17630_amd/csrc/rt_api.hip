@@ -1,0 +1,935 @@
+// Host side of the C ABI declared in include/rt.h: argument validation, the
+// one-time mesh preparation (minimum-image face offsets, least-squares
+// geometry matrices and their inverses, sliced-ELL face lists), state
+// allocation, the subcycle driver and field conversion.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "rt.h"
+#include "rt_internal.hpp"
+#include "rt_kernels.hpp"
+
+using namespace rtk;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_last_error;
+
+int rt_fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+extern "C" const char* rt_last_error(void) { return g_last_error.c_str(); }
+
+#define RT_HIP(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) {                                                                        \
+            int code_ = (e_ == hipErrorOutOfMemory) ? RT_ENOMEM : RT_EDEVICE;                          \
+            return rt_fail(code_, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+        }                                                                                              \
+    } while (0)
+
+namespace {
+
+// True if p points into device memory (device or managed allocation).  With
+// no usable device the runtime reports an error and p is host memory.
+bool is_device_pointer(const void* p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Copies n elements from a host or device pointer into a host vector.
+template <typename V>
+int fetch(const V* src, size_t n, std::vector<V>& dst, const char* what) {
+    if (n == 0) { dst.clear(); return RT_OK; }
+    if (!src) return rt_fail(RT_EINVAL, "null pointer for %s", what);
+    try {
+        dst.resize(n);
+    } catch (const std::bad_alloc&) {
+        return rt_fail(RT_ENOMEM, "host allocation for %s", what);
+    }
+    if (is_device_pointer(src)) RT_HIP(hipMemcpy(dst.data(), src, n * sizeof(V), hipMemcpyDeviceToHost));
+    else std::memcpy(dst.data(), src, n * sizeof(V));
+    return RT_OK;
+}
+
+bool finite_all(const std::vector<double>& v) {
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr double kBoltzH = 1.380649e-16;
+constexpr double kProtonMassH = 1.67262192369e-24;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Device buffers
+// ---------------------------------------------------------------------------
+
+int DevMem::alloc(size_t nbytes) {
+    release();
+    if (nbytes == 0) return RT_OK;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return rt_fail(e == hipErrorOutOfMemory ? RT_ENOMEM : RT_EDEVICE, "hipMalloc(%zu bytes): %s", nbytes,
+                       hipGetErrorString(e));
+    }
+    ptr = p;
+    bytes = nbytes;
+    return RT_OK;
+}
+
+void DevMem::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+int DevMem::upload(const void* src, size_t nbytes) {
+    int rc = alloc(nbytes);
+    if (rc) return rc;
+    if (nbytes) RT_HIP(hipMemcpy(ptr, src, nbytes, hipMemcpyHostToDevice));
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Mesh
+// ---------------------------------------------------------------------------
+
+extern "C" int rt_params_default(int32_t nb, rt_params* p) {
+    if (!p) return rt_fail(RT_EINVAL, "null params");
+    if (nb < 1 || nb > RT_MAX_BINS) return rt_fail(RT_EINVAL, "nb=%d outside 1..%d", nb, RT_MAX_BINS);
+    std::memset(p, 0, sizeof(*p));
+    p->nb = nb;
+    p->chem_mode = RT_CHEM_H;
+    p->isothermal = 1;
+    p->rate_set = RT_RATES_CASEB_CONST;
+    p->use_limiter = 1;
+    p->chem_max_substeps = 100000;
+    p->c_reduced = 0.01 * 2.99792458e10;
+    p->cfl_eta = 0.3;
+    p->T_iso = 1.0e4;
+    p->Y_He = 0.0;
+    p->alpha_B_const = 2.59e-13;
+    p->gamma = 5.0 / 3.0;
+    p->chem_fmax = 0.1;
+    p->chem_fs = 0.05;
+    p->chem_growth = 2.0;
+    p->chem_xfloor = 1.0e-6;
+    return RT_OK;
+}
+
+static double min_image(double x, double box) {
+    if (box > 0) x -= box * std::floor(x / box + 0.5);
+    return x;
+}
+
+int rt_mesh::build_float_geometry() {
+    if (geo32_ready) return RT_OK;
+    std::vector<float> f(face.size()), mi(minv.size()), v(vol.size()), vc(vcap.size());
+    for (size_t q = 0; q < face.size(); ++q) f[q] = (float)face[q];
+    for (size_t q = 0; q < minv.size(); ++q) mi[q] = (float)minv[q];
+    for (size_t q = 0; q < vol.size(); ++q) v[q] = (float)vol[q];
+    for (size_t q = 0; q < vcap.size(); ++q) vc[q] = (float)vcap[q];
+    int rc;
+    if ((rc = d_face32.upload(f.data(), f.size() * 4))) return rc;
+    if ((rc = d_minv32.upload(mi.data(), mi.size() * 4))) return rc;
+    if ((rc = d_vol32.upload(v.data(), v.size() * 4))) return rc;
+    if ((rc = d_vcap32.upload(vc.data(), vc.size() * 4))) return rc;
+    geo32_ready = true;
+    return RT_OK;
+}
+
+extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const double* centre, int64_t n_faces,
+                              const int64_t* face_cells, const double* area, const double* normal,
+                              const double* face_centre, const double box_in[3], int device, rt_mesh** out) {
+    if (!out) return rt_fail(RT_EINVAL, "null output handle");
+    *out = nullptr;
+    if (n_cells < 1 || n_faces < 1) return rt_fail(RT_EINVAL, "n_cells=%lld n_faces=%lld", (long long)n_cells,
+                                                   (long long)n_faces);
+    if (n_cells >= INT32_MAX / 2 || n_faces >= INT32_MAX / 2)
+        return rt_fail(RT_EINVAL, "mesh too large for 32-bit face indices");
+    if (!box_in) return rt_fail(RT_EINVAL, "null box");
+
+    const int64_t nc = n_cells, nf = n_faces;
+    std::vector<double> V, S, A, Nrm, Xf;
+    std::vector<int64_t> FC;
+    int rc;
+    if ((rc = fetch(volume, nc, V, "volume"))) return rc;
+    if ((rc = fetch(centre, 3 * nc, S, "centre"))) return rc;
+    if ((rc = fetch(face_cells, 2 * nf, FC, "face_cells"))) return rc;
+    if ((rc = fetch(area, nf, A, "area"))) return rc;
+    if ((rc = fetch(normal, 3 * nf, Nrm, "normal"))) return rc;
+    if ((rc = fetch(face_centre, 3 * nf, Xf, "face_centre"))) return rc;
+    double box[3] = {box_in[0], box_in[1], box_in[2]};
+    for (int k = 0; k < 3; ++k)
+        if (!(box[k] >= 0) || !std::isfinite(box[k])) return rt_fail(RT_EINVAL, "box[%d]=%g", k, box[k]);
+    if (!finite_all(S) || !finite_all(Xf)) return rt_fail(RT_EMESH, "non-finite centre or face centre");
+    for (int64_t i = 0; i < nc; ++i)
+        if (!(V[i] > 0) || !std::isfinite(V[i])) return rt_fail(RT_EMESH, "cell %lld: volume %g", (long long)i, V[i]);
+    std::vector<int32_t> deg(nc, 0);
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t L = FC[f], R = FC[nf + f];
+        if (L < 0 || L >= nc || R < 0 || R >= nc)
+            return rt_fail(RT_EMESH, "face %lld: cell index out of range (%lld, %lld)", (long long)f, (long long)L,
+                           (long long)R);
+        if (L == R) return rt_fail(RT_EMESH, "face %lld joins cell %lld to itself", (long long)f, (long long)L);
+        if (!(A[f] > 0) || !std::isfinite(A[f])) return rt_fail(RT_EMESH, "face %lld: area %g", (long long)f, A[f]);
+        double nn = std::sqrt(Nrm[f] * Nrm[f] + Nrm[nf + f] * Nrm[nf + f] + Nrm[2 * nf + f] * Nrm[2 * nf + f]);
+        if (!(std::fabs(nn - 1.0) <= 1e-12)) return rt_fail(RT_EMESH, "face %lld: |n| = %.17g", (long long)f, nn);
+        ++deg[L];
+        ++deg[R];
+    }
+    for (int64_t i = 0; i < nc; ++i)
+        if (deg[i] < 4) return rt_fail(RT_EMESH, "cell %lld has %d faces (< 4)", (long long)i, deg[i]);
+
+    rt_mesh* m = new (std::nothrow) rt_mesh();
+    if (!m) return rt_fail(RT_ENOMEM, "mesh handle");
+    m->device = device;
+    m->nc = nc;
+    m->nf = nf;
+    double vsum = 0;
+    for (double v : V) vsum += v;
+    const double h = std::cbrt(vsum / (double)nc);
+    m->h_ref = h;
+    const double h2 = h * h, h3 = h2 * h;
+
+    // Per-face geometry in units of h: A, n, r_Lf, r_Rf (minimum image).
+    m->face.assign(10 * nf, 0.0);
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t L = FC[f], R = FC[nf + f];
+        m->face[f] = A[f] / h2;
+        for (int k = 0; k < 3; ++k) {
+            m->face[(1 + k) * nf + f] = Nrm[k * nf + f];
+            m->face[(4 + k) * nf + f] = min_image(Xf[k * nf + f] - S[k * nc + L], box[k]) / h;
+            m->face[(7 + k) * nf + f] = min_image(Xf[k * nf + f] - S[k * nc + R], box[k]) / h;
+        }
+    }
+    // Face sides per cell in face-index order (counting sort keeps the order).
+    std::vector<int64_t> off(nc + 1, 0);
+    for (int64_t i = 0; i < nc; ++i) off[i + 1] = off[i] + deg[i];
+    std::vector<int32_t> side_face(2 * nf), side_nbr(2 * nf);
+    std::vector<uint8_t> side_isL(2 * nf);
+    {
+        std::vector<int64_t> fill(off.begin(), off.end() - 1);
+        for (int64_t f = 0; f < nf; ++f) {
+            int64_t L = FC[f], R = FC[nf + f];
+            int64_t eL = fill[L]++, eR = fill[R]++;
+            side_face[eL] = (int32_t)f; side_nbr[eL] = (int32_t)R; side_isL[eL] = 1;
+            side_face[eR] = (int32_t)f; side_nbr[eR] = (int32_t)L; side_isL[eR] = 0;
+        }
+    }
+    // Geometry matrix M_i = sum A u u^T (u = unit separation through the face),
+    // its inverse by the adjugate, and a Frobenius condition-number check.
+    m->minv.assign(6 * nc, 0.0);
+    m->vol.resize(nc);
+    m->vcap.resize(nc);
+    m->vphys = V;
+    for (int64_t i = 0; i < nc; ++i) {
+        double M[6] = {0, 0, 0, 0, 0, 0};   // xx yy zz xy xz yz
+        for (int64_t e = off[i]; e < off[i + 1]; ++e) {
+            const int64_t f = side_face[e];
+            const bool isL = side_isL[e];
+            double d[3];
+            for (int k = 0; k < 3; ++k) {
+                const double rl = m->face[(4 + k) * nf + f], rr = m->face[(7 + k) * nf + f];
+                d[k] = isL ? rl - rr : rr - rl;
+            }
+            const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!(dd > 0)) {
+                delete m;
+                return rt_fail(RT_EMESH, "cell %lld: coincident neighbour centre through face %lld", (long long)i,
+                               (long long)f);
+            }
+            const double Af = m->face[f] / dd;
+            M[0] += Af * d[0] * d[0]; M[1] += Af * d[1] * d[1]; M[2] += Af * d[2] * d[2];
+            M[3] += Af * d[0] * d[1]; M[4] += Af * d[0] * d[2]; M[5] += Af * d[1] * d[2];
+        }
+        const double a = M[0], b = M[1], c = M[2], dxy = M[3], exz = M[4], fyz = M[5];
+        const double det = a * (b * c - fyz * fyz) - dxy * (dxy * c - fyz * exz) + exz * (dxy * fyz - b * exz);
+        double inv[6];
+        inv[0] = (b * c - fyz * fyz) / det;
+        inv[1] = (a * c - exz * exz) / det;
+        inv[2] = (a * b - dxy * dxy) / det;
+        inv[3] = (exz * fyz - dxy * c) / det;
+        inv[4] = (dxy * fyz - b * exz) / det;
+        inv[5] = (dxy * exz - a * fyz) / det;
+        double nM = a * a + b * b + c * c + 2 * (dxy * dxy + exz * exz + fyz * fyz);
+        double nI = inv[0] * inv[0] + inv[1] * inv[1] + inv[2] * inv[2] +
+                    2 * (inv[3] * inv[3] + inv[4] * inv[4] + inv[5] * inv[5]);
+        double cond = std::sqrt(nM * nI);
+        if (!(det != 0) || !std::isfinite(cond) || cond > 1e12) {
+            delete m;
+            return rt_fail(RT_EMESH, "cell %lld: geometry matrix condition number %g", (long long)i, cond);
+        }
+        for (int q = 0; q < 6; ++q) m->minv[q * nc + i] = inv[q];
+        m->vol[i] = V[i] / h3;
+        m->vcap[i] = m->vol[i] / (double)deg[i];
+    }
+    // Sliced ELL with 64-cell slices.
+    const int64_t ns = (nc + kSlice - 1) / kSlice;
+    m->sdeg.assign(ns, 0);
+    m->sptr.assign(ns + 1, 0);
+    for (int64_t s = 0; s < ns; ++s) {
+        int32_t mx = 0;
+        for (int64_t i = s * kSlice; i < std::min<int64_t>(nc, (s + 1) * kSlice); ++i) mx = std::max(mx, deg[i]);
+        m->sdeg[s] = mx;
+        m->sptr[s + 1] = m->sptr[s] + mx * kSlice;
+        if ((int64_t)m->sptr[s + 1] > INT32_MAX / 2) {
+            delete m;
+            return rt_fail(RT_EINVAL, "too many face sides");
+        }
+    }
+    const int64_t ne = m->sptr[ns];
+    m->nbr.assign(ne, -1);
+    m->fsf.assign(ne, 0);
+    for (int64_t i = 0; i < nc; ++i) {
+        const int64_t s = i / kSlice, lane = i % kSlice;
+        for (int64_t k = 0; k < deg[i]; ++k) {
+            const int64_t e = m->sptr[s] + k * kSlice + lane;
+            const int64_t src = off[i] + k;
+            m->nbr[e] = side_nbr[src];
+            m->fsf[e] = side_isL[src] ? side_face[src] : ~side_face[src];
+        }
+    }
+    m->max_deg = *std::max_element(deg.begin(), deg.end());
+    m->deg = std::move(deg);
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) {
+        (void)hipGetLastError();
+        ndev = 0;
+    }
+    if (device < 0 || device >= ndev) {
+        delete m;
+        return rt_fail(RT_EDEVICE, "device %d of %d", device, ndev);
+    }
+    DeviceGuard dg(device);
+
+    if ((rc = m->d_face64.upload(m->face.data(), m->face.size() * 8)) ||
+        (rc = m->d_minv64.upload(m->minv.data(), m->minv.size() * 8)) ||
+        (rc = m->d_vol64.upload(m->vol.data(), m->vol.size() * 8)) ||
+        (rc = m->d_vcap64.upload(m->vcap.data(), m->vcap.size() * 8)) ||
+        (rc = m->d_vphys.upload(m->vphys.data(), m->vphys.size() * 8)) ||
+        (rc = m->d_nbr.upload(m->nbr.data(), m->nbr.size() * 4)) ||
+        (rc = m->d_fsf.upload(m->fsf.data(), m->fsf.size() * 4)) ||
+        (rc = m->d_sptr.upload(m->sptr.data(), m->sptr.size() * 4)) ||
+        (rc = m->d_sdeg.upload(m->sdeg.data(), m->sdeg.size() * 4))) {
+        delete m;
+        return rc;
+    }
+    // CFL length min_i (3V/4pi)^(1/3) by the device min-reduction.
+    {
+        DevMem part;
+        const int64_t np = cfl_partials(nc);
+        if ((rc = part.alloc(np * 8))) { delete m; return rc; }
+        launch_min_cfl_length((const double*)m->d_vphys.ptr, nc, (double*)part.ptr, nullptr);
+        std::vector<double> hp(np);
+        hipError_t e = hipMemcpy(hp.data(), part.ptr, np * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) { delete m; return rt_fail(RT_EDEVICE, "CFL reduction: %s", hipGetErrorString(e)); }
+        m->dx_min = *std::min_element(hp.begin(), hp.end());
+    }
+    m->refs.store(1);
+    *out = m;
+    return RT_OK;
+}
+
+void rt_mesh_release(rt_mesh* m) {
+    if (m && m->refs.fetch_sub(1) == 1) {
+        DeviceGuard dg(m->device);
+        delete m;
+    }
+}
+
+extern "C" int rt_mesh_destroy(rt_mesh* m) {
+    if (!m) return rt_fail(RT_EINVAL, "null mesh");
+    rt_mesh_release(m);
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// State
+// ---------------------------------------------------------------------------
+
+static int check_params(const rt_params* p) {
+    if (!p) return rt_fail(RT_EINVAL, "null params");
+    if (p->nb < 1 || p->nb > RT_MAX_BINS) return rt_fail(RT_EINVAL, "nb=%d", p->nb);
+    if (p->chem_mode < RT_CHEM_NONE || p->chem_mode > RT_CHEM_HHE) return rt_fail(RT_EINVAL, "chem_mode=%d", p->chem_mode);
+    if (p->rate_set != RT_RATES_CASEB_CONST && p->rate_set != RT_RATES_HG97)
+        return rt_fail(RT_EINVAL, "rate_set=%d", p->rate_set);
+    if (p->rate_set == RT_RATES_CASEB_CONST && p->chem_mode == RT_CHEM_HHE)
+        return rt_fail(RT_EINVAL, "constant case-B rates are hydrogen-only");
+    if (p->rate_set == RT_RATES_CASEB_CONST && p->chem_mode != RT_CHEM_NONE && !p->isothermal)
+        return rt_fail(RT_EINVAL, "constant case-B rates need an isothermal run");
+    if (!(p->c_reduced > 0) || !std::isfinite(p->c_reduced)) return rt_fail(RT_EINVAL, "c_reduced=%g", p->c_reduced);
+    if (!(p->cfl_eta > 0 && p->cfl_eta <= 1)) return rt_fail(RT_EINVAL, "cfl_eta=%g", p->cfl_eta);
+    if (p->isothermal && !(p->T_iso > 0)) return rt_fail(RT_EINVAL, "T_iso=%g", p->T_iso);
+    if (!(p->Y_He >= 0 && p->Y_He < 1)) return rt_fail(RT_EINVAL, "Y_He=%g", p->Y_He);
+    if (!(p->gamma > 1)) return rt_fail(RT_EINVAL, "gamma=%g", p->gamma);
+    if (!(p->chem_fmax > 0) || !(p->chem_fs > 0) || !(p->chem_growth >= 1) || !(p->chem_xfloor > 0) ||
+        p->chem_max_substeps < 1)
+        return rt_fail(RT_EINVAL, "chemistry controller parameters");
+    if (p->rate_set == RT_RATES_CASEB_CONST && !(p->alpha_B_const >= 0)) return rt_fail(RT_EINVAL, "alpha_B_const");
+    for (int b = 0; b < p->nb; ++b)
+        for (int s = 0; s < 3; ++s)
+            if (!(p->sigma[b][s] >= 0) || !std::isfinite(p->sigma[b][s]) || !(p->e_heat[b][s] >= 0) ||
+                !std::isfinite(p->e_heat[b][s]))
+                return rt_fail(RT_EINVAL, "sigma/e_heat[%d][%d]", b, s);
+    return RT_OK;
+}
+
+static ChemParams chem_params_of(const rt_params& p) {
+    ChemParams c;
+    std::memset(&c, 0, sizeof(c));
+    c.nb = p.nb;
+    c.chem_mode = p.chem_mode;
+    c.isothermal = p.isothermal;
+    c.rate_set = p.rate_set;
+    c.max_sub = p.chem_max_substeps;
+    c.c = p.c_reduced;
+    c.T_iso = p.T_iso;
+    c.yhe = p.chem_mode == RT_CHEM_HHE ? p.Y_He / (4.0 * (1.0 - p.Y_He)) : 0.0;
+    c.alpha_B = p.alpha_B_const;
+    c.gm1 = p.gamma - 1.0;
+    c.fmax = p.chem_fmax;
+    c.fs = p.chem_fs;
+    c.growth = p.chem_growth;
+    c.xfloor = p.chem_xfloor;
+    for (int b = 0; b < p.nb; ++b)
+        for (int s = 0; s < 3; ++s) {
+            c.sigma[b][s] = p.sigma[b][s];
+            c.eheat[b][s] = p.e_heat[b][s];
+        }
+    return c;
+}
+
+static double pow2_at_least(double m) {
+    if (!(m > 0) || !std::isfinite(m)) return 1.0;
+    int e;
+    double fr = std::frexp(m, &e);   // m = fr * 2^e, fr in [0.5, 1)
+    (void)fr;
+    return std::ldexp(1.0, e);
+}
+
+size_t rt_state::tbytes() const { return precision == RT_MIXED ? 4 : 8; }
+
+int rt_state::alloc_buffers() {
+    const size_t t = tbytes();
+    int rc;
+    if ((rc = U[0].alloc((size_t)nb * 4 * nc * t)) || (rc = U[1].alloc((size_t)nb * 4 * nc * t)) ||
+        (rc = G.alloc((size_t)nb * 12 * nc * t)) || (rc = X.alloc(5 * nc * 8)) || (rc = Ue.alloc(nc * 8)) ||
+        (rc = nH.alloc(nc * 8)))
+        return rc;
+    n_fblk = transport_blocks(nc, nb);
+    n_cblk = chem_blocks(nc);
+    if ((rc = part_nv.alloc(n_fblk * 8)) || (rc = part_cnt.alloc(5 * n_fblk * 8)) ||
+        (rc = part_fst.alloc(n_fblk * 4)) || (rc = chem_sum.alloc(n_cblk * 8)) || (rc = chem_max.alloc(n_cblk * 8)) ||
+        (rc = chem_st.alloc(n_cblk * 4)) || (rc = d_diag.alloc(sizeof(DiagDev))))
+        return rc;
+    RT_HIP(hipHostMalloc((void**)&h_diag, sizeof(DiagDev), hipHostMallocDefault));
+    return RT_OK;
+}
+
+int rt_state::upload_scales() {
+    std::vector<double> s(nb), inv(nb), nvs(nb);
+    for (int b = 0; b < nb; ++b) {
+        s[b] = scale[b];
+        inv[b] = 1.0 / scale[b];
+        nvs[b] = scale[b] * mesh->h_ref * mesh->h_ref * mesh->h_ref;
+    }
+    int rc;
+    if ((rc = d_scale.upload(s.data(), nb * 8)) || (rc = d_inv_scale.upload(inv.data(), nb * 8)) ||
+        (rc = d_nv_scale.upload(nvs.data(), nb * 8)))
+        return rc;
+    return RT_OK;
+}
+
+int rt_state::upload_sources() {
+    // Stable sort of the sources by cell; each source cell adds its sources
+    // in list order.
+    std::vector<int64_t> order(n_src);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return src_cell[a] < src_cell[b]; });
+    std::vector<int32_t> cells, ptr;
+    std::vector<double> rate((size_t)nb * n_src), vp(n_src);
+    for (int64_t q = 0; q < n_src; ++q) {
+        const int64_t k = order[q];
+        if (cells.empty() || cells.back() != (int32_t)src_cell[k]) {
+            cells.push_back((int32_t)src_cell[k]);
+            ptr.push_back((int32_t)q);
+        }
+        for (int b = 0; b < nb; ++b) rate[(size_t)b * n_src + q] = src_rate[(size_t)b * n_src + k];
+        vp[q] = mesh->vphys[src_cell[k]];
+    }
+    ptr.push_back((int32_t)n_src);
+    n_src_cells = (int32_t)cells.size();
+    int rc;
+    if ((rc = d_src_cell.upload(cells.data(), cells.size() * 4)) || (rc = d_src_ptr.upload(ptr.data(), ptr.size() * 4)) ||
+        (rc = d_src_rate.upload(rate.data(), rate.size() * 8)) || (rc = d_src_vphys.upload(vp.data(), vp.size() * 8)))
+        return rc;
+    return RT_OK;
+}
+
+extern "C" int rt_state_create(const rt_mesh* mesh_c, const rt_params* params, int precision, const double* N,
+                               const double* F, const double* n_H, const double* species, const double* T,
+                               int64_t n_src, const int64_t* src_cell, const double* src_rate, rt_state** out) {
+    if (!out) return rt_fail(RT_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!mesh_c) return rt_fail(RT_EINVAL, "null mesh");
+    rt_mesh* mesh = const_cast<rt_mesh*>(mesh_c);
+    int rc;
+    if ((rc = check_params(params))) return rc;
+    if (precision != RT_FP64 && precision != RT_MIXED) return rt_fail(RT_EINVAL, "precision=%d", precision);
+    if (n_src < 0) return rt_fail(RT_EINVAL, "n_src=%lld", (long long)n_src);
+    DeviceGuard dg(mesh->device);
+    const int64_t nc = mesh->nc;
+    const int nb = params->nb;
+    std::vector<double> hN, hF, hnH, hX, hT, hR;
+    std::vector<int64_t> hC;
+    if ((rc = fetch(N, (size_t)nb * nc, hN, "N")) || (rc = fetch(F, (size_t)nb * 3 * nc, hF, "F")) ||
+        (rc = fetch(n_H, nc, hnH, "n_H")) || (rc = fetch(species, 5 * nc, hX, "species")) ||
+        (rc = fetch(T, nc, hT, "T")) || (rc = fetch(src_cell, n_src, hC, "src_cell")) ||
+        (rc = fetch(src_rate, (size_t)nb * n_src, hR, "src_rate")))
+        return rc;
+    for (int64_t q = 0; q < (int64_t)hN.size(); ++q)
+        if (!(hN[q] >= 0) || !std::isfinite(hN[q])) return rt_fail(RT_EINVAL, "N[%lld]=%g", (long long)q, hN[q]);
+    if (!finite_all(hF)) return rt_fail(RT_EINVAL, "non-finite F");
+    for (int64_t i = 0; i < nc; ++i) {
+        if (!(hnH[i] > 0) || !std::isfinite(hnH[i])) return rt_fail(RT_EINVAL, "n_H[%lld]=%g", (long long)i, hnH[i]);
+        if (!(hT[i] > 0) || !std::isfinite(hT[i])) return rt_fail(RT_EINVAL, "T[%lld]=%g", (long long)i, hT[i]);
+        for (int s = 0; s < 5; ++s) {
+            double x = hX[s * nc + i];
+            if (!(x >= 0 && x <= 1)) return rt_fail(RT_EINVAL, "species[%d][%lld]=%g", s, (long long)i, x);
+        }
+    }
+    for (int64_t k = 0; k < n_src; ++k) {
+        if (hC[k] < 0 || hC[k] >= nc) return rt_fail(RT_EINVAL, "src_cell[%lld]=%lld", (long long)k, (long long)hC[k]);
+        for (int b = 0; b < nb; ++b) {
+            double r = hR[(size_t)b * n_src + k];
+            if (!(r >= 0) || !std::isfinite(r)) return rt_fail(RT_EINVAL, "src_rate[%d][%lld]=%g", b, (long long)k, r);
+        }
+    }
+    if (precision == RT_MIXED && (rc = mesh->build_float_geometry())) return rc;
+
+    rt_state* s = new (std::nothrow) rt_state();
+    if (!s) return rt_fail(RT_ENOMEM, "state handle");
+    mesh->refs.fetch_add(1);
+    s->mesh = mesh;
+    s->params = *params;
+    s->cp = chem_params_of(*params);
+    s->precision = precision;
+    s->nb = nb;
+    s->nc = nc;
+    s->dt_cfl = params->cfl_eta * mesh->dx_min / params->c_reduced;
+    s->n_src = n_src;
+    s->src_cell = hC;
+    s->src_rate = hR;
+    // Per-bin storage scale (power of two: scaling is exact).
+    for (int b = 0; b < RT_MAX_BINS; ++b) s->scale[b] = 1.0;
+    if (precision == RT_MIXED) {
+        for (int b = 0; b < nb; ++b) {
+            double mx = 0;
+            for (int64_t i = 0; i < nc; ++i) {
+                mx = std::max(mx, hN[(size_t)b * nc + i]);
+                for (int k = 0; k < 3; ++k) mx = std::max(mx, std::fabs(hF[((size_t)b * 3 + k) * nc + i]) / params->c_reduced);
+            }
+            for (int64_t k = 0; k < n_src; ++k)
+                mx = std::max(mx, hR[(size_t)b * n_src + k] * s->dt_cfl / mesh->vphys[hC[k]]);
+            s->scale[b] = pow2_at_least(mx);
+        }
+    }
+    if ((rc = s->alloc_buffers()) || (rc = s->upload_scales()) || (rc = s->upload_sources())) {
+        rt_state_destroy(s);
+        return rc;
+    }
+    // Fields in the internal layout U[b][4][nc] = (N, F/c~) / scale.
+    {
+        std::vector<double> U((size_t)nb * 4 * nc);
+        for (int b = 0; b < nb; ++b) {
+            const double inv = 1.0 / s->scale[b];
+            for (int64_t i = 0; i < nc; ++i) {
+                U[((size_t)b * 4) * nc + i] = hN[(size_t)b * nc + i] * inv;
+                for (int k = 0; k < 3; ++k)
+                    U[((size_t)b * 4 + 1 + k) * nc + i] = hF[((size_t)b * 3 + k) * nc + i] / params->c_reduced * inv;
+            }
+        }
+        hipError_t e;
+        if (precision == RT_MIXED) {
+            std::vector<float> Uf(U.size());
+            for (size_t q = 0; q < U.size(); ++q) Uf[q] = (float)U[q];
+            e = hipMemcpy(s->U[0].ptr, Uf.data(), Uf.size() * 4, hipMemcpyHostToDevice);
+        } else {
+            e = hipMemcpy(s->U[0].ptr, U.data(), U.size() * 8, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) { rt_state_destroy(s); return rt_fail(RT_EDEVICE, "upload U: %s", hipGetErrorString(e)); }
+        // Thermal energy u = k_B T / ((gamma - 1) mu m_p).
+        std::vector<double> ue(nc);
+        const double yhe = s->cp.yhe;
+        for (int64_t i = 0; i < nc; ++i) {
+            const double xe = hX[1 * nc + i] + yhe * (hX[3 * nc + i] + 2.0 * hX[4 * nc + i]);
+            const double mu = (1.0 + 4.0 * yhe) / (1.0 + yhe + xe);
+            ue[i] = kBoltzH * hT[i] / ((params->gamma - 1.0) * mu * kProtonMassH);
+        }
+        if ((e = hipMemcpy(s->X.ptr, hX.data(), hX.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(s->Ue.ptr, ue.data(), nc * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(s->nH.ptr, hnH.data(), nc * 8, hipMemcpyHostToDevice)) != hipSuccess) {
+            rt_state_destroy(s);
+            return rt_fail(RT_EDEVICE, "upload state: %s", hipGetErrorString(e));
+        }
+    }
+    s->cur = 0;
+    std::memset(&s->diag, 0, sizeof(s->diag));
+    s->diag.dt = s->dt_cfl;
+    for (int b = 0; b < RT_MAX_BINS; ++b) s->diag.scale[b] = s->scale[b];
+    *out = s;
+    return RT_OK;
+}
+
+rt_state::~rt_state() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (h_diag) (void)hipHostFree(h_diag);
+}
+
+extern "C" int rt_state_destroy(rt_state* s) {
+    if (!s) return rt_fail(RT_EINVAL, "null state");
+    rt_mesh* m = s->mesh;
+    {
+        DeviceGuard dg(m ? m->device : 0);
+        delete s;
+    }
+    rt_mesh_release(m);
+    return RT_OK;
+}
+
+static int copy_dev(DevMem& dst, const DevMem& src) {
+    int rc = dst.alloc(src.bytes);
+    if (rc) return rc;
+    if (src.bytes) RT_HIP(hipMemcpy(dst.ptr, src.ptr, src.bytes, hipMemcpyDeviceToDevice));
+    return RT_OK;
+}
+
+extern "C" int rt_state_clone(const rt_state* src, rt_state** out) {
+    if (!src || !out) return rt_fail(RT_EINVAL, "null argument");
+    *out = nullptr;
+    DeviceGuard dg(src->mesh->device);
+    rt_state* s = new (std::nothrow) rt_state();
+    if (!s) return rt_fail(RT_ENOMEM, "state handle");
+    src->mesh->refs.fetch_add(1);
+    s->mesh = src->mesh;
+    s->params = src->params;
+    s->cp = src->cp;
+    s->precision = src->precision;
+    s->nb = src->nb;
+    s->nc = src->nc;
+    s->dt_cfl = src->dt_cfl;
+    s->n_src = src->n_src;
+    s->src_cell = src->src_cell;
+    s->src_rate = src->src_rate;
+    std::memcpy(s->scale, src->scale, sizeof(s->scale));
+    int rc;
+    if ((rc = s->alloc_buffers()) || (rc = s->upload_scales()) || (rc = s->upload_sources()) ||
+        (rc = copy_dev(s->U[0], src->U[src->cur])) || (rc = copy_dev(s->X, src->X)) ||
+        (rc = copy_dev(s->Ue, src->Ue)) || (rc = copy_dev(s->nH, src->nH))) {
+        rt_state_destroy(s);
+        return rc;
+    }
+    s->cur = 0;
+    s->diag = src->diag;
+    *out = s;
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Subcycle driver
+// ---------------------------------------------------------------------------
+
+void rt_state::prof_begin(int kernel, hipStream_t st) {
+    if (!prof) return;
+    if (ev_used + 2 > ev_pool.size()) {
+        for (int q = 0; q < 64; ++q) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            ev_pool.push_back(e);
+        }
+    }
+    prof_open = (int)ev_used;
+    prof_kernel = kernel;
+    (void)hipEventRecord(ev_pool[ev_used++], st);
+}
+
+void rt_state::prof_end(hipStream_t st) {
+    if (!prof || prof_open < 0) return;
+    (void)hipEventRecord(ev_pool[ev_used++], st);
+    ev_marks.push_back({prof_kernel, prof_open});
+    prof_open = -1;
+}
+
+int rt_state::prof_collect() {
+    if (!prof) return RT_OK;
+    for (const auto& mk : ev_marks) {
+        float ms = 0;
+        RT_HIP(hipEventElapsedTime(&ms, ev_pool[mk.second], ev_pool[mk.second + 1]));
+        launches[mk.first] += 1;
+        total_ms[mk.first] += ms;
+    }
+    ev_marks.clear();
+    ev_used = 0;
+    return RT_OK;
+}
+
+template <typename T>
+static void run_subcycles(rt_state* s, int n, double dt, hipStream_t st) {
+    rt_mesh* m = s->mesh;
+    const int64_t nc = s->nc;
+    const int nb = s->nb;
+    GeomView<T> geo;
+    if (sizeof(T) == 8) {
+        geo.face = (const T*)m->d_face64.ptr; geo.minv = (const T*)m->d_minv64.ptr;
+        geo.vol = (const T*)m->d_vol64.ptr; geo.vcap = (const T*)m->d_vcap64.ptr;
+    } else {
+        geo.face = (const T*)m->d_face32.ptr; geo.minv = (const T*)m->d_minv32.ptr;
+        geo.vol = (const T*)m->d_vol32.ptr; geo.vcap = (const T*)m->d_vcap32.ptr;
+    }
+    geo.nf = m->nf;
+    SellView sell{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_sptr.ptr,
+                  (const int32_t*)m->d_sdeg.ptr};
+    const double cdt = s->params.c_reduced * dt / m->h_ref;
+    for (int it = 0; it < n; ++it) {
+        T* U = (T*)s->U[s->cur].ptr;
+        T* Un = (T*)s->U[s->cur ^ 1].ptr;
+        s->prof_begin(RT_KERNEL_SOURCES, st);
+        launch_sources<T>(U, nc, nb, s->n_src_cells, (const int32_t*)s->d_src_cell.ptr, (const int32_t*)s->d_src_ptr.ptr,
+                          (const double*)s->d_src_rate.ptr, s->n_src, (const double*)s->d_src_vphys.ptr,
+                          (const double*)s->d_inv_scale.ptr, (const double*)s->d_scale.ptr, dt, st);
+        s->prof_end(st);
+        if (s->params.chem_mode != RT_CHEM_NONE) {
+            s->prof_begin(RT_KERNEL_CHEM, st);
+            launch_chem<T>(U, (double*)s->X.ptr, (double*)s->Ue.ptr, (const double*)s->nH.ptr, nc, s->cp, dt,
+                           (const double*)s->d_scale.ptr, (const double*)s->d_inv_scale.ptr, (int64_t*)s->chem_sum.ptr,
+                           (int64_t*)s->chem_max.ptr, (int32_t*)s->chem_st.ptr, st);
+            s->prof_end(st);
+        }
+        s->prof_begin(RT_KERNEL_GRADIENT, st);
+        launch_gradient<T>(U, (T*)s->G.ptr, nc, nb, geo, sell, s->params.use_limiter, st);
+        s->prof_end(st);
+        s->prof_begin(RT_KERNEL_FLUX, st);
+        launch_flux<T>(U, (const T*)s->G.ptr, Un, nc, nb, geo, sell, cdt, (double*)s->part_nv.ptr,
+                       (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
+        s->prof_end(st);
+        s->cur ^= 1;
+    }
+}
+
+extern "C" int rt_subcycle(rt_state* s, int n, double dt, void* hip_stream) {
+    if (!s) return rt_fail(RT_EINVAL, "null state");
+    if (n < 0) return rt_fail(RT_EINVAL, "n_subcycles=%d", n);
+    if (!(dt <= 0) && !(dt <= s->dt_cfl)) return rt_fail(RT_EINVAL, "dt=%g above the CFL step %g", dt, s->dt_cfl);
+    if (!std::isfinite(dt)) return rt_fail(RT_EINVAL, "dt=%g", dt);
+    const double step = dt <= 0 ? s->dt_cfl : dt;
+    DeviceGuard dg(s->mesh->device);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t t = s->tbytes();
+    const size_t ubytes = (size_t)s->nb * 4 * s->nc * t;
+    // Entry copy for roll-back on error.
+    int rc;
+    if ((!s->bU.ptr && (rc = s->bU.alloc(ubytes))) || (!s->bX.ptr && (rc = s->bX.alloc(5 * s->nc * 8))) ||
+        (!s->bUe.ptr && (rc = s->bUe.alloc(s->nc * 8))))
+        return rc;
+    const int cur0 = s->cur;
+    RT_HIP(hipMemcpyAsync(s->bU.ptr, s->U[cur0].ptr, ubytes, hipMemcpyDeviceToDevice, st));
+    RT_HIP(hipMemcpyAsync(s->bX.ptr, s->X.ptr, 5 * s->nc * 8, hipMemcpyDeviceToDevice, st));
+    RT_HIP(hipMemcpyAsync(s->bUe.ptr, s->Ue.ptr, s->nc * 8, hipMemcpyDeviceToDevice, st));
+    fill_words(s->part_cnt.ptr, 5 * s->n_fblk * 2, 0, st);
+    fill_words(s->part_fst.ptr, s->n_fblk, 0, st);
+    fill_words(s->part_nv.ptr, s->n_fblk * 2, 0, st);
+    fill_words(s->chem_sum.ptr, s->n_cblk * 2, 0, st);
+    fill_words(s->chem_max.ptr, s->n_cblk * 2, 0, st);
+    fill_words(s->chem_st.ptr, s->n_cblk, 0, st);
+    if (s->precision == RT_MIXED) run_subcycles<float>(s, n, step, st);
+    else run_subcycles<double>(s, n, step, st);
+    s->prof_begin(RT_KERNEL_REDUCE, st);
+    launch_reduce((const double*)s->part_nv.ptr, (const int64_t*)s->part_cnt.ptr, (const int32_t*)s->part_fst.ptr,
+                  s->n_fblk, s->nb, (const int64_t*)s->chem_sum.ptr, (const int64_t*)s->chem_max.ptr,
+                  (const int32_t*)s->chem_st.ptr, s->n_cblk, (const double*)s->d_nv_scale.ptr, (DiagDev*)s->d_diag.ptr,
+                  st);
+    s->prof_end(st);
+    RT_HIP(hipGetLastError());
+    RT_HIP(hipMemcpyAsync(s->h_diag, s->d_diag.ptr, sizeof(DiagDev), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    if ((rc = s->prof_collect())) return rc;
+    const DiagDev& d = *s->h_diag;
+    rt_diag& o = s->diag;
+    o.dt = step;
+    for (int b = 0; b < RT_MAX_BINS; ++b) {
+        o.photon_sum[b] = b < s->nb ? d.photon_sum[b] : 0.0;
+        o.scale[b] = s->scale[b];
+    }
+    o.adm_N = d.counters[0]; o.adm_F = d.counters[1]; o.flux_caps = d.counters[2];
+    o.guard_N = d.counters[3]; o.guard_F = d.counters[4];
+    o.substeps = d.substeps; o.max_substeps = d.max_substeps;
+    o.status = d.status;
+    o.n_subcycles = n;
+    if (n > 0 && d.status != 0) {
+        // Roll back to the entry state.
+        s->cur = cur0;
+        RT_HIP(hipMemcpyAsync(s->U[cur0].ptr, s->bU.ptr, ubytes, hipMemcpyDeviceToDevice, st));
+        RT_HIP(hipMemcpyAsync(s->X.ptr, s->bX.ptr, 5 * s->nc * 8, hipMemcpyDeviceToDevice, st));
+        RT_HIP(hipMemcpyAsync(s->Ue.ptr, s->bUe.ptr, s->nc * 8, hipMemcpyDeviceToDevice, st));
+        RT_HIP(hipStreamSynchronize(st));
+        return rt_fail(RT_ENUMERIC, "subcycle status 0x%x (%s%s); state restored", d.status,
+                       (d.status & 1) ? "non-finite value " : "", (d.status & 2) ? "chemistry substep cap" : "");
+    }
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Fields, info, diagnostics, profiling
+// ---------------------------------------------------------------------------
+
+static size_t field_count(const rt_state* s, int field) {
+    switch (field) {
+        case RT_FIELD_N: return (size_t)s->nb * s->nc;
+        case RT_FIELD_F: return (size_t)s->nb * 3 * s->nc;
+        case RT_FIELD_NH: return s->nc;
+        case RT_FIELD_SPECIES: return 5 * s->nc;
+        case RT_FIELD_T: return s->nc;
+        default: return 0;
+    }
+}
+
+extern "C" int rt_state_get_field(const rt_state* s, int field, double* out, int out_on_device) {
+    (void)out_on_device;
+    if (!s || !out) return rt_fail(RT_EINVAL, "null argument");
+    const size_t n = field_count(s, field);
+    if (!n) return rt_fail(RT_EINVAL, "field=%d", field);
+    DeviceGuard dg(s->mesh->device);
+    if (field == RT_FIELD_NH) { RT_HIP(hipMemcpy(out, s->nH.ptr, n * 8, hipMemcpyDefault)); return RT_OK; }
+    if (field == RT_FIELD_SPECIES) { RT_HIP(hipMemcpy(out, s->X.ptr, n * 8, hipMemcpyDefault)); return RT_OK; }
+    DevMem tmp;
+    int rc = tmp.alloc(n * 8);
+    if (rc) return rc;
+    if (s->precision == RT_MIXED)
+        launch_get_fields<float>((const float*)s->U[s->cur].ptr, (const double*)s->X.ptr, (const double*)s->Ue.ptr,
+                                 s->nc, s->nb, field, (const double*)s->d_scale.ptr, s->params.c_reduced, s->cp,
+                                 (double*)tmp.ptr, nullptr);
+    else
+        launch_get_fields<double>((const double*)s->U[s->cur].ptr, (const double*)s->X.ptr, (const double*)s->Ue.ptr,
+                                  s->nc, s->nb, field, (const double*)s->d_scale.ptr, s->params.c_reduced, s->cp,
+                                  (double*)tmp.ptr, nullptr);
+    RT_HIP(hipGetLastError());
+    RT_HIP(hipMemcpy(out, tmp.ptr, n * 8, hipMemcpyDefault));
+    return RT_OK;
+}
+
+extern "C" int rt_state_set_field(rt_state* s, int field, const double* in, int in_on_device) {
+    (void)in_on_device;
+    if (!s || !in) return rt_fail(RT_EINVAL, "null argument");
+    if (field == RT_FIELD_NH) return rt_fail(RT_EINVAL, "n_H is fixed at create time");
+    const size_t n = field_count(s, field);
+    if (!n) return rt_fail(RT_EINVAL, "field=%d", field);
+    DeviceGuard dg(s->mesh->device);
+    std::vector<double> h;
+    int rc = fetch(in, n, h, "field");
+    if (rc) return rc;
+    if (!finite_all(h)) return rt_fail(RT_EINVAL, "non-finite field values");
+    if (field == RT_FIELD_SPECIES) {
+        for (double x : h)
+            if (!(x >= 0 && x <= 1)) return rt_fail(RT_EINVAL, "species outside [0, 1]");
+        RT_HIP(hipMemcpy(s->X.ptr, h.data(), n * 8, hipMemcpyHostToDevice));
+        return RT_OK;
+    }
+    if (field == RT_FIELD_N)
+        for (double x : h)
+            if (!(x >= 0)) return rt_fail(RT_EINVAL, "negative N");
+    if (field == RT_FIELD_T)
+        for (double x : h)
+            if (!(x > 0)) return rt_fail(RT_EINVAL, "non-positive T");
+    DevMem tmp;
+    if ((rc = tmp.upload(h.data(), n * 8))) return rc;
+    if (s->precision == RT_MIXED)
+        launch_set_fields<float>((float*)s->U[s->cur].ptr, (const double*)s->X.ptr, (double*)s->Ue.ptr, s->nc, s->nb,
+                                 field, (const double*)s->d_inv_scale.ptr, s->params.c_reduced, s->cp,
+                                 (const double*)tmp.ptr, nullptr);
+    else
+        launch_set_fields<double>((double*)s->U[s->cur].ptr, (const double*)s->X.ptr, (double*)s->Ue.ptr, s->nc, s->nb,
+                                  field, (const double*)s->d_inv_scale.ptr, s->params.c_reduced, s->cp,
+                                  (const double*)tmp.ptr, nullptr);
+    RT_HIP(hipGetLastError());
+    RT_HIP(hipDeviceSynchronize());
+    return RT_OK;
+}
+
+extern "C" int rt_state_info(const rt_state* s, int64_t* n_cells, int32_t* nb, int64_t* n_src, int32_t* precision,
+                             double* dt_cfl) {
+    if (!s) return rt_fail(RT_EINVAL, "null state");
+    if (n_cells) *n_cells = s->nc;
+    if (nb) *nb = s->nb;
+    if (n_src) *n_src = s->n_src;
+    if (precision) *precision = s->precision;
+    if (dt_cfl) *dt_cfl = s->dt_cfl;
+    return RT_OK;
+}
+
+extern "C" int rt_state_diagnostics(const rt_state* s, rt_diag* out) {
+    if (!s || !out) return rt_fail(RT_EINVAL, "null argument");
+    *out = s->diag;
+    return RT_OK;
+}
+
+extern "C" int rt_profile_enable(rt_state* s, int enable) {
+    if (!s) return rt_fail(RT_EINVAL, "null state");
+    s->prof = enable != 0;
+    return RT_OK;
+}
+
+extern "C" int rt_profile_reset(rt_state* s) {
+    if (!s) return rt_fail(RT_EINVAL, "null state");
+    for (int k = 0; k < RT_N_KERNELS; ++k) { s->launches[k] = 0; s->total_ms[k] = 0; }
+    return RT_OK;
+}
+
+extern "C" int rt_profile_read(const rt_state* s, int kernel, int64_t* launches, double* total_ms) {
+    if (!s || kernel < 0 || kernel >= RT_N_KERNELS) return rt_fail(RT_EINVAL, "bad argument");
+    if (launches) *launches = s->launches[kernel];
+    if (total_ms) *total_ms = s->total_ms[kernel];
+    return RT_OK;
+}

@@ -1,0 +1,109 @@
+// Internal host-side structures of the M1 radiative-transfer library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <utility>
+#include <vector>
+
+#include "rt.h"
+#include "rt_kernels.hpp"
+#include "rt_types.hpp"
+
+// Sets the thread-local error message and returns `code`.
+int rt_fail(int code, const char* fmt, ...);
+
+// Owning device allocation.
+struct DevMem {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    int alloc(size_t nbytes);
+    int upload(const void* src, size_t nbytes);
+    void release();
+};
+
+struct rt_mesh {
+    int device = 0;
+    int64_t nc = 0, nf = 0;
+    double h_ref = 1.0;          // length unit of the stored geometry: <V>^(1/3)
+    double dx_min = 0.0;         // min_i (3 V_i / 4 pi)^(1/3), cm
+    int32_t max_deg = 0;
+    std::atomic<int> refs{0};
+    // Host copies (FP64, units of h_ref).
+    std::vector<double> face;    // [10][nf]
+    std::vector<double> minv;    // [6][nc]
+    std::vector<double> vol;     // [nc]
+    std::vector<double> vcap;    // [nc]
+    std::vector<double> vphys;   // [nc] cm^3
+    std::vector<int32_t> deg;    // faces per cell
+    std::vector<int32_t> nbr, fsf, sptr, sdeg;   // sliced ELL
+    // Device copies.
+    DevMem d_face64, d_minv64, d_vol64, d_vcap64, d_vphys;
+    DevMem d_face32, d_minv32, d_vol32, d_vcap32;
+    bool geo32_ready = false;
+    DevMem d_nbr, d_fsf, d_sptr, d_sdeg;
+
+    int build_float_geometry();
+};
+
+void rt_mesh_release(rt_mesh* m);
+
+struct rt_state {
+    rt_mesh* mesh = nullptr;
+    rt_params params{};
+    rtk::ChemParams cp{};
+    int precision = RT_FP64;
+    int nb = 1;
+    int64_t nc = 0;
+    double dt_cfl = 0.0;
+
+    // Fields: U[b][4][nc] = (N, Fh_x, Fh_y, Fh_z) / scale_b in the transport
+    // precision, double-buffered; gradients G[b][4][3][nc]; chemistry in FP64.
+    DevMem U[2];
+    int cur = 0;
+    DevMem G;
+    DevMem X, Ue, nH;            // [5][nc], [nc], [nc]
+    double scale[RT_MAX_BINS];
+    DevMem d_scale, d_inv_scale, d_nv_scale;
+
+    // Sources (original order on the host; sorted by cell on the device).
+    int64_t n_src = 0;
+    std::vector<int64_t> src_cell;
+    std::vector<double> src_rate;    // [nb][n_src]
+    int32_t n_src_cells = 0;
+    DevMem d_src_cell, d_src_ptr, d_src_rate, d_src_vphys;
+
+    // Per-block partials and the diagnostics record.
+    int64_t n_fblk = 0, n_cblk = 0;
+    DevMem part_nv, part_cnt, part_fst, chem_sum, chem_max, chem_st, d_diag;
+    rtk::DiagDev* h_diag = nullptr;
+    rt_diag diag{};
+
+    // Entry copy for roll-back on error.
+    DevMem bU, bX, bUe;
+
+    // Profiling.
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    int prof_open = -1;
+    int prof_kernel = 0;
+    std::vector<std::pair<int, int>> ev_marks;
+    int64_t launches[RT_N_KERNELS] = {0, 0, 0, 0, 0};
+    double total_ms[RT_N_KERNELS] = {0, 0, 0, 0, 0};
+
+    ~rt_state();
+    size_t tbytes() const;
+    int alloc_buffers();
+    int upload_scales();
+    int upload_sources();
+    void prof_begin(int kernel, hipStream_t st);
+    void prof_end(hipStream_t st);
+    int prof_collect();
+};

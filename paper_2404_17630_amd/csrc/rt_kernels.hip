@@ -1,0 +1,686 @@
+// HIP kernels of the M1 radiative-transfer subcycle for gfx950 (CDNA4).
+//
+// One subcycle (Zier et al. 2024, Fig. 1) is five launches on one stream:
+//   k_sources   point-source injection, one lane per source cell
+//   k_chem      thermochemistry + absorption, one lane per cell (FP64)
+//   k_gradient  least-squares gradients + slope limiter, one lane per (cell, bin)
+//   k_flux      face fluxes + divergence update, one lane per (cell, bin)
+//   (k_reduce   diagnostics, once per call)
+// The path is a six-neighbour gather stencil bound by HBM bandwidth, so
+// there is no matrix-core work: lanes of a wavefront are 64 consecutive
+// cells of one bin (coalesced SoA loads of the cell's own fields), each
+// cell gathers its neighbours through a sliced-ELL face list, and each cell
+// recomputes the fluxes of its own faces from the states of both sides in
+// the face's canonical (L, R) orientation.  The two cells of a face thus
+// obtain bit-identical fluxes of opposite sign: accumulation is
+// deterministic and needs no atomics or face-flux array (the paper's GPU
+// design stores fluxes per interface and gathers them in a second kernel,
+// Sec. 4.1.3).  T is the transport precision (double, or float in the
+// mixed form); flux sums, photon sums and chemistry are always double.
+
+#include <hip/hip_runtime.h>
+
+#include "rt_chem.hpp"
+#include "rt_kernels.hpp"
+#include "rt_types.hpp"
+
+namespace rtk {
+
+// ---------------------------------------------------------------------------
+// Reduction helpers (wave64 shuffles, then the four waves of a block in a
+// fixed order).
+// ---------------------------------------------------------------------------
+
+template <typename V>
+__device__ inline V wave_sum(V v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <typename V>
+__device__ inline V wave_max(V v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        V w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+__device__ inline int wave_or(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the block; the result is valid in thread 0.
+template <typename V>
+__device__ inline V block_sum(V v, V* lds) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    V s = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kBlock / 64; ++k) s += lds[k];
+    return s;
+}
+template <typename V>
+__device__ inline V block_max(V v, V* lds) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    V s = lds[0];
+    if (threadIdx.x == 0)
+        for (int k = 1; k < kBlock / 64; ++k) s = lds[k] > s ? lds[k] : s;
+    return s;
+}
+__device__ inline int block_or(int v, int* lds) {
+    v = wave_or(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    int s = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kBlock / 64; ++k) s |= lds[k];
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Fill kernels (used instead of memset so every launch is a kernel).
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_bytes(uint32_t* p, int64_t n_words, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_words) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// k_sources: N_b += Q_bk dt / V_k for the sources of each source cell, in
+// source-list order (sources were stably sorted by cell on the host).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_sources(T* __restrict__ U, int64_t nc, int nb, int32_t n_cells_src,
+                          const int32_t* __restrict__ cell, const int32_t* __restrict__ ptr,
+                          const double* __restrict__ rate /*[nb][n_src] sorted*/, int64_t n_src,
+                          const double* __restrict__ vphys /*[n_src]*/, const double* __restrict__ inv_scale,
+                          const double* __restrict__ scale, double dt) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells_src) return;
+    const int64_t i = cell[c];
+    for (int b = 0; b < nb; ++b) {
+        T* Nb = U + (int64_t)(b * 4) * nc;
+        double N = (double)Nb[i] * scale[b];
+        for (int32_t k = ptr[c]; k < ptr[c + 1]; ++k) N = N + rate[(int64_t)b * n_src + k] * dt / vphys[k];
+        Nb[i] = (T)(N * inv_scale[b]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_chem: one lane per cell; the whole adaptive substep sequence stays in
+// registers (Sec. 4.1.1).
+// ---------------------------------------------------------------------------
+
+template <int NB, typename T>
+__global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __restrict__ X /*[5][nc]*/,
+                                                 double* __restrict__ Ue /*[nc]*/, const double* __restrict__ nH,
+                                                 int64_t nc, ChemParams P, double dt,
+                                                 const double* __restrict__ scale, const double* __restrict__ inv_scale,
+                                                 int64_t* __restrict__ part_sum, int64_t* __restrict__ part_max,
+                                                 int32_t* __restrict__ part_status) {
+    __shared__ int64_t lds64[kBlock / 64];
+    __shared__ int lds32[kBlock / 64];
+    const int64_t blk = xcd_logical_block();
+    const int64_t i = blk * kBlock + threadIdx.x;
+    int attempts = 0;
+    int status = 0;
+    if (i < nc) {
+        double N[NB], Fh[NB][3], x[5];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            N[b] = (double)U[(int64_t)(b * 4) * nc + i] * scale[b];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Fh[b][k] = (double)U[(int64_t)(b * 4 + 1 + k) * nc + i] * scale[b];
+        }
+#pragma unroll
+        for (int s = 0; s < 5; ++s) x[s] = X[(int64_t)s * nc + i];
+        double u = Ue[i];
+        attempts = integrate_cell<NB>(P, dt, nH[i], N, Fh, x, u);
+        if (attempts > P.max_sub) {
+            status = 2;              // leave the cell untouched; the call is rolled back
+        } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                U[(int64_t)(b * 4) * nc + i] = (T)(N[b] * inv_scale[b]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) U[(int64_t)(b * 4 + 1 + k) * nc + i] = (T)(Fh[b][k] * inv_scale[b]);
+            }
+#pragma unroll
+            for (int s = 0; s < 5; ++s) X[(int64_t)s * nc + i] = x[s];
+            Ue[i] = u;
+            if (!isfinite(u)) status |= 1;
+        }
+    }
+    const int64_t s = block_sum<int64_t>(attempts, lds64);
+    const int64_t m = block_max<int64_t>(attempts, lds64);
+    const int st = block_or(status, lds32);
+    if (threadIdx.x == 0) {
+        part_sum[blk] += s;
+        part_max[blk] = m > part_max[blk] ? m : part_max[blk];
+        part_status[blk] |= st;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_gradient: g = M^-1 sum_j w_ij (phi_j - phi_i) for phi = N, Fh_x, Fh_y,
+// Fh_z of one bin (Sec. 2.3.2, eq. normalEquation), w_ij = A d / |d|^2 with
+// d = s_j - s_i taken through the face centre, then a Barth-Jespersen factor
+// per variable so that no face-centre extrapolation leaves [min, max] of the
+// cell and its neighbours.  Output layout g[b][v][k][nc].
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gradient(const T* __restrict__ U, T* __restrict__ G, int64_t nc, int nb,
+                                                     GeomView<T> geo, SellView sell, int use_limiter) {
+    const int64_t blk = xcd_logical_block();
+    const int b = (int)(blk % nb);
+    const int64_t i = (blk / nb) * kBlock + threadIdx.x;
+    if (i >= nc) return;
+    const int64_t nf = geo.nf;
+    const T* Ub = U + (int64_t)(b * 4) * nc;
+
+    T ui[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ui[v] = Ub[(int64_t)v * nc + i];
+    T bs[4][3], umax[4], umin[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        bs[v][0] = bs[v][1] = bs[v][2] = T(0);
+        umax[v] = umin[v] = ui[v];
+    }
+    const int64_t slice = i / kSlice;
+    const int32_t deg = sell.deg[slice];
+    const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
+    for (int k = 0; k < deg; ++k) {
+        const int64_t e = base + (int64_t)k * kSlice;
+        const int32_t j = sell.nbr[e];
+        if (j < 0) continue;
+        const int32_t fs = sell.fsf[e];
+        const bool isL = fs >= 0;
+        const int64_t f = isL ? fs : ~fs;
+        const T A = geo.face[f];
+        const T rl0 = geo.face[4 * nf + f], rl1 = geo.face[5 * nf + f], rl2 = geo.face[6 * nf + f];
+        const T rr0 = geo.face[7 * nf + f], rr1 = geo.face[8 * nf + f], rr2 = geo.face[9 * nf + f];
+        // d = r_if - r_jf = s_j - s_i
+        const T d0 = isL ? rl0 - rr0 : rr0 - rl0;
+        const T d1 = isL ? rl1 - rr1 : rr1 - rl1;
+        const T d2 = isL ? rl2 - rr2 : rr2 - rl2;
+        const T s = A / (d0 * d0 + d1 * d1 + d2 * d2);
+        const T w0 = d0 * s, w1 = d1 * s, w2 = d2 * s;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const T uj = Ub[(int64_t)v * nc + j];
+            const T dphi = uj - ui[v];
+            bs[v][0] += w0 * dphi;
+            bs[v][1] += w1 * dphi;
+            bs[v][2] += w2 * dphi;
+            umax[v] = uj > umax[v] ? uj : umax[v];
+            umin[v] = uj < umin[v] ? uj : umin[v];
+        }
+    }
+    const T mxx = geo.minv[i], myy = geo.minv[nc + i], mzz = geo.minv[2 * nc + i];
+    const T mxy = geo.minv[3 * nc + i], mxz = geo.minv[4 * nc + i], myz = geo.minv[5 * nc + i];
+    T g[4][3];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        g[v][0] = mxx * bs[v][0] + mxy * bs[v][1] + mxz * bs[v][2];
+        g[v][1] = mxy * bs[v][0] + myy * bs[v][1] + myz * bs[v][2];
+        g[v][2] = mxz * bs[v][0] + myz * bs[v][1] + mzz * bs[v][2];
+    }
+    if (use_limiter) {
+        T alpha[4] = {T(1), T(1), T(1), T(1)};
+        for (int k = 0; k < deg; ++k) {
+            const int64_t e = base + (int64_t)k * kSlice;
+            if (sell.nbr[e] < 0) continue;
+            const int32_t fs = sell.fsf[e];
+            const bool isL = fs >= 0;
+            const int64_t f = isL ? fs : ~fs;
+            const int64_t o = isL ? 4 * nf : 7 * nf;
+            const T r0 = geo.face[o + f], r1 = geo.face[o + nf + f], r2 = geo.face[o + 2 * nf + f];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const T delta = g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2;
+                T psi = T(1);
+                if (delta > T(0)) psi = (umax[v] - ui[v]) / delta;
+                else if (delta < T(0)) psi = (umin[v] - ui[v]) / delta;
+                alpha[v] = psi < alpha[v] ? psi : alpha[v];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            g[v][0] *= alpha[v];
+            g[v][1] *= alpha[v];
+            g[v][2] *= alpha[v];
+        }
+    }
+    T* Gb = G + (int64_t)(b * 12) * nc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Gb[(int64_t)(v * 3 + c) * nc + i] = g[v][c];
+}
+
+// ---------------------------------------------------------------------------
+// Face physics (Sec. 2.3.3): admissibility of an extrapolated state,
+// M1 closure (eq. edd) with the Levermore factor, HLL flux with bounds
+// -c~, +c~.  Fluxes are in units of c~ (the caller multiplies by c~ dt / h).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ inline void make_admissible(T* U, int& cN, int& cF) {
+    if (U[0] < T(0)) { U[0] = T(0); ++cN; }
+    const T F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+    if (F2 > U[0] * U[0]) {
+        ++cF;
+        if (U[0] <= T(0)) {
+            U[1] = U[2] = U[3] = T(0);
+        } else {
+            const T s = U[0] / sqrt(F2);
+            U[1] *= s; U[2] *= s; U[3] *= s;
+        }
+    }
+}
+
+// N D n for state U = (N, Fh).
+template <typename T>
+__device__ inline void radiation_pressure_n(const T* U, T n0, T n1, T n2, T* P) {
+    const T N = U[0];
+    const T F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+    if (N <= T(0) || F2 <= T(0)) {
+        const T third = N * T(1.0 / 3.0);
+        P[0] = third * n0; P[1] = third * n1; P[2] = third * n2;
+        return;
+    }
+    const T Fm = sqrt(F2);
+    T f = Fm / N;
+    f = f < T(1) ? f : T(1);
+    const T chi = (T(3) + T(4) * f * f) / (T(5) + T(2) * sqrt(T(4) - T(3) * f * f));
+    const T iso = T(0.5) * (T(1) - chi);
+    const T dir = T(0.5) * (T(3) * chi - T(1)) * (U[1] * n0 + U[2] * n1 + U[3] * n2) / F2;
+    P[0] = N * (iso * n0 + dir * U[1]);
+    P[1] = N * (iso * n1 + dir * U[2]);
+    P[2] = N * (iso * n2 + dir * U[3]);
+}
+
+template <typename T>
+__device__ inline void hll_flux(const T* UL, const T* UR, T n0, T n1, T n2, T* Phi) {
+    T PL[3], PR[3];
+    radiation_pressure_n(UL, n0, n1, n2, PL);
+    radiation_pressure_n(UR, n0, n1, n2, PR);
+    const T FLn = UL[1] * n0 + UL[2] * n1 + UL[3] * n2;
+    const T FRn = UR[1] * n0 + UR[2] * n1 + UR[3] * n2;
+    Phi[0] = T(0.5) * (FLn + FRn) - T(0.5) * (UR[0] - UL[0]);
+    Phi[1] = T(0.5) * (PL[0] + PR[0]) - T(0.5) * (UR[1] - UL[1]);
+    Phi[2] = T(0.5) * (PL[1] + PR[1]) - T(0.5) * (UR[2] - UL[2]);
+    Phi[3] = T(0.5) * (PL[2] + PR[2]) - T(0.5) * (UR[3] - UL[3]);
+}
+
+// ---------------------------------------------------------------------------
+// k_flux: for each face of the cell, both face states from the
+// start-of-transport fields and gradients, the HLL flux, the outflow cap
+// theta = min(1, N_up V_up / (n_faces(up) |Phi_N| dt A)); then
+// U_i <- U_i - (dt / V_i) sum_f sigma A Phi in face-index order, with
+// post-update guards.  Writes the new fields to Unew (double buffering:
+// neighbours still read U).  Per-block partials: sum N V (this bin),
+// counters and status, accumulated across the subcycles of one call.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ G, T* __restrict__ Unew,
+                                                 int64_t nc, int nb, GeomView<T> geo, SellView sell, T cdt,
+                                                 double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
+                                                 int32_t* __restrict__ part_status, int64_t n_blocks) {
+    __shared__ double ldsd[kBlock / 64];
+    __shared__ int64_t ldsi[kBlock / 64];
+    __shared__ int ldss[kBlock / 64];
+    const int64_t blk = xcd_logical_block();
+    const int b = (int)(blk % nb);
+    const int64_t i = (blk / nb) * kBlock + threadIdx.x;
+    const int64_t nf = geo.nf;
+    const T* Ub = U + (int64_t)(b * 4) * nc;
+    const T* Gb = G + (int64_t)(b * 12) * nc;
+
+    int cAdmN = 0, cAdmF = 0, cCap = 0, cGN = 0, cGF = 0, status = 0;
+    double nv = 0.0;
+    if (i < nc) {
+        T ui[4], gi[4][3];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            ui[v] = Ub[(int64_t)v * nc + i];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gi[v][c] = Gb[(int64_t)(v * 3 + c) * nc + i];
+        }
+        const T vcap_i = geo.vcap[i];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const int64_t slice = i / kSlice;
+        const int32_t deg = sell.deg[slice];
+        const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
+        for (int k = 0; k < deg; ++k) {
+            const int64_t e = base + (int64_t)k * kSlice;
+            const int32_t j = sell.nbr[e];
+            if (j < 0) continue;
+            const int32_t fs = sell.fsf[e];
+            const bool isL = fs >= 0;
+            const int64_t f = isL ? fs : ~fs;
+            const T A = geo.face[f];
+            const T n0 = geo.face[nf + f], n1 = geo.face[2 * nf + f], n2 = geo.face[3 * nf + f];
+            T rl[3], rr[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                rl[c] = geo.face[(4 + c) * nf + f];
+                rr[c] = geo.face[(7 + c) * nf + f];
+            }
+            T uj[4], gj[4][3];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                uj[v] = Ub[(int64_t)v * nc + j];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gj[v][c] = Gb[(int64_t)(v * 3 + c) * nc + j];
+            }
+            const T vcap_j = geo.vcap[j];
+            // Canonical orientation: L then R, whichever lane computes it.
+            T UL[4], UR[4], sL[4], sR[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                UL[v] = isL ? ui[v] : uj[v];
+                UR[v] = isL ? uj[v] : ui[v];
+                const T gl0 = isL ? gi[v][0] : gj[v][0], gl1 = isL ? gi[v][1] : gj[v][1], gl2 = isL ? gi[v][2] : gj[v][2];
+                const T gr0 = isL ? gj[v][0] : gi[v][0], gr1 = isL ? gj[v][1] : gi[v][1], gr2 = isL ? gj[v][2] : gi[v][2];
+                sL[v] = UL[v] + (gl0 * rl[0] + gl1 * rl[1] + gl2 * rl[2]);
+                sR[v] = UR[v] + (gr0 * rr[0] + gr1 * rr[1] + gr2 * rr[2]);
+            }
+            int aN = 0, aF = 0;
+            make_admissible(sL, aN, aF);
+            make_admissible(sR, aN, aF);
+            T Phi[4];
+            hll_flux(sL, sR, n0, n1, n2, Phi);
+            bool capped = false;
+            if (Phi[0] != T(0)) {
+                const bool upL = Phi[0] > T(0);
+                const T Nup = upL ? UL[0] : UR[0];
+                const T vc = upL ? (isL ? vcap_i : vcap_j) : (isL ? vcap_j : vcap_i);
+                const T cap = Nup * vc / (fabs(Phi[0]) * cdt * A);
+                if (cap < T(1)) {
+                    capped = true;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Phi[v] = cap * Phi[v];
+                }
+            }
+            if (isL) {
+                cAdmN += aN; cAdmF += aF; cCap += capped ? 1 : 0;
+            }
+            const T sA = isL ? A : -A;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += (double)(sA * Phi[v]);
+        }
+        const double coef = (double)cdt / (double)geo.vol[i];
+        double un[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) un[v] = (double)ui[v] - coef * acc[v];
+        if (un[0] < 0.0) { un[0] = 0.0; ++cGN; }
+        const double F2 = un[1] * un[1] + un[2] * un[2] + un[3] * un[3];
+        if (F2 > un[0] * un[0]) {
+            ++cGF;
+            if (un[0] <= 0.0) {
+                un[1] = un[2] = un[3] = 0.0;
+            } else {
+                const double s = un[0] / sqrt(F2);
+                un[1] *= s; un[2] *= s; un[3] *= s;
+            }
+        }
+        T* Ob = Unew + (int64_t)(b * 4) * nc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const T o = (T)un[v];
+            Ob[(int64_t)v * nc + i] = o;
+            if (!isfinite((double)o)) status = 1;
+        }
+        nv = (double)(T)un[0] * (double)geo.vol[i];
+    }
+    const double snv = block_sum<double>(nv, ldsd);
+    const int64_t s0 = block_sum<int64_t>(cAdmN, ldsi);
+    const int64_t s1 = block_sum<int64_t>(cAdmF, ldsi);
+    const int64_t s2 = block_sum<int64_t>(cCap, ldsi);
+    const int64_t s3 = block_sum<int64_t>(cGN, ldsi);
+    const int64_t s4 = block_sum<int64_t>(cGF, ldsi);
+    const int st = block_or(status, ldss);
+    if (threadIdx.x == 0) {
+        part_nv[blk] = snv;
+        part_cnt[0 * n_blocks + blk] += s0;
+        part_cnt[1 * n_blocks + blk] += s1;
+        part_cnt[2 * n_blocks + blk] += s2;
+        part_cnt[3 * n_blocks + blk] += s3;
+        part_cnt[4 * n_blocks + blk] += s4;
+        part_status[blk] |= st;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_reduce: one block folds the per-block partials in a fixed order into the
+// diagnostics record (deterministic).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part_nv, const int64_t* __restrict__ part_cnt,
+                                                   const int32_t* __restrict__ part_fstatus, int64_t n_fblocks, int nb,
+                                                   const int64_t* __restrict__ chem_sum, const int64_t* __restrict__ chem_max,
+                                                   const int32_t* __restrict__ chem_status, int64_t n_cblocks,
+                                                   const double* __restrict__ nv_scale /*[nb] scale*h^3*/,
+                                                   DiagDev* __restrict__ out) {
+    __shared__ double ldsd[kBlock / 64];
+    __shared__ int64_t ldsi[kBlock / 64];
+    __shared__ int ldss[kBlock / 64];
+    for (int b = 0; b < nb; ++b) {
+        double s = 0.0;
+        for (int64_t k = threadIdx.x; k * nb + b < n_fblocks; k += kBlock) s += part_nv[k * nb + b];
+        s = block_sum<double>(s, ldsd);
+        if (threadIdx.x == 0) out->photon_sum[b] = s * nv_scale[b];
+    }
+    for (int c = 0; c < 5; ++c) {
+        int64_t s = 0;
+        for (int64_t k = threadIdx.x; k < n_fblocks; k += kBlock) s += part_cnt[c * n_fblocks + k];
+        s = block_sum<int64_t>(s, ldsi);
+        if (threadIdx.x == 0) out->counters[c] = s;
+    }
+    int st = 0;
+    for (int64_t k = threadIdx.x; k < n_fblocks; k += kBlock) st |= part_fstatus[k];
+    for (int64_t k = threadIdx.x; k < n_cblocks; k += kBlock) st |= chem_status[k];
+    st = block_or(st, ldss);
+    int64_t cs = 0, cm = 0;
+    for (int64_t k = threadIdx.x; k < n_cblocks; k += kBlock) {
+        cs += chem_sum[k];
+        cm = chem_max[k] > cm ? chem_max[k] : cm;
+    }
+    cs = block_sum<int64_t>(cs, ldsi);
+    cm = block_max<int64_t>(cm, ldsi);
+    if (threadIdx.x == 0) {
+        out->status = st;
+        out->substeps = cs;
+        out->max_substeps = cm;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CFL length: min_i (3 V_i / 4 pi)^(1/3) by a two-pass wave64 min-reduction.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_min_cfl_length(const double* __restrict__ vphys, int64_t nc,
+                                                           double* __restrict__ part) {
+    __shared__ double lds[kBlock / 64];
+    double m = INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nc; i += (int64_t)gridDim.x * kBlock)
+        m = fmin(m, cbrt(3.0 * vphys[i] / (4.0 * M_PI)));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlock / 64; ++k) m = fmin(m, lds[k]);
+        part[blockIdx.x] = fmin(m, lds[0]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Field conversion between the caller's FP64 layout and the internal one.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_get_fields(const T* __restrict__ U, const double* __restrict__ X, const double* __restrict__ Ue,
+                             int64_t nc, int nb, int field, const double* __restrict__ scale, double c_red,
+                             ChemParams P, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    if (field == 0) {
+        for (int b = 0; b < nb; ++b) out[(int64_t)b * nc + i] = (double)U[(int64_t)(b * 4) * nc + i] * scale[b];
+    } else if (field == 1) {
+        for (int b = 0; b < nb; ++b)
+            for (int k = 0; k < 3; ++k)
+                out[(int64_t)(b * 3 + k) * nc + i] = (double)U[(int64_t)(b * 4 + 1 + k) * nc + i] * scale[b] * c_red;
+    } else if (field == 4) {
+        double x[5];
+        for (int s = 0; s < 5; ++s) x[s] = X[(int64_t)s * nc + i];
+        out[i] = P.isothermal ? P.T_iso : temperature(P, Ue[i], x);
+    }
+}
+
+template <typename T>
+__global__ void k_set_fields(T* __restrict__ U, const double* __restrict__ X, double* __restrict__ Ue, int64_t nc,
+                             int nb, int field, const double* __restrict__ inv_scale, double c_red, ChemParams P,
+                             const double* __restrict__ in) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    if (field == 0) {
+        for (int b = 0; b < nb; ++b) U[(int64_t)(b * 4) * nc + i] = (T)(in[(int64_t)b * nc + i] * inv_scale[b]);
+    } else if (field == 1) {
+        for (int b = 0; b < nb; ++b)
+            for (int k = 0; k < 3; ++k)
+                U[(int64_t)(b * 4 + 1 + k) * nc + i] = (T)(in[(int64_t)(b * 3 + k) * nc + i] / c_red * inv_scale[b]);
+    } else if (field == 4) {
+        // thermal energy from T and the current fractions
+        double x[5];
+        for (int s = 0; s < 5; ++s) x[s] = X[(int64_t)s * nc + i];
+        Ue[i] = kBoltz * in[i] / (P.gm1 * mean_mass(P, x) * kProtonMass);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+
+static inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+void fill_words(void* p, int64_t n_words, uint32_t v, hipStream_t s) {
+    if (n_words <= 0) return;
+    hipLaunchKernelGGL(k_fill_bytes, dim3(grid_for(n_words, 256)), dim3(256), 0, s, (uint32_t*)p, n_words, v);
+}
+
+template <typename T>
+void launch_sources(T* U, int64_t nc, int nb, int32_t n_cells_src, const int32_t* cell, const int32_t* ptr,
+                    const double* rate, int64_t n_src, const double* vphys, const double* inv_scale,
+                    const double* scale, double dt, hipStream_t s) {
+    if (n_cells_src <= 0) return;
+    hipLaunchKernelGGL(k_sources<T>, dim3(grid_for(n_cells_src, 64)), dim3(64), 0, s, U, nc, nb, n_cells_src, cell,
+                       ptr, rate, n_src, vphys, inv_scale, scale, dt);
+}
+
+template <typename T, int NB>
+static void launch_chem_nb(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
+                           const double* scale, const double* inv_scale, int64_t* ps, int64_t* pm, int32_t* pst,
+                           hipStream_t s) {
+    hipLaunchKernelGGL((k_chem<NB, T>), dim3(grid_for(nc, kBlock)), dim3(kBlock), 0, s, U, X, Ue, nH, nc, P, dt,
+                       scale, inv_scale, ps, pm, pst);
+}
+
+template <typename T>
+void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
+                 const double* scale, const double* inv_scale, int64_t* ps, int64_t* pm, int32_t* pst,
+                 hipStream_t s) {
+    switch (P.nb) {
+#define RT_CHEM_CASE(K) \
+    case K: launch_chem_nb<T, K>(U, X, Ue, nH, nc, P, dt, scale, inv_scale, ps, pm, pst, s); break;
+        RT_CHEM_CASE(1) RT_CHEM_CASE(2) RT_CHEM_CASE(3) RT_CHEM_CASE(4)
+        RT_CHEM_CASE(5) RT_CHEM_CASE(6) RT_CHEM_CASE(7) RT_CHEM_CASE(8)
+#undef RT_CHEM_CASE
+        default: break;
+    }
+}
+
+int64_t chem_blocks(int64_t nc) { return (int64_t)grid_for(nc, kBlock); }
+int64_t transport_blocks(int64_t nc, int nb) { return (int64_t)grid_for(nc, kBlock) * nb; }
+
+template <typename T>
+void launch_gradient(const T* U, T* G, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
+                     int use_limiter, hipStream_t s) {
+    hipLaunchKernelGGL(k_gradient<T>, dim3((unsigned)transport_blocks(nc, nb)), dim3(kBlock), 0, s, U, G, nc, nb, geo,
+                       sell, use_limiter);
+}
+
+template <typename T>
+void launch_flux(const T* U, const T* G, T* Unew, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
+                 double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
+    const int64_t nblk = transport_blocks(nc, nb);
+    hipLaunchKernelGGL(k_flux<T>, dim3((unsigned)nblk), dim3(kBlock), 0, s, U, G, Unew, nc, nb, geo, sell, (T)cdt,
+                       part_nv, part_cnt, part_status, nblk);
+}
+
+void launch_reduce(const double* part_nv, const int64_t* part_cnt, const int32_t* part_fstatus, int64_t n_fblocks,
+                   int nb, const int64_t* chem_sum, const int64_t* chem_max, const int32_t* chem_status,
+                   int64_t n_cblocks, const double* nv_scale, DiagDev* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part_nv, part_cnt, part_fstatus, n_fblocks, nb,
+                       chem_sum, chem_max, chem_status, n_cblocks, nv_scale, out);
+}
+
+int64_t cfl_partials(int64_t nc) {
+    int64_t g = grid_for(nc, kBlock);
+    return g < 1024 ? g : 1024;
+}
+
+void launch_min_cfl_length(const double* vphys, int64_t nc, double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_min_cfl_length, dim3((unsigned)cfl_partials(nc)), dim3(kBlock), 0, s, vphys, nc, part);
+}
+
+template <typename T>
+void launch_get_fields(const T* U, const double* X, const double* Ue, int64_t nc, int nb, int field,
+                       const double* scale, double c_red, const ChemParams& P, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_get_fields<T>, dim3(grid_for(nc, 256)), dim3(256), 0, s, U, X, Ue, nc, nb, field, scale,
+                       c_red, P, out);
+}
+
+template <typename T>
+void launch_set_fields(T* U, const double* X, double* Ue, int64_t nc, int nb, int field, const double* inv_scale,
+                       double c_red, const ChemParams& P, const double* in, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_fields<T>, dim3(grid_for(nc, 256)), dim3(256), 0, s, U, X, Ue, nc, nb, field, inv_scale,
+                       c_red, P, in);
+}
+
+#define RT_INSTANTIATE(T)                                                                                          \
+    template void launch_sources<T>(T*, int64_t, int, int32_t, const int32_t*, const int32_t*, const double*,       \
+                                    int64_t, const double*, const double*, const double*, double, hipStream_t);    \
+    template void launch_chem<T>(T*, double*, double*, const double*, int64_t, const ChemParams&, double,           \
+                                 const double*, const double*, int64_t*, int64_t*, int32_t*, hipStream_t);          \
+    template void launch_gradient<T>(const T*, T*, int64_t, int, const GeomView<T>&, const SellView&, int,          \
+                                     hipStream_t);                                                                 \
+    template void launch_flux<T>(const T*, const T*, T*, int64_t, int, const GeomView<T>&, const SellView&, double, \
+                                 double*, int64_t*, int32_t*, hipStream_t);                                         \
+    template void launch_get_fields<T>(const T*, const double*, const double*, int64_t, int, int, const double*,   \
+                                       double, const ChemParams&, double*, hipStream_t);                           \
+    template void launch_set_fields<T>(T*, const double*, double*, int64_t, int, int, const double*, double,       \
+                                       const ChemParams&, const double*, hipStream_t);
+
+RT_INSTANTIATE(double)
+RT_INSTANTIATE(float)
+
+}  // namespace rtk

@@ -1,0 +1,59 @@
+// Launchers of the M1 radiative-transfer kernels (rt_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rt_types.hpp"
+
+namespace rtk {
+
+// Diagnostics record written by k_reduce.
+struct DiagDev {
+    double photon_sum[kMaxBins];
+    int64_t counters[5];     // adm_N, adm_F, flux_caps, guard_N, guard_F
+    int64_t substeps;
+    int64_t max_substeps;
+    int32_t status;
+    int32_t pad_;
+};
+
+void fill_words(void* p, int64_t n_words, uint32_t v, hipStream_t s);
+
+int64_t chem_blocks(int64_t nc);
+int64_t transport_blocks(int64_t nc, int nb);
+int64_t cfl_partials(int64_t nc);
+
+template <typename T>
+void launch_sources(T* U, int64_t nc, int nb, int32_t n_cells_src, const int32_t* cell, const int32_t* ptr,
+                    const double* rate, int64_t n_src, const double* vphys, const double* inv_scale,
+                    const double* scale, double dt, hipStream_t s);
+
+template <typename T>
+void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
+                 const double* scale, const double* inv_scale, int64_t* part_sum, int64_t* part_max,
+                 int32_t* part_status, hipStream_t s);
+
+template <typename T>
+void launch_gradient(const T* U, T* G, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
+                     int use_limiter, hipStream_t s);
+
+template <typename T>
+void launch_flux(const T* U, const T* G, T* Unew, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
+                 double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status, hipStream_t s);
+
+void launch_reduce(const double* part_nv, const int64_t* part_cnt, const int32_t* part_fstatus, int64_t n_fblocks,
+                   int nb, const int64_t* chem_sum, const int64_t* chem_max, const int32_t* chem_status,
+                   int64_t n_cblocks, const double* nv_scale, DiagDev* out, hipStream_t s);
+
+void launch_min_cfl_length(const double* vphys, int64_t nc, double* part, hipStream_t s);
+
+template <typename T>
+void launch_get_fields(const T* U, const double* X, const double* Ue, int64_t nc, int nb, int field,
+                       const double* scale, double c_red, const ChemParams& P, double* out, hipStream_t s);
+
+template <typename T>
+void launch_set_fields(T* U, const double* X, double* Ue, int64_t nc, int nb, int field, const double* inv_scale,
+                       double c_red, const ChemParams& P, const double* in, hipStream_t s);
+
+}  // namespace rtk

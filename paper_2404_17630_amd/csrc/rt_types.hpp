@@ -1,0 +1,61 @@
+// Device-side parameter blocks and launch helpers shared by the kernels and
+// the host driver of the M1 radiative-transfer library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtk {
+
+constexpr int kMaxBins = 8;
+constexpr int kBlock = 256;          // threads per workgroup (four wave64s)
+constexpr int kSlice = 64;           // cells per SELL slice = one wavefront
+constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, workgroups dispatched round-robin
+
+// Chemistry constants (from rt_params).
+struct ChemParams {
+    int nb, chem_mode, isothermal, rate_set, max_sub, pad_;
+    double c, T_iso, yhe, alpha_B, gm1, fmax, fs, growth, xfloor;
+    double sigma[kMaxBins][3];
+    double eheat[kMaxBins][3];
+};
+
+// Geometry of one precision variant (lengths in units of h_ref).
+//   face [10][nf]: A, n_x, n_y, n_z, rL_x, rL_y, rL_z, rR_x, rR_y, rR_z
+//     (rL = minimum-image offset from the L cell centre to the face centre)
+//   minv [6][nc]: xx, yy, zz, xy, xz, yz of the inverse geometry matrix
+//   vol  [nc]: V;  vcap [nc]: V / (number of faces of the cell)
+template <typename T>
+struct GeomView {
+    const T* face;
+    const T* minv;
+    const T* vol;
+    const T* vcap;
+    int64_t nf;
+};
+
+// Face sides of each cell in sliced-ELL order: slice s (cells 64s..64s+63)
+// holds deg[s] slots; slot k of lane l is entry ptr[s] + 64 k + l.  nbr is
+// the neighbour cell (-1 for padding), fsf the face index (f when the cell is
+// the face's L cell, ~f when it is R).  Slots are in increasing face index.
+struct SellView {
+    const int32_t* nbr;
+    const int32_t* fsf;
+    const int32_t* ptr;
+    const int32_t* deg;
+};
+
+// Workgroup id -> logical block: hardware hands workgroups to the 8 XCDs in
+// turn, so consecutive logical blocks (neighbouring cells in a locality
+// order) are remapped to run on the same XCD and share its L2.
+__device__ inline int64_t xcd_logical_block() {
+    const int64_t w = blockIdx.x;
+    const int64_t G = gridDim.x;
+    const int64_t xcd = w % kNumXcd;
+    const int64_t local = w / kNumXcd;
+    const int64_t per = G / kNumXcd;
+    const int64_t rem = G % kNumXcd;
+    return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+}  // namespace rtk

@@ -81,14 +81,16 @@ def _pack(name, mesh, params, state, src_cell, src_rate, n_sub, precision, **met
 
 
 def stromgren(n: int = 32, n_sub: int = 100, precision: str = "fp64", hhe: bool = False,
-              order: str = "hilbert", seed_offset: int = 1) -> dict:
+              order: str = "hilbert", seed_offset: int = 1, dims=None) -> dict:
     """Point source in uniform hydrogen (or H+He) gas."""
     h = 0.5 * KPC
-    mesh = jittered_lattice((n, n, n), h, 0.2, 1000 + seed_offset, order)
+    dims = (n, n, n) if dims is None else tuple(dims)
+    mesh = jittered_lattice(dims, h, 0.2, 1000 + seed_offset, order)
     lex = _lex_ids(mesh)
-    c = n // 2
-    src_lex = c + n * (c + n * c)
+    cx, cy, cz = (d // 2 for d in dims)
+    src_lex = cx + dims[0] * (cy + dims[1] * cz)
     src_cell = np.flatnonzero(lex == src_lex)
+    c = (cx, cy, cz)
     if hhe:
         nb = 3
         p = default_params(nb)
@@ -104,15 +106,15 @@ def stromgren(n: int = 32, n_sub: int = 100, precision: str = "fp64", hhe: bool 
     state = neutral_state(nb, mesh.n_cells, 1.0e-3, 1.0e4)
     name = "stromgren_hhe" if hhe else "stromgren"
     return _pack(name, mesh, p, state, src_cell, rate, n_sub, precision,
-                 source_lex=(c, c, c))
+                 source_lex=c)
 
 
 def cosmological(n: int, spacing_kpc: float, sigma_ln: float, n_src: int, c_frac: float,
                  n_sub: int, cfg_id: int, precision: str = "fp64", order: str = "hilbert",
-                 name: str = "cosmo", t0: float = 100.0, mean_nh: float = 2.0e-4) -> dict:
+                 name: str = "cosmo", t0: float = 100.0, mean_nh: float = 2.0e-4, dims=None) -> dict:
     """Lognormal H+He gas with power-law point sources at density peaks."""
     h = spacing_kpc * KPC
-    mesh = jittered_lattice((n, n, n), h, 0.2, 1000 + cfg_id, order)
+    mesh = jittered_lattice((n, n, n) if dims is None else tuple(dims), h, 0.2, 1000 + cfg_id, order)
     dims = mesh.dims
     g = fields.gaussian_random_field(dims, h, 2.0 * h, 2000 + cfg_id)
     n_lex = fields.lognormal_density(g, mean_nh, sigma_ln)
@@ -185,3 +187,33 @@ def by_name(name: str, **kw) -> dict:
         "travelling_wave": travelling_wave,
     }
     return table[name](**kw)
+
+
+def reorder(cfg: dict, perm: np.ndarray) -> dict:
+    """The same workload with cells relabelled: new cell k is old cell perm[k].
+    Faces stay grouped by their L cell (lattice meshes: three faces per cell)."""
+    perm = np.asarray(perm, dtype=np.int64)
+    m = cfg["mesh"]
+    nc, nf = m["n_cells"], m["n_faces"]
+    if nf != 3 * nc or not np.array_equal(m["face_cells"][0], np.repeat(np.arange(nc), 3)):
+        raise ValueError("reorder expects a lattice mesh from jittered_lattice")
+    new_of_old = np.empty(nc, dtype=np.int64)
+    new_of_old[perm] = np.arange(nc)
+    fperm = (3 * perm[:, None] + np.arange(3)[None, :]).reshape(-1)
+    mesh = dict(m, volume=np.ascontiguousarray(m["volume"][perm]),
+                centre=np.ascontiguousarray(m["centre"][:, perm]),
+                face_cells=np.ascontiguousarray(new_of_old[m["face_cells"][:, fperm]]),
+                area=np.ascontiguousarray(m["area"][fperm]), normal=np.ascontiguousarray(m["normal"][:, fperm]),
+                face_centre=np.ascontiguousarray(m["face_centre"][:, fperm]))
+    st = cfg["state"]
+    state = dict(N=np.ascontiguousarray(st["N"][:, perm]), F=np.ascontiguousarray(st["F"][..., perm]),
+                 n_H=np.ascontiguousarray(st["n_H"][perm]), species=np.ascontiguousarray(st["species"][:, perm]),
+                 T=np.ascontiguousarray(st["T"][perm]))
+    meta = dict(cfg["meta"], lattice_index=np.ascontiguousarray(cfg["meta"]["lattice_index"][:, perm]))
+    src = dict(cfg["sources"], cell=new_of_old[cfg["sources"]["cell"]])
+    return dict(cfg, mesh=mesh, state=state, sources=src, meta=meta)
+
+
+def random_order(cfg: dict, seed: int = 4000) -> dict:
+    """The workload in a seeded random cell order."""
+    return reorder(cfg, np.random.default_rng(seed).permutation(cfg["mesh"]["n_cells"]))

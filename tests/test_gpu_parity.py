@@ -1,0 +1,208 @@
+"""GPU parity of the FP64 path (through the C ABI) against the CPU oracle:
+1e-10 relative per field and bin (with a floor of 1e-10 of the field's
+maximum), plus determinism, conservation and the documented error paths."""
+import numpy as np
+import pytest
+
+import oracle
+import rtgen
+from paper_2404_17630_amd import rt
+from tests.gpu_common import field_errors, rel_err, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def assert_parity(cfg, gpu, ref, tol=TOL):
+    errs = field_errors(gpu, ref, cfg["params"]["c_reduced"])
+    worst = max(errs, key=errs.get)
+    say(cfg["name"], "worst", worst, f"{errs[worst]:.3e}")
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, bad
+    # photon sums per bin
+    assert np.allclose(gpu["diag"]["photon_sum"], ref["diag"]["photon_sum"], rtol=1e-12, atol=0)
+    assert gpu["diag"]["dt"] == pytest.approx(ref["diag"]["dt"], rel=1e-14)
+
+
+def test_stromgren_fp64_matches_oracle():
+    cfg = rtgen.stromgren()
+    say("stromgren 32^3, 100 subcycles, fp64")
+    gpu = run_gpu(cfg)
+    ref = oracle.run(cfg)
+    assert_parity(cfg, gpu, ref)
+    # same controller path: identical attempt counts
+    assert gpu["diag"]["substeps"] == ref["diag"]["substeps"]
+    assert gpu["diag"]["max_substeps"] == ref["diag"]["max_substeps"]
+    for k in ("guard_N", "guard_F", "adm_N", "adm_F", "flux_caps"):
+        assert abs(gpu["diag"][k] - ref["diag"][k]) <= 0.01 * max(ref["diag"][k], 100), k
+
+
+@pytest.mark.parametrize("order", ["hilbert", "random"])
+def test_hhe_ragged_mesh_matches_oracle(order):
+    """H+He, 3 bins, evolving T on a 20x18x17 lattice (6120 cells: several
+    256-cell blocks and a ragged last wavefront), two sources in one cell."""
+    cfg = rtgen.cosmological(0, 1.0, 1.0, 6, 0.01, 8, 2, dims=(20, 18, 17), order=order, name="hhe_ragged")
+    cfg["sources"]["cell"][1] = cfg["sources"]["cell"][0]
+    say("hhe ragged", order)
+    gpu = run_gpu(cfg)
+    ref = oracle.run(cfg)
+    assert_parity(cfg, gpu, ref)
+    assert gpu["diag"]["substeps"] == ref["diag"]["substeps"]
+
+
+def test_transport_only_travelling_wave():
+    cfg = rtgen.travelling_wave(n=12, n_sub=10, amplitude=0.1)
+    say("travelling wave")
+    gpu = run_gpu(cfg)
+    ref = oracle.run(cfg)
+    assert_parity(cfg, gpu, ref)
+
+
+def test_photon_conservation_on_gpu():
+    """Optically thin periodic transport conserves sum N V to rounding: each
+    face flux is computed bit-identically by both of its cells."""
+    cfg = rtgen.travelling_wave(n=16, n_sub=1, amplitude=0.1)
+    V = cfg["mesh"]["volume"]
+    total0 = float(np.sum(cfg["state"]["N"][0] * V))
+    m = rt.Mesh(cfg["mesh"])
+    s = rt.State.from_config(m, cfg)
+    for k in range(20):
+        s.subcycle(1)
+        tot = s.diagnostics()["photon_sum"][0]
+        assert abs(tot - total0) <= 1e-14 * total0 * (k + 1)
+    s.close()
+    m.close()
+
+
+def test_single_subcycle_pieces():
+    """One subcycle at a time for a few steps: catches an error that a long run
+    could average out."""
+    cfg = rtgen.cosmological(0, 1.0, 1.5, 4, 0.1, 1, 4, dims=(16, 16, 16), name="pieces")
+    m = rt.Mesh(cfg["mesh"])
+    s = rt.State.from_config(m, cfg)
+    st = cfg
+    for k in range(4):
+        s.subcycle(1)
+        g = s.fields()
+        g["diag"] = s.diagnostics()
+        ref = oracle.run(st, n_sub=1)
+        assert_parity(cfg, g, ref)
+        st = dict(cfg, state=dict(N=ref["N"], F=ref["F"], n_H=ref["n_H"], species=ref["species"], T=ref["T"]))
+    s.close()
+    m.close()
+
+
+def test_determinism_bitwise():
+    cfg = rtgen.cosmological(0, 1.0, 1.0, 6, 0.01, 6, 2, dims=(24, 24, 24), name="det")
+    a = run_gpu(cfg)
+    b = run_gpu(cfg)
+    for k in ("N", "F", "species", "T"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["diag"]["photon_sum"], b["diag"]["photon_sum"])
+
+
+def test_full_size_hhe_2m_first_subcycles():
+    """The 2.1M-cell H+He workload at full size: two subcycles against the
+    oracle, then the full 50 subcycles against the invariants."""
+    say("hhe_2m full size: generating")
+    cfg = rtgen.hhe_2m()
+    say("hhe_2m: gpu 2 subcycles")
+    gpu = run_gpu(cfg, n_sub=2)
+    say("hhe_2m: oracle 2 subcycles (about 30 s)")
+    ref = oracle.run(cfg, n_sub=2)
+    assert_parity(cfg, gpu, ref)
+    say("hhe_2m: gpu 50 subcycles")
+    full = run_gpu(cfg)
+    x = full["species"]
+    assert np.all((x >= 0) & (x <= 1))
+    assert np.abs(x[0] + x[1] - 1).max() < 1e-13
+    assert np.abs(x[2:].sum(0) - 1).max() < 1e-13
+    assert np.all(full["T"] > 0) and np.all(full["N"] >= 0)
+    Fm = np.sqrt(((full["F"] / cfg["params"]["c_reduced"]) ** 2).sum(1))
+    assert np.all(Fm <= full["N"] * (1 + 1e-12) + 1e-300)
+    assert full["diag"]["status"] == 0
+
+
+def test_clone_and_fields_roundtrip():
+    cfg = rtgen.cosmological(0, 1.0, 1.0, 3, 0.01, 3, 2, dims=(8, 8, 8), name="clone")
+    m = rt.Mesh(cfg["mesh"])
+    s = rt.State.from_config(m, cfg)
+    s.subcycle(2)
+    c = s.clone()
+    s.subcycle(1)
+    c.subcycle(1)
+    for f in (rt.RT_FIELD_N, rt.RT_FIELD_F, rt.RT_FIELD_SPECIES, rt.RT_FIELD_T):
+        assert np.array_equal(s.get(f), c.get(f))
+    # set/get round trip
+    N = s.get(rt.RT_FIELD_N) * 1.5
+    s.set(rt.RT_FIELD_N, N)
+    assert np.array_equal(s.get(rt.RT_FIELD_N), N)
+    T = s.get(rt.RT_FIELD_T)
+    s.set(rt.RT_FIELD_T, T * 2)
+    assert np.allclose(s.get(rt.RT_FIELD_T), 2 * T, rtol=1e-14)
+    info = s.info()
+    assert info["n_cells"] == 512 and info["nb"] == 3 and info["n_src"] == 3
+    c.close()
+    s.close()
+    m.close()
+
+
+def test_error_paths():
+    cfg = rtgen.stromgren(n=8, n_sub=2)
+    m = rt.Mesh(cfg["mesh"])
+    s = rt.State.from_config(m, cfg)
+    dt = s.info()["dt_cfl"]
+    with pytest.raises(rt.RtError) as e:
+        s.subcycle(1, dt=1.01 * dt)
+    assert e.value.code == rt.RT_EINVAL
+    # substep cap: the call fails and the state is unchanged
+    p = dict(cfg["params"], chem_max_substeps=2)
+    s2 = rt.State(m, p, rt.RT_FP64, cfg["state"]["N"], cfg["state"]["F"], cfg["state"]["n_H"],
+                  cfg["state"]["species"], cfg["state"]["T"], cfg["sources"]["cell"], cfg["sources"]["rate"])
+    before = s2.fields()
+    with pytest.raises(rt.RtError) as e:
+        s2.subcycle(3)      # ionising the source cell needs many more attempts
+    assert e.value.code == rt.RT_ENUMERIC
+    after = s2.fields()
+    for k in ("N", "F", "species", "T"):
+        assert np.array_equal(before[k], after[k]), k
+    assert s2.diagnostics()["status"] & 2
+    # invalid inputs at create
+    bad = np.array(cfg["state"]["N"])
+    bad[0, 3] = np.nan
+    with pytest.raises(rt.RtError) as e:
+        rt.State(m, cfg["params"], rt.RT_FP64, bad, cfg["state"]["F"], cfg["state"]["n_H"],
+                 cfg["state"]["species"], cfg["state"]["T"], cfg["sources"]["cell"], cfg["sources"]["rate"])
+    assert e.value.code == rt.RT_EINVAL
+    with pytest.raises(rt.RtError) as e:
+        rt.State(m, cfg["params"], rt.RT_FP64, cfg["state"]["N"], cfg["state"]["F"], cfg["state"]["n_H"],
+                 cfg["state"]["species"], cfg["state"]["T"], np.array([cfg["mesh"]["n_cells"]]),
+                 cfg["sources"]["rate"])
+    assert e.value.code == rt.RT_EINVAL
+    with pytest.raises(rt.RtError) as e:
+        rt.State(m, dict(cfg["params"], nb=9), rt.RT_FP64, cfg["state"]["N"], cfg["state"]["F"],
+                 cfg["state"]["n_H"], cfg["state"]["species"], cfg["state"]["T"], cfg["sources"]["cell"],
+                 cfg["sources"]["rate"])
+    assert e.value.code == rt.RT_EINVAL
+    s2.close()
+    s.close()
+    m.close()
+
+
+def test_no_sources_and_zero_subcycles():
+    cfg = rtgen.travelling_wave(n=6, n_sub=0)
+    gpu = run_gpu(cfg)
+    assert np.array_equal(gpu["N"], cfg["state"]["N"])
+    gpu = run_gpu(cfg, n_sub=3)
+    ref = oracle.run(cfg, n_sub=3)
+    assert rel_err(gpu["N"][0], ref["N"][0]) < TOL
+
+
+def test_profile_counters():
+    cfg = rtgen.stromgren(n=8, n_sub=5)
+    g = run_gpu(cfg, profile=True)
+    prof = g["profile"]
+    for k in (rt.RT_KERNEL_SOURCES, rt.RT_KERNEL_CHEM, rt.RT_KERNEL_GRADIENT, rt.RT_KERNEL_FLUX):
+        assert prof[k][0] == 5 and prof[k][1] > 0
+    assert prof[rt.RT_KERNEL_REDUCE][0] == 1
