@@ -717,10 +717,7 @@ int rt_state::prof_collect() {
 }
 
 template <typename T>
-static void run_subcycles(rt_state* s, int n, double dt, hipStream_t st) {
-    rt_mesh* m = s->mesh;
-    const int64_t nc = s->nc;
-    const int nb = s->nb;
+static GeomView<T> geom_view(const rt_mesh* m) {
     GeomView<T> geo;
     if (sizeof(T) == 8) {
         geo.face = (const T*)m->d_face64.ptr; geo.minv = (const T*)m->d_minv64.ptr;
@@ -730,33 +727,102 @@ static void run_subcycles(rt_state* s, int n, double dt, hipStream_t st) {
         geo.vol = (const T*)m->d_vol32.ptr; geo.vcap = (const T*)m->d_vcap32.ptr;
     }
     geo.nf = m->nf;
-    SellView sell{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_sptr.ptr,
-                  (const int32_t*)m->d_sdeg.ptr};
-    const double cdt = s->params.c_reduced * dt / m->h_ref;
+    return geo;
+}
+
+GeomView<double> rt_geo64(const rt_mesh* m) { return geom_view<double>(m); }
+
+SellView rt_sell(const rt_mesh* m) {
+    return SellView{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_sptr.ptr,
+                    (const int32_t*)m->d_sdeg.ptr};
+}
+
+// One piece of a subcycle on explicit buffers (U, G in the state's precision).
+void rt_step_sources(rt_state* s, void* U, double dt, hipStream_t st) {
+    s->prof_begin(RT_KERNEL_SOURCES, st);
+    if (s->precision == RT_MIXED)
+        launch_sources<float>((float*)U, s->nc, s->nb, s->n_src_cells, (const int32_t*)s->d_src_cell.ptr,
+                              (const int32_t*)s->d_src_ptr.ptr, (const double*)s->d_src_rate.ptr, s->n_src,
+                              (const double*)s->d_src_vphys.ptr, (const double*)s->d_inv_scale.ptr,
+                              (const double*)s->d_scale.ptr, dt, st);
+    else
+        launch_sources<double>((double*)U, s->nc, s->nb, s->n_src_cells, (const int32_t*)s->d_src_cell.ptr,
+                               (const int32_t*)s->d_src_ptr.ptr, (const double*)s->d_src_rate.ptr, s->n_src,
+                               (const double*)s->d_src_vphys.ptr, (const double*)s->d_inv_scale.ptr,
+                               (const double*)s->d_scale.ptr, dt, st);
+    s->prof_end(st);
+}
+
+void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStream_t st) {
+    if (s->params.chem_mode == RT_CHEM_NONE) return;
+    s->prof_begin(RT_KERNEL_CHEM, st);
+    if (s->precision == RT_MIXED)
+        launch_chem<float>((float*)U, X, Ue, (const double*)s->nH.ptr, s->nc, s->cp, dt, (const double*)s->d_scale.ptr,
+                           (const double*)s->d_inv_scale.ptr, (int64_t*)s->chem_sum.ptr, (int64_t*)s->chem_max.ptr,
+                           (int32_t*)s->chem_st.ptr, st);
+    else
+        launch_chem<double>((double*)U, X, Ue, (const double*)s->nH.ptr, s->nc, s->cp, dt,
+                            (const double*)s->d_scale.ptr, (const double*)s->d_inv_scale.ptr,
+                            (int64_t*)s->chem_sum.ptr, (int64_t*)s->chem_max.ptr, (int32_t*)s->chem_st.ptr, st);
+    s->prof_end(st);
+}
+
+void rt_step_gradient(rt_state* s, const void* U, void* G, hipStream_t st) {
+    s->prof_begin(RT_KERNEL_GRADIENT, st);
+    if (s->precision == RT_MIXED)
+        launch_gradient<float>((const float*)U, (float*)G, s->nc, s->nb, geom_view<float>(s->mesh), rt_sell(s->mesh),
+                               s->params.use_limiter, st);
+    else
+        launch_gradient<double>((const double*)U, (double*)G, s->nc, s->nb, geom_view<double>(s->mesh),
+                                rt_sell(s->mesh), s->params.use_limiter, st);
+    s->prof_end(st);
+}
+
+void rt_step_flux(rt_state* s, const void* U, const void* G, void* Un, double dt, hipStream_t st) {
+    const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
+    s->prof_begin(RT_KERNEL_FLUX, st);
+    if (s->precision == RT_MIXED)
+        launch_flux<float>((const float*)U, (const float*)G, (float*)Un, s->nc, s->nb, geom_view<float>(s->mesh),
+                           rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr, (int64_t*)s->part_cnt.ptr,
+                           (int32_t*)s->part_fst.ptr, st);
+    else
+        launch_flux<double>((const double*)U, (const double*)G, (double*)Un, s->nc, s->nb, geom_view<double>(s->mesh),
+                            rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr, (int64_t*)s->part_cnt.ptr,
+                            (int32_t*)s->part_fst.ptr, st);
+    s->prof_end(st);
+}
+
+void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st) {
     for (int it = 0; it < n; ++it) {
-        T* U = (T*)s->U[s->cur].ptr;
-        T* Un = (T*)s->U[s->cur ^ 1].ptr;
-        s->prof_begin(RT_KERNEL_SOURCES, st);
-        launch_sources<T>(U, nc, nb, s->n_src_cells, (const int32_t*)s->d_src_cell.ptr, (const int32_t*)s->d_src_ptr.ptr,
-                          (const double*)s->d_src_rate.ptr, s->n_src, (const double*)s->d_src_vphys.ptr,
-                          (const double*)s->d_inv_scale.ptr, (const double*)s->d_scale.ptr, dt, st);
-        s->prof_end(st);
-        if (s->params.chem_mode != RT_CHEM_NONE) {
-            s->prof_begin(RT_KERNEL_CHEM, st);
-            launch_chem<T>(U, (double*)s->X.ptr, (double*)s->Ue.ptr, (const double*)s->nH.ptr, nc, s->cp, dt,
-                           (const double*)s->d_scale.ptr, (const double*)s->d_inv_scale.ptr, (int64_t*)s->chem_sum.ptr,
-                           (int64_t*)s->chem_max.ptr, (int32_t*)s->chem_st.ptr, st);
-            s->prof_end(st);
-        }
-        s->prof_begin(RT_KERNEL_GRADIENT, st);
-        launch_gradient<T>(U, (T*)s->G.ptr, nc, nb, geo, sell, s->params.use_limiter, st);
-        s->prof_end(st);
-        s->prof_begin(RT_KERNEL_FLUX, st);
-        launch_flux<T>(U, (const T*)s->G.ptr, Un, nc, nb, geo, sell, cdt, (double*)s->part_nv.ptr,
-                       (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
-        s->prof_end(st);
+        void* U = s->U[s->cur].ptr;
+        void* Un = s->U[s->cur ^ 1].ptr;
+        rt_step_sources(s, U, dt, st);
+        rt_step_chem(s, U, (double*)s->X.ptr, (double*)s->Ue.ptr, dt, st);
+        rt_step_gradient(s, U, s->G.ptr, st);
+        rt_step_flux(s, U, s->G.ptr, Un, dt, st);
         s->cur ^= 1;
     }
+}
+
+void rt_reset_partials(rt_state* s, hipStream_t st) {
+    fill_words(s->part_cnt.ptr, 5 * s->n_fblk * 2, 0, st);
+    fill_words(s->part_fst.ptr, s->n_fblk, 0, st);
+    fill_words(s->part_nv.ptr, s->n_fblk * 2, 0, st);
+    fill_words(s->chem_sum.ptr, s->n_cblk * 2, 0, st);
+    fill_words(s->chem_max.ptr, s->n_cblk * 2, 0, st);
+    fill_words(s->chem_st.ptr, s->n_cblk, 0, st);
+}
+
+int rt_read_status(rt_state* s, hipStream_t st, int* status) {
+    launch_reduce((const double*)s->part_nv.ptr, (const int64_t*)s->part_cnt.ptr, (const int32_t*)s->part_fst.ptr,
+                  s->n_fblk, s->nb, (const int64_t*)s->chem_sum.ptr, (const int64_t*)s->chem_max.ptr,
+                  (const int32_t*)s->chem_st.ptr, s->n_cblk, (const double*)s->d_nv_scale.ptr, (DiagDev*)s->d_diag.ptr,
+                  st);
+    RT_HIP(hipGetLastError());
+    RT_HIP(hipMemcpyAsync(s->h_diag, s->d_diag.ptr, sizeof(DiagDev), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipStreamSynchronize(st));
+    *status = s->h_diag->status;
+    return RT_OK;
 }
 
 extern "C" int rt_subcycle(rt_state* s, int n, double dt, void* hip_stream) {
@@ -778,14 +844,8 @@ extern "C" int rt_subcycle(rt_state* s, int n, double dt, void* hip_stream) {
     RT_HIP(hipMemcpyAsync(s->bU.ptr, s->U[cur0].ptr, ubytes, hipMemcpyDeviceToDevice, st));
     RT_HIP(hipMemcpyAsync(s->bX.ptr, s->X.ptr, 5 * s->nc * 8, hipMemcpyDeviceToDevice, st));
     RT_HIP(hipMemcpyAsync(s->bUe.ptr, s->Ue.ptr, s->nc * 8, hipMemcpyDeviceToDevice, st));
-    fill_words(s->part_cnt.ptr, 5 * s->n_fblk * 2, 0, st);
-    fill_words(s->part_fst.ptr, s->n_fblk, 0, st);
-    fill_words(s->part_nv.ptr, s->n_fblk * 2, 0, st);
-    fill_words(s->chem_sum.ptr, s->n_cblk * 2, 0, st);
-    fill_words(s->chem_max.ptr, s->n_cblk * 2, 0, st);
-    fill_words(s->chem_st.ptr, s->n_cblk, 0, st);
-    if (s->precision == RT_MIXED) run_subcycles<float>(s, n, step, st);
-    else run_subcycles<double>(s, n, step, st);
+    rt_reset_partials(s, st);
+    rt_run_subcycles(s, n, step, st);
     s->prof_begin(RT_KERNEL_REDUCE, st);
     launch_reduce((const double*)s->part_nv.ptr, (const int64_t*)s->part_cnt.ptr, (const int32_t*)s->part_fst.ptr,
                   s->n_fblk, s->nb, (const int64_t*)s->chem_sum.ptr, (const int64_t*)s->chem_max.ptr,

@@ -18,126 +18,140 @@
 // recombination, collisional ionisation and their cooling, and Cen (1992,
 // ApJS 78, 341) dielectronic recombination, collisional-excitation cooling and
 // the free-free Gaunt factor.  Fits are evaluated at T >= 1 K.
+//
+// Everything is templated on the scalar type R (double in the forward
+// kernels, Dual<K> in the adjoint's replay).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include "rt_dual.hpp"
 #include "rt_types.hpp"
 
 namespace rtk {
 
-constexpr double kBoltz = 1.380649e-16;     // erg/K (CODATA 2018)
+constexpr double kBoltz = 1.380649e-16;            // erg/K (CODATA 2018)
 constexpr double kProtonMass = 1.67262192369e-24;  // g
 // Ionisation temperatures chi/k of H I, He I, He II (Hui & Gnedin 1997).
 constexpr double kTHI = 157807.0;
 constexpr double kTHeI = 285335.0;
 constexpr double kTHeII = 631515.0;
 
+template <typename R>
 struct Rates {
-    double rec_HII, rec_HeII, rec_HeIII;    // recombination coefficients, cm^3/s
-    double col_HI, col_HeI, col_HeII;       // collisional ionisation, cm^3/s
+    R rec_HII, rec_HeII, rec_HeIII;    // recombination coefficients, cm^3/s
+    R col_HI, col_HeI, col_HeII;       // collisional ionisation, cm^3/s
 };
 
 // Case-B hydrogenic recombination of Hui & Gnedin in terms of
 // lambda = 2 T_ion / T.
-__device__ inline double hg_rec_caseB(double lam) {
-    return 2.753e-14 * pow(lam, 1.5) / pow(1.0 + pow(lam * (1.0 / 2.740), 0.407), 2.242);
+template <typename R>
+__device__ inline R hg_rec_caseB(const R& lam) {
+    return 2.753e-14 * m_pow(lam, 1.5) / m_pow(1.0 + m_pow(lam * (1.0 / 2.740), 0.407), 2.242);
 }
 // Matching case-B recombination cooling coefficient (erg cm^3/s).
-__device__ inline double hg_rec_cool_caseB(double T, double lam) {
-    return 3.435e-30 * T * pow(lam, 1.970) / pow(1.0 + pow(lam * (1.0 / 2.250), 0.376), 3.720);
+template <typename R>
+__device__ inline R hg_rec_cool_caseB(const R& T, const R& lam) {
+    return 3.435e-30 * T * m_pow(lam, 1.970) / m_pow(1.0 + m_pow(lam * (1.0 / 2.250), 0.376), 3.720);
 }
 // Temperature shape of dielectronic He II recombination (Cen 1992).
-__device__ inline double cen_dielectronic(double T) {
-    return pow(T, -1.5) * exp(-470000.0 / T) * (1.0 + 0.3 * exp(-94000.0 / T));
+template <typename R>
+__device__ inline R cen_dielectronic(const R& T) {
+    return m_pow(T, -1.5) * m_exp(-470000.0 / T) * (1.0 + 0.3 * m_exp(-94000.0 / T));
 }
 
-__device__ inline Rates network_rates(const ChemParams& P, double T) {
-    Rates r;
+template <typename R>
+__device__ inline Rates<R> network_rates(const ChemParams& P, R T) {
+    Rates<R> r;
     if (P.rate_set == 0) {
         r.rec_HII = P.alpha_B;
-        r.rec_HeII = r.rec_HeIII = 0.0;
-        r.col_HI = r.col_HeI = r.col_HeII = 0.0;
+        r.rec_HeII = 0.0; r.rec_HeIII = 0.0;
+        r.col_HI = 0.0; r.col_HeI = 0.0; r.col_HeII = 0.0;
         return r;
     }
-    T = fmax(T, 1.0);
-    const double lH = 2.0 * kTHI / T, lHe1 = 2.0 * kTHeI / T, lHe2 = 2.0 * kTHeII / T;
-    const double t32 = pow(T, -1.5);
+    T = m_max(T, R(1.0));
+    const R lH = 2.0 * kTHI / T, lHe1 = 2.0 * kTHeI / T, lHe2 = 2.0 * kTHeII / T;
+    const R t32 = m_pow(T, -1.5);
     r.rec_HII = hg_rec_caseB(lH);
-    r.rec_HeII = 1.26e-14 * pow(lHe1, 0.75) + 1.9e-3 * cen_dielectronic(T);
+    r.rec_HeII = 1.26e-14 * m_pow(lHe1, 0.75) + 1.9e-3 * cen_dielectronic(T);
     r.rec_HeIII = 2.0 * hg_rec_caseB(lHe2);
-    r.col_HI = 21.11 * t32 * exp(-0.5 * lH) * pow(lH, -1.089) / pow(1.0 + pow(lH * (1.0 / 0.354), 0.874), 1.101);
-    r.col_HeI = 32.38 * t32 * exp(-0.5 * lHe1) * pow(lHe1, -1.146) / pow(1.0 + pow(lHe1 * (1.0 / 0.416), 0.987), 1.056);
-    r.col_HeII = 19.95 * t32 * exp(-0.5 * lHe2) * pow(lHe2, -1.089) / pow(1.0 + pow(lHe2 * (1.0 / 0.553), 0.735), 1.275);
+    r.col_HI = 21.11 * t32 * m_exp(-0.5 * lH) * m_pow(lH, -1.089) /
+               m_pow(1.0 + m_pow(lH * (1.0 / 0.354), 0.874), 1.101);
+    r.col_HeI = 32.38 * t32 * m_exp(-0.5 * lHe1) * m_pow(lHe1, -1.146) /
+                m_pow(1.0 + m_pow(lHe1 * (1.0 / 0.416), 0.987), 1.056);
+    r.col_HeII = 19.95 * t32 * m_exp(-0.5 * lHe2) * m_pow(lHe2, -1.089) /
+                 m_pow(1.0 + m_pow(lHe2 * (1.0 / 0.553), 0.735), 1.275);
     return r;
 }
 
 // Radiative cooling per volume (erg cm^-3 s^-1).  x = x_HI, x_HII, y_I, y_II, y_III.
-__device__ inline double cooling_rate(const ChemParams& P, double T, double nH, const double* x, const Rates& r) {
-    if (P.rate_set == 0) return 0.0;
-    T = fmax(T, 1.0);
+template <typename R>
+__device__ inline R cooling_rate(const ChemParams& P, R T, const R& nH, const R* x, const Rates<R>& r) {
+    if (P.rate_set == 0) return R(0.0);
+    T = m_max(T, R(1.0));
     const double yhe = P.yhe;
-    const double ne = nH * (x[1] + yhe * (x[3] + 2.0 * x[4]));
-    const double nHI = nH * x[0], nHII = nH * x[1];
-    const double nHe = yhe * nH;
-    const double nHeI = nHe * x[2], nHeII = nHe * x[3], nHeIII = nHe * x[4];
-    const double lH = 2.0 * kTHI / T, lHe1 = 2.0 * kTHeI / T, lHe2 = 2.0 * kTHeII / T;
-    const double sq = 1.0 + sqrt(T * 1.0e-5);
+    const R ne = nH * (x[1] + yhe * (x[3] + 2.0 * x[4]));
+    const R nHI = nH * x[0], nHII = nH * x[1];
+    const R nHe = yhe * nH;
+    const R nHeI = nHe * x[2], nHeII = nHe * x[3], nHeIII = nHe * x[4];
+    const R lH = 2.0 * kTHI / T, lHe1 = 2.0 * kTHeI / T, lHe2 = 2.0 * kTHeII / T;
+    const R sq = 1.0 + m_sqrt(T * 1.0e-5);
     // recombination (radiative, case B) and dielectronic recombination
-    double L = hg_rec_cool_caseB(T, lH) * nHII
-             + kBoltz * T * 1.26e-14 * pow(lHe1, 0.75) * nHeII
-             + 8.0 * hg_rec_cool_caseB(T, lHe2) * nHeIII
-             + 1.24e-13 * cen_dielectronic(T) * nHeII;
+    R L = hg_rec_cool_caseB(T, lH) * nHII
+        + kBoltz * T * 1.26e-14 * m_pow(lHe1, 0.75) * nHeII
+        + 8.0 * hg_rec_cool_caseB(T, lHe2) * nHeIII
+        + 1.24e-13 * cen_dielectronic(T) * nHeII;
     // collisional ionisation: one ionisation energy per event
     L += kBoltz * (kTHI * r.col_HI * nHI + kTHeI * r.col_HeI * nHeI + kTHeII * r.col_HeII * nHeII);
     // collisional excitation of H I and He II
-    L += 7.5e-19 * exp(-118348.0 / T) / sq * nHI + 5.54e-17 * pow(T, -0.397) * exp(-473638.0 / T) / sq * nHeII;
+    L += 7.5e-19 * m_exp(-118348.0 / T) / sq * nHI + 5.54e-17 * m_pow(T, -0.397) * m_exp(-473638.0 / T) / sq * nHeII;
     // free-free emission
-    const double lg = log10(T) - 5.5;
-    const double gff = 1.1 + 0.34 * exp(-lg * lg * (1.0 / 3.0));
-    L += 1.42e-27 * gff * sqrt(T) * (nHII + nHeII + 4.0 * nHeIII);
+    const R lg = m_log10(T) - 5.5;
+    const R gff = 1.1 + 0.34 * m_exp(-lg * lg * (1.0 / 3.0));
+    L += 1.42e-27 * gff * m_sqrt(T) * (nHII + nHeII + 4.0 * nHeIII);
     return ne * L;
 }
 
 // Mean particle mass per proton mass for the current ionisation state.
-__device__ inline double mean_mass(const ChemParams& P, const double* x) {
-    const double xe = x[1] + P.yhe * (x[3] + 2.0 * x[4]);
+template <typename R>
+__device__ inline R mean_mass(const ChemParams& P, const R* x) {
+    const R xe = x[1] + P.yhe * (x[3] + 2.0 * x[4]);
     return (1.0 + 4.0 * P.yhe) / (1.0 + P.yhe + xe);
 }
 
-__device__ inline double temperature(const ChemParams& P, double u, const double* x) {
+template <typename R>
+__device__ inline R temperature(const ChemParams& P, const R& u, const R* x) {
     return P.gm1 * mean_mass(P, x) * kProtonMass * u / kBoltz;
 }
 
 // Integrate one cell over the subcycle Dt.  N[b], Fh[b][3], x[5] and u are
 // updated in place; returns the number of attempts (> max_sub on failure).
-template <int NB>
-__device__ inline int integrate_cell(const ChemParams& P, double Dt, double nH, double* N, double (*Fh)[3],
-                                     double* x, double& u) {
+template <int NB, typename R>
+__device__ inline int integrate_cell(const ChemParams& P, double Dt, const R& nH, R* N, R (*Fh)[3], R* x, R& u) {
     const bool hhe = P.chem_mode == 2;
     const double ct = P.c;
     const double yhe = P.yhe;
-    const double rho = kProtonMass * nH * (1.0 + 4.0 * yhe);
-    double tau = 0.0;
-    double d = Dt;
+    const R rho = kProtonMass * nH * (1.0 + 4.0 * yhe);
+    R tau = 0.0;
+    R d = Dt;
     int attempts = 0;
     while (true) {
         bool last = false;
-        if (d >= Dt - tau) { d = Dt - tau; last = true; }
+        if (val(d) >= val(Dt - tau)) { d = Dt - tau; last = true; }
         if (++attempts > P.max_sub) return attempts;
 
-        const double T = P.isothermal ? P.T_iso : temperature(P, u, x);
-        const Rates r = network_rates(P, T);
-        const double ne = nH * (x[1] + yhe * (x[3] + 2.0 * x[4]));
-        const double nHI = nH * x[0];
-        const double nHeI = yhe * nH * x[2];
-        const double nHeII = yhe * nH * x[3];
+        const R T = P.isothermal ? R(P.T_iso) : temperature(P, u, x);
+        const Rates<R> r = network_rates(P, T);
+        const R ne = nH * (x[1] + yhe * (x[3] + 2.0 * x[4]));
+        const R nHI = nH * x[0];
+        const R nHeI = yhe * nH * x[2];
+        const R nHeII = yhe * nH * x[3];
 
-        double fac[NB], Nn[NB];
-        double G0 = 0.0, G1 = 0.0, G2 = 0.0, heat = 0.0;
+        R fac[NB], Nn[NB];
+        R G0 = 0.0, G1 = 0.0, G2 = 0.0, heat = 0.0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const double kap = P.sigma[b][0] * nHI + P.sigma[b][1] * nHeI + P.sigma[b][2] * nHeII;
+            const R kap = P.sigma[b][0] * nHI + P.sigma[b][1] * nHeI + P.sigma[b][2] * nHeII;
             fac[b] = 1.0 + ct * d * kap;
             Nn[b] = N[b] / fac[b];
             G0 += ct * P.sigma[b][0] * Nn[b];
@@ -147,17 +161,17 @@ __device__ inline int integrate_cell(const ChemParams& P, double Dt, double nH, 
                                   P.sigma[b][2] * nHeII * P.eheat[b][2]);
         }
 
-        double xn[5];
-        const double den = 1.0 + (G0 + r.col_HI * ne + r.rec_HII * ne) * d;
+        R xn[5];
+        const R den = 1.0 + (G0 + r.col_HI * ne + r.rec_HII * ne) * d;
         xn[0] = (x[0] + r.rec_HII * ne * d) / den;
         xn[1] = (x[1] + (G0 + r.col_HI * ne) * d) / den;
         if (hhe) {
             xn[2] = (x[2] + r.rec_HeII * ne * x[3] * d) / (1.0 + (G1 + r.col_HeI * ne) * d);
             xn[4] = (x[4] + (G2 + r.col_HeII * ne) * x[3] * d) / (1.0 + r.rec_HeIII * ne * d);
             xn[3] = 1.0 - xn[2] - xn[4];
-            if (xn[3] < 0.0) {
+            if (val(xn[3]) < 0.0) {
                 xn[3] = 0.0;
-                const double s = xn[2] + xn[4];
+                const R s = xn[2] + xn[4];
                 xn[2] = xn[2] / s;
                 xn[4] = xn[4] / s;
             }
@@ -165,16 +179,16 @@ __device__ inline int integrate_cell(const ChemParams& P, double Dt, double nH, 
             xn[2] = x[2]; xn[3] = x[3]; xn[4] = x[4];
         }
 
-        double un = u;
-        double f = 0.0;
+        R un = u;
+        R f = 0.0;
         if (!P.isothermal) {
             un = u + d * (heat - cooling_rate(P, T, nH, x, r)) / rho;
-            f = fabs(un - u) / u;
+            f = m_abs(un - u) / u;
         }
         const int ns = hhe ? 5 : 2;
-        for (int s = 0; s < ns; ++s) f = fmax(f, fabs(xn[s] - x[s]) / fmax(x[s], P.xfloor));
+        for (int s = 0; s < ns; ++s) f = m_max(f, m_abs(xn[s] - x[s]) / m_max(x[s], R(P.xfloor)));
 
-        if (f > P.fmax) {
+        if (val(f) > P.fmax) {
             d = d * (P.fs / f);
             continue;
         }
@@ -189,7 +203,7 @@ __device__ inline int integrate_cell(const ChemParams& P, double Dt, double nH, 
         u = un;
         if (last) break;
         tau = tau + d;
-        d = f > 0.0 ? d * fmin(P.fs / f, P.growth) : d * P.growth;
+        d = val(f) > 0.0 ? d * m_min(P.fs / f, R(P.growth)) : d * P.growth;
     }
     return attempts;
 }

@@ -107,3 +107,16 @@ struct rt_state {
     void prof_end(hipStream_t st);
     int prof_collect();
 };
+
+// Pieces of a subcycle on explicit buffers (U, G in the state's precision);
+// used by rt_subcycle and by the adjoint's recomputation.
+rtk::GeomView<double> rt_geo64(const rt_mesh* m);
+rtk::SellView rt_sell(const rt_mesh* m);
+void rt_step_sources(rt_state* s, void* U, double dt, hipStream_t st);
+void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStream_t st);
+void rt_step_gradient(rt_state* s, const void* U, void* G, hipStream_t st);
+void rt_step_flux(rt_state* s, const void* U, const void* G, void* Un, double dt, hipStream_t st);
+void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st);
+void rt_reset_partials(rt_state* s, hipStream_t st);
+// Folds the partials and returns the status word (synchronises the stream).
+int rt_read_status(rt_state* s, hipStream_t st, int* status);

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 
 #include "rt_chem.hpp"
+#include "rt_face.hpp"
+#include "rt_transport.hpp"
 #include "rt_kernels.hpp"
 #include "rt_types.hpp"
 
@@ -275,61 +277,6 @@ __global__ __launch_bounds__(kBlock) void k_gradient(const T* __restrict__ U, T*
 }
 
 // ---------------------------------------------------------------------------
-// Face physics (Sec. 2.3.3): admissibility of an extrapolated state,
-// M1 closure (eq. edd) with the Levermore factor, HLL flux with bounds
-// -c~, +c~.  Fluxes are in units of c~ (the caller multiplies by c~ dt / h).
-// ---------------------------------------------------------------------------
-
-template <typename T>
-__device__ inline void make_admissible(T* U, int& cN, int& cF) {
-    if (U[0] < T(0)) { U[0] = T(0); ++cN; }
-    const T F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
-    if (F2 > U[0] * U[0]) {
-        ++cF;
-        if (U[0] <= T(0)) {
-            U[1] = U[2] = U[3] = T(0);
-        } else {
-            const T s = U[0] / sqrt(F2);
-            U[1] *= s; U[2] *= s; U[3] *= s;
-        }
-    }
-}
-
-// N D n for state U = (N, Fh).
-template <typename T>
-__device__ inline void radiation_pressure_n(const T* U, T n0, T n1, T n2, T* P) {
-    const T N = U[0];
-    const T F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
-    if (N <= T(0) || F2 <= T(0)) {
-        const T third = N * T(1.0 / 3.0);
-        P[0] = third * n0; P[1] = third * n1; P[2] = third * n2;
-        return;
-    }
-    const T Fm = sqrt(F2);
-    T f = Fm / N;
-    f = f < T(1) ? f : T(1);
-    const T chi = (T(3) + T(4) * f * f) / (T(5) + T(2) * sqrt(T(4) - T(3) * f * f));
-    const T iso = T(0.5) * (T(1) - chi);
-    const T dir = T(0.5) * (T(3) * chi - T(1)) * (U[1] * n0 + U[2] * n1 + U[3] * n2) / F2;
-    P[0] = N * (iso * n0 + dir * U[1]);
-    P[1] = N * (iso * n1 + dir * U[2]);
-    P[2] = N * (iso * n2 + dir * U[3]);
-}
-
-template <typename T>
-__device__ inline void hll_flux(const T* UL, const T* UR, T n0, T n1, T n2, T* Phi) {
-    T PL[3], PR[3];
-    radiation_pressure_n(UL, n0, n1, n2, PL);
-    radiation_pressure_n(UR, n0, n1, n2, PR);
-    const T FLn = UL[1] * n0 + UL[2] * n1 + UL[3] * n2;
-    const T FRn = UR[1] * n0 + UR[2] * n1 + UR[3] * n2;
-    Phi[0] = T(0.5) * (FLn + FRn) - T(0.5) * (UR[0] - UL[0]);
-    Phi[1] = T(0.5) * (PL[0] + PR[0]) - T(0.5) * (UR[1] - UL[1]);
-    Phi[2] = T(0.5) * (PL[1] + PR[1]) - T(0.5) * (UR[2] - UL[2]);
-    Phi[3] = T(0.5) * (PL[2] + PR[2]) - T(0.5) * (UR[3] - UL[3]);
-}
-
-// ---------------------------------------------------------------------------
 // k_flux: for each face of the cell, both face states from the
 // start-of-transport fields and gradients, the HLL flux, the outflow cap
 // theta = min(1, N_up V_up / (n_faces(up) |Phi_N| dt A)); then
@@ -350,7 +297,6 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
     const int64_t blk = xcd_logical_block();
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
-    const int64_t nf = geo.nf;
     const T* Ub = U + (int64_t)(b * 4) * nc;
     const T* Gb = G + (int64_t)(b * 12) * nc;
 
@@ -366,82 +312,12 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
         }
         const T vcap_i = geo.vcap[i];
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        const int64_t slice = i / kSlice;
-        const int32_t deg = sell.deg[slice];
-        const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
-        for (int k = 0; k < deg; ++k) {
-            const int64_t e = base + (int64_t)k * kSlice;
-            const int32_t j = sell.nbr[e];
-            if (j < 0) continue;
-            const int32_t fs = sell.fsf[e];
-            const bool isL = fs >= 0;
-            const int64_t f = isL ? fs : ~fs;
-            const T A = geo.face[f];
-            const T n0 = geo.face[nf + f], n1 = geo.face[2 * nf + f], n2 = geo.face[3 * nf + f];
-            T rl[3], rr[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                rl[c] = geo.face[(4 + c) * nf + f];
-                rr[c] = geo.face[(7 + c) * nf + f];
-            }
-            T uj[4], gj[4][3];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                uj[v] = Ub[(int64_t)v * nc + j];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) gj[v][c] = Gb[(int64_t)(v * 3 + c) * nc + j];
-            }
-            const T vcap_j = geo.vcap[j];
-            // Canonical orientation: L then R, whichever lane computes it.
-            T UL[4], UR[4], sL[4], sR[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                UL[v] = isL ? ui[v] : uj[v];
-                UR[v] = isL ? uj[v] : ui[v];
-                const T gl0 = isL ? gi[v][0] : gj[v][0], gl1 = isL ? gi[v][1] : gj[v][1], gl2 = isL ? gi[v][2] : gj[v][2];
-                const T gr0 = isL ? gj[v][0] : gi[v][0], gr1 = isL ? gj[v][1] : gi[v][1], gr2 = isL ? gj[v][2] : gi[v][2];
-                sL[v] = UL[v] + (gl0 * rl[0] + gl1 * rl[1] + gl2 * rl[2]);
-                sR[v] = UR[v] + (gr0 * rr[0] + gr1 * rr[1] + gr2 * rr[2]);
-            }
-            int aN = 0, aF = 0;
-            make_admissible(sL, aN, aF);
-            make_admissible(sR, aN, aF);
-            T Phi[4];
-            hll_flux(sL, sR, n0, n1, n2, Phi);
-            bool capped = false;
-            if (Phi[0] != T(0)) {
-                const bool upL = Phi[0] > T(0);
-                const T Nup = upL ? UL[0] : UR[0];
-                const T vc = upL ? (isL ? vcap_i : vcap_j) : (isL ? vcap_j : vcap_i);
-                const T cap = Nup * vc / (fabs(Phi[0]) * cdt * A);
-                if (cap < T(1)) {
-                    capped = true;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) Phi[v] = cap * Phi[v];
-                }
-            }
-            if (isL) {
-                cAdmN += aN; cAdmF += aF; cCap += capped ? 1 : 0;
-            }
-            const T sA = isL ? A : -A;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] += (double)(sA * Phi[v]);
-        }
+        cell_flux_sum<T>(i, nc, Ub, Gb, geo, sell, cdt, ui, gi, vcap_i, acc, cAdmN, cAdmF, cCap);
         const double coef = (double)cdt / (double)geo.vol[i];
         double un[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) un[v] = (double)ui[v] - coef * acc[v];
-        if (un[0] < 0.0) { un[0] = 0.0; ++cGN; }
-        const double F2 = un[1] * un[1] + un[2] * un[2] + un[3] * un[3];
-        if (F2 > un[0] * un[0]) {
-            ++cGF;
-            if (un[0] <= 0.0) {
-                un[1] = un[2] = un[3] = 0.0;
-            } else {
-                const double s = un[0] / sqrt(F2);
-                un[1] *= s; un[2] *= s; un[3] *= s;
-            }
-        }
+        update_guards<double>(un, cGN, cGF);
         T* Ob = Unew + (int64_t)(b * 4) * nc;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {

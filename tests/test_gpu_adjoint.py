@@ -1,0 +1,161 @@
+"""Adjoint of the subcycle (rt_subcycle_adjoint and the autograd Function)
+against the oracle's forward-mode derivative and against central finite
+differences of the GPU forward run (h = 1e-6, 1e-5 relative)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rtgen
+from paper_2404_17630_amd import rt
+from paper_2404_17630_amd.autograd import Problem, RTSubcycles
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+def adjoint(problem, log_lum, log_nH, w):
+    """dL/dlog_lum, dL/dlog_nH for L = w . x_HI (via autograd)."""
+    a = torch.tensor(log_lum, dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.tensor(log_nH, dtype=torch.float64, device="cuda", requires_grad=True)
+    x = RTSubcycles.apply(a, b, problem)
+    loss = (torch.tensor(w, device="cuda") * x).sum()
+    loss.backward()
+    return a.grad.cpu().numpy(), b.grad.cpu().numpy(), x.detach().cpu().numpy()
+
+
+def forward_xhi(problem, log_lum, log_nH):
+    s = problem.state(log_lum, log_nH)
+    s.subcycle(problem.n_subcycles)
+    x = s.get(rt.RT_FIELD_SPECIES)[0]
+    s.close()
+    return x
+
+
+def small_cfg(n_sub=6):
+    return rtgen.cosmological(0, 1.0, 1.0, 4, 0.01, n_sub, 5, dims=(12, 10, 9), name="adj_small")
+
+
+def test_adjoint_matches_oracle_forward_derivative():
+    cfg = small_cfg()
+    pb = Problem(cfg, checkpoint_every=4)
+    nc = cfg["mesh"]["n_cells"]
+    rng = np.random.default_rng(1)
+    w = rng.normal(size=nc)
+    lq0, ln0 = pb.log_lum0.copy(), np.log(cfg["state"]["n_H"])
+    gq, gn, _ = adjoint(pb, lq0, ln0, w)
+    # oracle directional derivatives along e_k of each source and two density directions
+    dirs_q = np.zeros((6, 4))
+    dirs_n = np.zeros((6, nc))
+    for k in range(4):
+        dirs_q[k, k] = 1.0
+    dirs_n[4] = rng.normal(size=nc)
+    dirs_n[5] = rng.normal(size=nc)
+    jv = oracle.run_jvp(cfg, dirs_q, dirs_n)["dxHI"]
+    for d in range(6):
+        ref = w @ jv[d]
+        got = gq @ dirs_q[d] + gn @ dirs_n[d]
+        say(f"direction {d}: adjoint {got:.12e} oracle {ref:.12e}")
+        assert got == pytest.approx(ref, rel=1e-8, abs=1e-14 * np.abs(jv[d]).max())
+
+
+def test_adjoint_matches_central_differences():
+    cfg = small_cfg(n_sub=5)
+    pb = Problem(cfg, checkpoint_every=2)
+    nc = cfg["mesh"]["n_cells"]
+    rng = np.random.default_rng(2)
+    w = rng.normal(size=nc)
+    lq0, ln0 = pb.log_lum0.copy(), np.log(cfg["state"]["n_H"])
+    gq, gn, _ = adjoint(pb, lq0, ln0, w)
+    h = 1e-6
+    for k in range(4):
+        e = np.zeros(4)
+        e[k] = h
+        fd = (w @ forward_xhi(pb, lq0 + e, ln0) - w @ forward_xhi(pb, lq0 - e, ln0)) / (2 * h)
+        say(f"source {k}: adjoint {gq[k]:.10e} fd {fd:.10e}")
+        assert gq[k] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(gq).max())
+    v = rng.normal(size=nc)
+    fd = (w @ forward_xhi(pb, lq0, ln0 + h * v) - w @ forward_xhi(pb, lq0, ln0 - h * v)) / (2 * h)
+    say(f"density direction: adjoint {gn @ v:.10e} fd {fd:.10e}")
+    assert gn @ v == pytest.approx(fd, rel=1e-5)
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient():
+    cfg = small_cfg(n_sub=7)
+    nc = cfg["mesh"]["n_cells"]
+    w = np.random.default_rng(3).normal(size=nc)
+    res = []
+    for every in (1, 3, 7, 100):
+        pb = Problem(cfg, checkpoint_every=every)
+        res.append(adjoint(pb, pb.log_lum0.copy(), np.log(cfg["state"]["n_H"]), w))
+    for r in res[1:]:
+        assert np.array_equal(r[0], res[0][0])
+        assert np.array_equal(r[1], res[0][1])
+
+
+def test_adjoint_errors():
+    cfg = small_cfg(n_sub=2)
+    m = rt.Mesh(cfg["mesh"])
+    s = rt.State.from_config(m, cfg, precision=rt.RT_MIXED)
+    nc = cfg["mesh"]["n_cells"]
+    with pytest.raises(rt.RtError) as e:
+        rt.rt_subcycle_adjoint(s.h, 2, 1, np.zeros(nc), np.zeros(4), np.zeros(nc))
+    assert e.value.code == rt.RT_ESTATE
+    s.close()
+    s = rt.State.from_config(m, cfg)
+    with pytest.raises(rt.RtError) as e:
+        rt.rt_subcycle_adjoint(s.h, 2, 0, np.zeros(nc), np.zeros(4), np.zeros(nc))
+    assert e.value.code == rt.RT_EINVAL
+    # the initial state is not modified
+    before = s.fields()
+    out_q, out_n = np.zeros(4), np.zeros(nc)
+    rt.rt_subcycle_adjoint(s.h, 2, 1, np.ones(nc), out_q, out_n)
+    after = s.fields()
+    for k in ("N", "F", "species", "T"):
+        assert np.array_equal(before[k], after[k])
+    assert np.any(out_q != 0) and np.all(np.isfinite(out_n))
+    s.close()
+    m.close()
+
+
+def test_full_size_adjoint_262k():
+    """The adjoint workload at full size: 64^3 cells, 64 sources, 50 FP64
+    subcycles with checkpoints every 10, loss sum (x_HI - target)^2 with the
+    target from luminosities perturbed by a seeded +-20%.  Gradients against
+    central differences (h = 1e-6) on all 64 log-luminosities and on random
+    density directions, 1e-5 relative."""
+    say("adjoint_262k: generating")
+    cfg = rtgen.adjoint_262k()
+    pb = Problem(cfg, checkpoint_every=10)
+    lq0 = pb.log_lum0.copy()
+    ln0 = np.log(cfg["state"]["n_H"])
+    say("adjoint_262k: target run")
+    target = forward_xhi(pb, lq0 + np.log(cfg["meta"]["target_rate_factor"]), ln0)
+    x0 = forward_xhi(pb, lq0, ln0)
+    w = 2.0 * (x0 - target)           # dL/dx for L = sum (x - target)^2
+    say("adjoint_262k: adjoint")
+    gq, gn, xa = adjoint(pb, lq0, ln0, w)
+    assert np.array_equal(xa, x0)
+    h = 1e-6
+
+    def loss(lq, ln):
+        return float(np.sum((forward_xhi(pb, lq, ln) - target) ** 2))
+
+    bad = []
+    for k in range(64):
+        e = np.zeros(64)
+        e[k] = h
+        fd = (loss(lq0 + e, ln0) - loss(lq0 - e, ln0)) / (2 * h)
+        ok = abs(gq[k] - fd) <= 1e-5 * max(abs(fd), 1e-6 * np.abs(gq).max())
+        if not ok:
+            bad.append((k, gq[k], fd))
+    say(f"adjoint_262k: {64 - len(bad)}/64 source gradients within 1e-5 of central differences")
+    for b in bad:
+        say("  mismatch", b)
+    assert not bad
+    rng = np.random.default_rng(4)
+    for r in range(4):
+        v = rng.normal(size=ln0.size)
+        fd = (loss(lq0, ln0 + h * v) - loss(lq0, ln0 - h * v)) / (2 * h)
+        say(f"adjoint_262k: density direction {r}: adjoint {gn @ v:.10e} fd {fd:.10e}")
+        assert gn @ v == pytest.approx(fd, rel=1e-5)

@@ -1,6 +1,8 @@
 """GPU parity of the FP64 path (through the C ABI) against the CPU oracle:
-1e-10 relative per field and bin (with a floor of 1e-10 of the field's
-maximum), plus determinism, conservation and the documented error paths."""
+1e-10 relative per element, field and bin (scale: the value itself, floored
+at 1e-6 of the largest value in its stencil and at 1e-10 of the field's
+maximum, see tests/gpu_common.field_errors), plus determinism, conservation
+and the documented error paths."""
 import numpy as np
 import pytest
 
@@ -15,7 +17,7 @@ TOL = 1e-10
 
 
 def assert_parity(cfg, gpu, ref, tol=TOL):
-    errs = field_errors(gpu, ref, cfg["params"]["c_reduced"])
+    errs = field_errors(gpu, ref, cfg["params"]["c_reduced"], cfg["mesh"]["face_cells"])
     worst = max(errs, key=errs.get)
     say(cfg["name"], "worst", worst, f"{errs[worst]:.3e}")
     bad = {k: v for k, v in errs.items() if not v <= tol}
