@@ -30,7 +30,7 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ("k_sources", "k_chem", "k_gradient", "k_flux", "k_reduce")
+KERNELS = ("k_sources", "k_chem", "k_facestate", "k_flux", "k_reduce")
 TRAFFIC_FILE = ROOT / "profiles" / "traffic.json"
 
 
@@ -39,16 +39,21 @@ def log(*a):
 
 
 def algorithmic_bytes(kernel: str, nc: int, nb: int, nf: int, n_sides: int, n_src: int, p: int, g: int) -> float:
-    """Compulsory HBM bytes of one launch: each array element the kernel must
-    read or write, counted once (neighbour gathers and per-bin geometry
-    re-reads assumed to hit cache).  p = bytes per transport value, g = bytes
-    per geometry value, indices 4 bytes."""
-    idx = 8 * n_sides                                   # neighbour + signed face index per face side
-    if kernel == "k_gradient":
-        return nc * nb * (4 + 12) * p + nc * 6 * g + nf * 7 * g + idx
+    """Compulsory HBM bytes of one launch: every array element the kernel must
+    read or write, counted once (a neighbour's record gathered by several
+    cells, and geometry re-read for each bin, are counted once).
+    p = bytes per transport value, g = bytes per geometry value; indices are
+    4 bytes.  Face sides per cell: n_sides / nc."""
+    if kernel == "k_facestate":
+        # fields (4) in, one 4-value face state per face side out;
+        # cell record (M^-1, V, V/n_f), face record (12 values), neighbour + face index
+        return nb * (4 * nc + 4 * n_sides) * p + nc * 8 * g + nf * 12 * g + n_sides * 8
     if kernel == "k_flux":
-        return nc * nb * (4 + 12 + 4) * p + nc * 2 * g + nf * 10 * g + idx
+        # fields in and out, face states of every face side in; cell volume,
+        # face record, neighbour + face + opposite-side index
+        return nb * (8 * nc + 4 * n_sides) * p + nc * g + nf * 12 * g + n_sides * 12
     if kernel == "k_chem":
+        # fields of all bins in and out, 5 fractions and u in and out, n_H in
         return nc * (8 * nb * p + 2 * 5 * 8 + 2 * 8 + 8)
     if kernel == "k_sources":
         return n_src * (nb * 8 + 16) + 2 * n_src * nb * p
@@ -103,6 +108,9 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=256, help="cells per side (256 = the throughput workload)")
     ap.add_argument("--no-extras", action="store_true", help="time only the mixed Hilbert-order run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
+                    help="first copy a GIB-sized device buffer three times (a plain copy kernel of known size, "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the design of one is in "
@@ -119,6 +127,15 @@ def main() -> int:
         return 2
     rt.lib()
     torch.cuda.set_device(0)
+    if args.calibrate_copy > 0:
+        n = int(args.calibrate_copy * (1 << 30)) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {n * 4} bytes (read {n * 4}, write {n * 4} each)")
+        del src, dst
     n_src = max(1, int(round(4096 * (args.n / 256) ** 3)))
     log(f"generating throughput workload {args.n}^3, {n_src} sources")
     cfg = rtgen.throughput_16m(n=args.n, n_src=n_src, n_sub=args.steps)

@@ -49,27 +49,20 @@ constexpr int kFaceDirs = 10;   // sL[4], sR[4], N_L, N_R
 // k_adj_guard: lambda_pre = J_guard^T lambda_new, with the pre-guard update
 // recomputed from the transport inputs.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_adj_guard(const double* __restrict__ U, const double* __restrict__ G,
+__global__ __launch_bounds__(kBlock) void k_adj_guard(const double* __restrict__ U, const double* __restrict__ FV,
                                                       const double* __restrict__ lam_new, double* __restrict__ lam_pre,
-                                                      int64_t nc, int nb, GeomView<double> geo, SellView sell,
-                                                      double cdt) {
+                                                      int64_t nc, int nb, int64_t n_entries, GeomView<double> geo,
+                                                      SellView sell, double cdt) {
     const int64_t blk = xcd_logical_block();
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
     if (i >= nc) return;
-    const double* Ub = U + (int64_t)(b * 4) * nc;
-    const double* Gb = G + (int64_t)(b * 12) * nc;
-    double ui[4], gi[4][3];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        ui[v] = Ub[(int64_t)v * nc + i];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) gi[v][c] = Gb[(int64_t)(v * 3 + c) * nc + i];
-    }
+    double ui[4];
+    load4(U + urec(b, nc, i), ui);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int c0 = 0, c1 = 0, c2 = 0;
-    cell_flux_sum<double>(i, nc, Ub, Gb, geo, sell, cdt, ui, gi, geo.vcap[i], acc, c0, c1, c2);
-    const double coef = cdt / geo.vol[i];
+    cell_flux_sum<double, double>(i, b, nc, n_entries, U, FV, geo, sell, cdt, ui[0], acc, c0, c1, c2);
+    const double coef = cdt / geo.cell[i * kCellRec + 6];
     Dual<4> un[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -106,20 +99,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_flux(const double* __restrict__ 
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
     if (i >= nc) return;
-    const int64_t nf = geo.nf;
-    const double* Ub = U + (int64_t)(b * 4) * nc;
     const double* Gb = G + (int64_t)(b * 12) * nc;
     const double* Lp = lam_pre + (int64_t)(b * 4) * nc;
     double ui[4], gi[4][3], li[4];
+    load4(U + urec(b, nc, i), ui);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        ui[v] = Ub[(int64_t)v * nc + i];
         li[v] = Lp[(int64_t)v * nc + i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) gi[v][c] = Gb[(int64_t)(v * 3 + c) * nc + i];
     }
-    const double vcap_i = geo.vcap[i];
-    const double coef_i = cdt / geo.vol[i];
+    const double coef_i = cdt / geo.cell[i * kCellRec + 6];
     double ld[4] = {li[0], li[1], li[2], li[3]};
     double lg[4][3];
 #pragma unroll
@@ -135,24 +125,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_flux(const double* __restrict__ 
         const int32_t fs = sell.fsf[e];
         const bool isL = fs >= 0;
         const int64_t f = isL ? fs : ~fs;
-        const double A = geo.face[f];
-        const double n0 = geo.face[nf + f], n1 = geo.face[2 * nf + f], n2 = geo.face[3 * nf + f];
-        double rl[3], rr[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            rl[c] = geo.face[(4 + c) * nf + f];
-            rr[c] = geo.face[(7 + c) * nf + f];
-        }
+        const FaceRec<double> fr = load_face(geo.face, f);
+        const double A = fr.A;
+        const double n0 = fr.n0, n1 = fr.n1, n2 = fr.n2;
+        const double rl[3] = {fr.rl0, fr.rl1, fr.rl2}, rr[3] = {fr.rr0, fr.rr1, fr.rr2};
         double uj[4], gj[4][3], lj[4];
+        load4(U + urec(b, nc, j), uj);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            uj[v] = Ub[(int64_t)v * nc + j];
             lj[v] = Lp[(int64_t)v * nc + j];
 #pragma unroll
             for (int c = 0; c < 3; ++c) gj[v][c] = Gb[(int64_t)(v * 3 + c) * nc + j];
         }
-        const double vcap_j = geo.vcap[j];
-        const double coef_j = cdt / geo.vol[j];
+        const double coef_j = cdt / geo.cell[(int64_t)j * kCellRec + 6];
         const double coefL = isL ? coef_i : coef_j, coefR = isL ? coef_j : coef_i;
         Dual<kFaceDirs> sL[4], sR[4];
         double mu[4];
@@ -174,8 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_flux(const double* __restrict__ 
         NR.d[9] = 1.0;
         int aN = 0, aF = 0;
         Dual<kFaceDirs> Phi[4];
-        const double vcL = isL ? vcap_i : vcap_j, vcR = isL ? vcap_j : vcap_i;
-        face_flux<Dual<kFaceDirs>, double>(sL, sR, NL, NR, vcL, vcR, n0, n1, n2, A, cdt, Phi, aN, aF);
+        face_flux<Dual<kFaceDirs>, double>(sL, sR, NL, NR, fr.vcL, fr.vcR, n0, n1, n2, A, cdt, Phi, aN, aF);
         const int off = isL ? 0 : 4;
         const double* r = isL ? rl : rr;
 #pragma unroll
@@ -218,16 +202,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
     if (i >= nc) return;
-    const int64_t nf = geo.nf;
-    const double* Ub = U + (int64_t)(b * 4) * nc;
     const double* Lg = lam_g + (int64_t)(b * 12) * nc;
     const int64_t slice = i / kSlice;
     const int32_t deg = sell.deg[slice];
     const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
-    const double mxx = geo.minv[i], myy = geo.minv[nc + i], mzz = geo.minv[2 * nc + i];
-    const double mxy = geo.minv[3 * nc + i], mxz = geo.minv[4 * nc + i], myz = geo.minv[5 * nc + i];
+    const double* cr = geo.cell + i * kCellRec;
+    const double mxx = cr[0], myy = cr[1], mzz = cr[2], mxy = cr[3], mxz = cr[4], myz = cr[5];
     for (int v = 0; v < 4; ++v) {
-        Dual<KG> phi_i(Ub[(int64_t)v * nc + i]);
+        Dual<KG> phi_i(U[urec(b, nc, i) + v]);
         phi_i.d[0] = 1.0;
         Dual<KG> bs[3], umax = phi_i, umin = phi_i;
         for (int k = 0; k < deg; ++k) {
@@ -236,15 +218,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
             if (j < 0) continue;
             const int32_t fs = sell.fsf[e];
             const bool isL = fs >= 0;
-            const int64_t f = isL ? fs : ~fs;
-            const double A = geo.face[f];
-            const double rl0 = geo.face[4 * nf + f], rl1 = geo.face[5 * nf + f], rl2 = geo.face[6 * nf + f];
-            const double rr0 = geo.face[7 * nf + f], rr1 = geo.face[8 * nf + f], rr2 = geo.face[9 * nf + f];
-            const double d0 = isL ? rl0 - rr0 : rr0 - rl0;
-            const double d1 = isL ? rl1 - rr1 : rr1 - rl1;
-            const double d2 = isL ? rl2 - rr2 : rr2 - rl2;
-            const double s = A / (d0 * d0 + d1 * d1 + d2 * d2);
-            Dual<KG> uj(Ub[(int64_t)v * nc + j]);
+            const FaceRec<double> fr = load_face(geo.face, isL ? fs : ~fs);
+            const double d0 = isL ? fr.rl0 - fr.rr0 : fr.rr0 - fr.rl0;
+            const double d1 = isL ? fr.rl1 - fr.rr1 : fr.rr1 - fr.rl1;
+            const double d2 = isL ? fr.rl2 - fr.rr2 : fr.rr2 - fr.rl2;
+            const double s = fr.A / (d0 * d0 + d1 * d1 + d2 * d2);
+            Dual<KG> uj(U[urec(b, nc, j) + v]);
             uj.d[1 + k] = 1.0;
             const Dual<KG> dphi = uj - phi_i;
             bs[0] += (d0 * s) * dphi;
@@ -264,9 +243,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
                 if (sell.nbr[e] < 0) continue;
                 const int32_t fs = sell.fsf[e];
                 const bool isL = fs >= 0;
-                const int64_t f = isL ? fs : ~fs;
-                const int64_t o = isL ? 4 * nf : 7 * nf;
-                const double r0 = geo.face[o + f], r1 = geo.face[o + nf + f], r2 = geo.face[o + 2 * nf + f];
+                const FaceRec<double> fr = load_face(geo.face, isL ? fs : ~fs);
+                const double r0 = isL ? fr.rl0 : fr.rr0, r1 = isL ? fr.rl1 : fr.rr1, r2 = isL ? fr.rl2 : fr.rr2;
                 const Dual<KG> delta = g[0] * r0 + g[1] * r1 + g[2] * r2;
                 Dual<KG> psi(1.0);
                 if (val(delta) > 0.0) psi = (umax - phi_i) / delta;
@@ -352,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_chem(const double* __restrict__ 
     Dual<K> N[NB], Fh[NB][3], x[5], u, nHd;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        N[b] = Dual<K>(Upre[(int64_t)(b * 4) * nc + i]);
+        N[b] = Dual<K>(Upre[urec(b, nc, i)]);
         N[b].d[6 + b] = 1.0;
         Fh[b][0] = Dual<K>(1.0);
         Fh[b][1] = Dual<K>(0.0);
@@ -391,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_chem(const double* __restrict__ 
         const double lN = lam_U[(int64_t)(b * 4) * nc + i];
         double lF = 0.0;
         for (int c = 0; c < 3; ++c)
-            lF += lam_U[(int64_t)(b * 4 + 1 + c) * nc + i] * Upre[(int64_t)(b * 4 + 1 + c) * nc + i];
+            lF += lam_U[(int64_t)(b * 4 + 1 + c) * nc + i] * Upre[urec(b, nc, i) + 1 + c];
 #pragma unroll
         for (int k = 0; k < K; ++k) lin[k] += lN * N[b].d[k] + lF * Fh[b][0].d[k];
     }
@@ -505,12 +483,12 @@ extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int
             (rc = mid_U[j].alloc(ub)))
             return rc;
     // Adjoint buffers.
-    const int64_t n_entries = m->sptr.back();
-    DevMem lU, lX, lu, lnn, lq, lpre, ldir, lg, cself, cslot, fail, d_cell, d_rate, d_vp, d_dL;
+    const int64_t n_entries = m->n_entries;
+    DevMem lU, lX, lu, lnn, lq, lpre, ldir, lg, cself, cslot, fail, d_cell, d_rate, d_vp, d_dL, G;
     if ((rc = lU.alloc(ub)) || (rc = lX.alloc(5 * nc * 8)) || (rc = lu.alloc(nc * 8)) || (rc = lnn.alloc(nc * 8)) ||
         (rc = lq.alloc(std::max<int64_t>(w->n_src, 1) * 8)) || (rc = lpre.alloc(ub)) || (rc = ldir.alloc(ub)) ||
         (rc = lg.alloc(3 * ub)) || (rc = cself.alloc(ub)) || (rc = cslot.alloc((size_t)nb * 4 * n_entries * 8)) ||
-        (rc = fail.alloc(grid1(nc, kBlock) * 4)))
+        (rc = fail.alloc(grid1(nc, kBlock) * 4)) || (rc = G.alloc(3 * ub)))
         return rc;
     {
         std::vector<int32_t> cell(w->n_src);
@@ -580,17 +558,18 @@ extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int
             if ((rc = save(pre_U[j], pre_X[j], pre_u[j]))) return rc;
             rt_step_chem(w, U, (double*)w->X.ptr, (double*)w->Ue.ptr, dt, st);
             RT_HIP_A(hipMemcpyAsync(mid_U[j].ptr, U, ub, hipMemcpyDeviceToDevice, st));
-            rt_step_gradient(w, U, w->G.ptr, st);
-            rt_step_flux(w, U, w->G.ptr, Un, dt, st);
+            rt_step_facestate(w, U, w->FV.ptr, st);
+            rt_step_flux(w, U, w->FV.ptr, Un, dt, st);
             w->cur ^= 1;
         }
         // Reverse sweep over the segment.
         for (int j = len - 1; j >= 0; --j) {
             const double* Um = (const double*)mid_U[j].ptr;
-            rt_step_gradient(w, Um, w->G.ptr, st);
-            hipLaunchKernelGGL(k_adj_guard, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, (const double*)w->G.ptr,
-                               (const double*)lU.ptr, (double*)lpre.ptr, nc, nb, geo, sell, cdt);
-            hipLaunchKernelGGL(k_adj_flux, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, (const double*)w->G.ptr,
+            rt_step_facestate(w, Um, w->FV.ptr, st);
+            launch_gradient(Um, (double*)G.ptr, nc, nb, geo, sell, w->params.use_limiter, st);
+            hipLaunchKernelGGL(k_adj_guard, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, (const double*)w->FV.ptr,
+                               (const double*)lU.ptr, (double*)lpre.ptr, nc, nb, n_entries, geo, sell, cdt);
+            hipLaunchKernelGGL(k_adj_flux, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, (const double*)G.ptr,
                                (const double*)lpre.ptr, (double*)ldir.ptr, (double*)lg.ptr, nc, nb, geo, sell, cdt);
             if (m->max_deg <= 6)
                 hipLaunchKernelGGL(k_adj_grad<7>, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, (const double*)lg.ptr,

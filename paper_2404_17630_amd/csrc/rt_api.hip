@@ -165,16 +165,12 @@ static double min_image(double x, double box) {
 
 int rt_mesh::build_float_geometry() {
     if (geo32_ready) return RT_OK;
-    std::vector<float> f(face.size()), mi(minv.size()), v(vol.size()), vc(vcap.size());
+    std::vector<float> f(face.size()), c(cell.size());
     for (size_t q = 0; q < face.size(); ++q) f[q] = (float)face[q];
-    for (size_t q = 0; q < minv.size(); ++q) mi[q] = (float)minv[q];
-    for (size_t q = 0; q < vol.size(); ++q) v[q] = (float)vol[q];
-    for (size_t q = 0; q < vcap.size(); ++q) vc[q] = (float)vcap[q];
+    for (size_t q = 0; q < cell.size(); ++q) c[q] = (float)cell[q];
     int rc;
     if ((rc = d_face32.upload(f.data(), f.size() * 4))) return rc;
-    if ((rc = d_minv32.upload(mi.data(), mi.size() * 4))) return rc;
-    if ((rc = d_vol32.upload(v.data(), v.size() * 4))) return rc;
-    if ((rc = d_vcap32.upload(vc.data(), vc.size() * 4))) return rc;
+    if ((rc = d_cell32.upload(c.data(), c.size() * 4))) return rc;
     geo32_ready = true;
     return RT_OK;
 }
@@ -233,15 +229,17 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
     m->h_ref = h;
     const double h2 = h * h, h3 = h2 * h;
 
-    // Per-face geometry in units of h: A, n, r_Lf, r_Rf (minimum image).
-    m->face.assign(10 * nf, 0.0);
+    // Per-face geometry in units of h: A, n, r_Lf, r_Rf (minimum image); the
+    // cells' V / n_faces are filled in below.
+    m->face.assign((size_t)kFaceRec * nf, 0.0);
     for (int64_t f = 0; f < nf; ++f) {
         int64_t L = FC[f], R = FC[nf + f];
-        m->face[f] = A[f] / h2;
+        double* rec = &m->face[(size_t)f * kFaceRec];
+        rec[0] = A[f] / h2;
         for (int k = 0; k < 3; ++k) {
-            m->face[(1 + k) * nf + f] = Nrm[k * nf + f];
-            m->face[(4 + k) * nf + f] = min_image(Xf[k * nf + f] - S[k * nc + L], box[k]) / h;
-            m->face[(7 + k) * nf + f] = min_image(Xf[k * nf + f] - S[k * nc + R], box[k]) / h;
+            rec[1 + k] = Nrm[k * nf + f];
+            rec[4 + k] = min_image(Xf[k * nf + f] - S[k * nc + L], box[k]) / h;
+            rec[7 + k] = min_image(Xf[k * nf + f] - S[k * nc + R], box[k]) / h;
         }
     }
     // Face sides per cell in face-index order (counting sort keeps the order).
@@ -260,27 +258,23 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
     }
     // Geometry matrix M_i = sum A u u^T (u = unit separation through the face),
     // its inverse by the adjugate, and a Frobenius condition-number check.
-    m->minv.assign(6 * nc, 0.0);
-    m->vol.resize(nc);
-    m->vcap.resize(nc);
+    m->cell.assign((size_t)kCellRec * nc, 0.0);
     m->vphys = V;
     for (int64_t i = 0; i < nc; ++i) {
         double M[6] = {0, 0, 0, 0, 0, 0};   // xx yy zz xy xz yz
         for (int64_t e = off[i]; e < off[i + 1]; ++e) {
             const int64_t f = side_face[e];
             const bool isL = side_isL[e];
+            const double* rec = &m->face[(size_t)f * kFaceRec];
             double d[3];
-            for (int k = 0; k < 3; ++k) {
-                const double rl = m->face[(4 + k) * nf + f], rr = m->face[(7 + k) * nf + f];
-                d[k] = isL ? rl - rr : rr - rl;
-            }
+            for (int k = 0; k < 3; ++k) d[k] = isL ? rec[4 + k] - rec[7 + k] : rec[7 + k] - rec[4 + k];
             const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             if (!(dd > 0)) {
                 delete m;
                 return rt_fail(RT_EMESH, "cell %lld: coincident neighbour centre through face %lld", (long long)i,
                                (long long)f);
             }
-            const double Af = m->face[f] / dd;
+            const double Af = rec[0] / dd;
             M[0] += Af * d[0] * d[0]; M[1] += Af * d[1] * d[1]; M[2] += Af * d[2] * d[2];
             M[3] += Af * d[0] * d[1]; M[4] += Af * d[0] * d[2]; M[5] += Af * d[1] * d[2];
         }
@@ -301,9 +295,14 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
             delete m;
             return rt_fail(RT_EMESH, "cell %lld: geometry matrix condition number %g", (long long)i, cond);
         }
-        for (int q = 0; q < 6; ++q) m->minv[q * nc + i] = inv[q];
-        m->vol[i] = V[i] / h3;
-        m->vcap[i] = m->vol[i] / (double)deg[i];
+        double* rec = &m->cell[(size_t)i * kCellRec];
+        for (int q = 0; q < 6; ++q) rec[q] = inv[q];
+        rec[6] = V[i] / h3;
+        rec[7] = rec[6] / (double)deg[i];
+    }
+    for (int64_t f = 0; f < nf; ++f) {
+        m->face[(size_t)f * kFaceRec + 10] = m->cell[(size_t)FC[f] * kCellRec + 7];
+        m->face[(size_t)f * kFaceRec + 11] = m->cell[(size_t)FC[nf + f] * kCellRec + 7];
     }
     // Sliced ELL with 64-cell slices.
     const int64_t ns = (nc + kSlice - 1) / kSlice;
@@ -320,8 +319,11 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
         }
     }
     const int64_t ne = m->sptr[ns];
+    m->n_entries = ne;
     m->nbr.assign(ne, -1);
     m->fsf.assign(ne, 0);
+    m->opp.assign(ne, 0);
+    std::vector<int64_t> entry_of_side(2 * nf);   // CSR face side -> sliced-ELL entry
     for (int64_t i = 0; i < nc; ++i) {
         const int64_t s = i / kSlice, lane = i % kSlice;
         for (int64_t k = 0; k < deg[i]; ++k) {
@@ -329,6 +331,17 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
             const int64_t src = off[i] + k;
             m->nbr[e] = side_nbr[src];
             m->fsf[e] = side_isL[src] ? side_face[src] : ~side_face[src];
+            entry_of_side[src] = e;
+        }
+    }
+    {
+        // the two sides of each face point at each other
+        std::vector<int64_t> side_of_face(2 * nf, -1);
+        for (int64_t src = 0; src < 2 * nf; ++src) side_of_face[2 * (int64_t)side_face[src] + (side_isL[src] ? 0 : 1)] = src;
+        for (int64_t f = 0; f < nf; ++f) {
+            const int64_t eL = entry_of_side[side_of_face[2 * f]], eR = entry_of_side[side_of_face[2 * f + 1]];
+            m->opp[eL] = (int32_t)eR;
+            m->opp[eR] = (int32_t)eL;
         }
     }
     m->max_deg = *std::max_element(deg.begin(), deg.end());
@@ -346,12 +359,11 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
     DeviceGuard dg(device);
 
     if ((rc = m->d_face64.upload(m->face.data(), m->face.size() * 8)) ||
-        (rc = m->d_minv64.upload(m->minv.data(), m->minv.size() * 8)) ||
-        (rc = m->d_vol64.upload(m->vol.data(), m->vol.size() * 8)) ||
-        (rc = m->d_vcap64.upload(m->vcap.data(), m->vcap.size() * 8)) ||
+        (rc = m->d_cell64.upload(m->cell.data(), m->cell.size() * 8)) ||
         (rc = m->d_vphys.upload(m->vphys.data(), m->vphys.size() * 8)) ||
         (rc = m->d_nbr.upload(m->nbr.data(), m->nbr.size() * 4)) ||
         (rc = m->d_fsf.upload(m->fsf.data(), m->fsf.size() * 4)) ||
+        (rc = m->d_opp.upload(m->opp.data(), m->opp.size() * 4)) ||
         (rc = m->d_sptr.upload(m->sptr.data(), m->sptr.size() * 4)) ||
         (rc = m->d_sdeg.upload(m->sdeg.data(), m->sdeg.size() * 4))) {
         delete m;
@@ -456,8 +468,8 @@ int rt_state::alloc_buffers() {
     const size_t t = tbytes();
     int rc;
     if ((rc = U[0].alloc((size_t)nb * 4 * nc * t)) || (rc = U[1].alloc((size_t)nb * 4 * nc * t)) ||
-        (rc = G.alloc((size_t)nb * 12 * nc * t)) || (rc = X.alloc(5 * nc * 8)) || (rc = Ue.alloc(nc * 8)) ||
-        (rc = nH.alloc(nc * 8)))
+        (rc = FV.alloc((size_t)nb * 4 * mesh->n_entries * t)) || (rc = X.alloc(5 * nc * 8)) ||
+        (rc = Ue.alloc(nc * 8)) || (rc = nH.alloc(nc * 8)))
         return rc;
     n_fblk = transport_blocks(nc, nb);
     n_cblk = chem_blocks(nc);
@@ -581,15 +593,15 @@ extern "C" int rt_state_create(const rt_mesh* mesh_c, const rt_params* params, i
         rt_state_destroy(s);
         return rc;
     }
-    // Fields in the internal layout U[b][4][nc] = (N, F/c~) / scale.
+    // Fields in the internal layout U[b][nc][4] = (N, F/c~) / scale.
     {
         std::vector<double> U((size_t)nb * 4 * nc);
         for (int b = 0; b < nb; ++b) {
             const double inv = 1.0 / s->scale[b];
             for (int64_t i = 0; i < nc; ++i) {
-                U[((size_t)b * 4) * nc + i] = hN[(size_t)b * nc + i] * inv;
+                U[urec(b, nc, i)] = hN[(size_t)b * nc + i] * inv;
                 for (int k = 0; k < 3; ++k)
-                    U[((size_t)b * 4 + 1 + k) * nc + i] = hF[((size_t)b * 3 + k) * nc + i] / params->c_reduced * inv;
+                    U[urec(b, nc, i) + 1 + k] = hF[((size_t)b * 3 + k) * nc + i] / params->c_reduced * inv;
             }
         }
         hipError_t e;
@@ -720,11 +732,11 @@ template <typename T>
 static GeomView<T> geom_view(const rt_mesh* m) {
     GeomView<T> geo;
     if (sizeof(T) == 8) {
-        geo.face = (const T*)m->d_face64.ptr; geo.minv = (const T*)m->d_minv64.ptr;
-        geo.vol = (const T*)m->d_vol64.ptr; geo.vcap = (const T*)m->d_vcap64.ptr;
+        geo.face = (const T*)m->d_face64.ptr;
+        geo.cell = (const T*)m->d_cell64.ptr;
     } else {
-        geo.face = (const T*)m->d_face32.ptr; geo.minv = (const T*)m->d_minv32.ptr;
-        geo.vol = (const T*)m->d_vol32.ptr; geo.vcap = (const T*)m->d_vcap32.ptr;
+        geo.face = (const T*)m->d_face32.ptr;
+        geo.cell = (const T*)m->d_cell32.ptr;
     }
     geo.nf = m->nf;
     return geo;
@@ -733,8 +745,8 @@ static GeomView<T> geom_view(const rt_mesh* m) {
 GeomView<double> rt_geo64(const rt_mesh* m) { return geom_view<double>(m); }
 
 SellView rt_sell(const rt_mesh* m) {
-    return SellView{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_sptr.ptr,
-                    (const int32_t*)m->d_sdeg.ptr};
+    return SellView{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_opp.ptr,
+                    (const int32_t*)m->d_sptr.ptr, (const int32_t*)m->d_sdeg.ptr};
 }
 
 // One piece of a subcycle on explicit buffers (U, G in the state's precision).
@@ -767,28 +779,28 @@ void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStr
     s->prof_end(st);
 }
 
-void rt_step_gradient(rt_state* s, const void* U, void* G, hipStream_t st) {
+void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st) {
     s->prof_begin(RT_KERNEL_GRADIENT, st);
     if (s->precision == RT_MIXED)
-        launch_gradient<float>((const float*)U, (float*)G, s->nc, s->nb, geom_view<float>(s->mesh), rt_sell(s->mesh),
-                               s->params.use_limiter, st);
+        launch_facestate<float>((const float*)U, (float*)FV, s->nc, s->nb, s->mesh->n_entries,
+                                geom_view<float>(s->mesh), rt_sell(s->mesh), s->params.use_limiter, st);
     else
-        launch_gradient<double>((const double*)U, (double*)G, s->nc, s->nb, geom_view<double>(s->mesh),
-                                rt_sell(s->mesh), s->params.use_limiter, st);
+        launch_facestate<double>((const double*)U, (double*)FV, s->nc, s->nb, s->mesh->n_entries,
+                                 geom_view<double>(s->mesh), rt_sell(s->mesh), s->params.use_limiter, st);
     s->prof_end(st);
 }
 
-void rt_step_flux(rt_state* s, const void* U, const void* G, void* Un, double dt, hipStream_t st) {
+void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st) {
     const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
     s->prof_begin(RT_KERNEL_FLUX, st);
     if (s->precision == RT_MIXED)
-        launch_flux<float>((const float*)U, (const float*)G, (float*)Un, s->nc, s->nb, geom_view<float>(s->mesh),
-                           rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr, (int64_t*)s->part_cnt.ptr,
-                           (int32_t*)s->part_fst.ptr, st);
+        launch_flux<float>((const float*)U, (const float*)FV, (float*)Un, s->nc, s->nb, s->mesh->n_entries,
+                           geom_view<float>(s->mesh), rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr,
+                           (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
     else
-        launch_flux<double>((const double*)U, (const double*)G, (double*)Un, s->nc, s->nb, geom_view<double>(s->mesh),
-                            rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr, (int64_t*)s->part_cnt.ptr,
-                            (int32_t*)s->part_fst.ptr, st);
+        launch_flux<double>((const double*)U, (const double*)FV, (double*)Un, s->nc, s->nb, s->mesh->n_entries,
+                            geom_view<double>(s->mesh), rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr,
+                            (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
     s->prof_end(st);
 }
 
@@ -798,8 +810,8 @@ void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st) {
         void* Un = s->U[s->cur ^ 1].ptr;
         rt_step_sources(s, U, dt, st);
         rt_step_chem(s, U, (double*)s->X.ptr, (double*)s->Ue.ptr, dt, st);
-        rt_step_gradient(s, U, s->G.ptr, st);
-        rt_step_flux(s, U, s->G.ptr, Un, dt, st);
+        rt_step_facestate(s, U, s->FV.ptr, st);
+        rt_step_flux(s, U, s->FV.ptr, Un, dt, st);
         s->cur ^= 1;
     }
 }

@@ -36,18 +36,17 @@ struct rt_mesh {
     int32_t max_deg = 0;
     std::atomic<int> refs{0};
     // Host copies (FP64, units of h_ref).
-    std::vector<double> face;    // [10][nf]
-    std::vector<double> minv;    // [6][nc]
-    std::vector<double> vol;     // [nc]
-    std::vector<double> vcap;    // [nc]
+    std::vector<double> face;    // [nf][kFaceRec]: A, n, rL, rR, vcap_L, vcap_R
+    std::vector<double> cell;    // [nc][kCellRec]: M^-1 (xx yy zz xy xz yz), V, vcap
     std::vector<double> vphys;   // [nc] cm^3
     std::vector<int32_t> deg;    // faces per cell
-    std::vector<int32_t> nbr, fsf, sptr, sdeg;   // sliced ELL
+    std::vector<int32_t> nbr, fsf, opp, sptr, sdeg;   // sliced ELL
+    int64_t n_entries = 0;       // sliced-ELL slots (face sides plus padding)
     // Device copies.
-    DevMem d_face64, d_minv64, d_vol64, d_vcap64, d_vphys;
-    DevMem d_face32, d_minv32, d_vol32, d_vcap32;
+    DevMem d_face64, d_cell64, d_vphys;
+    DevMem d_face32, d_cell32;
     bool geo32_ready = false;
-    DevMem d_nbr, d_fsf, d_sptr, d_sdeg;
+    DevMem d_nbr, d_fsf, d_opp, d_sptr, d_sdeg;
 
     int build_float_geometry();
 };
@@ -63,11 +62,11 @@ struct rt_state {
     int64_t nc = 0;
     double dt_cfl = 0.0;
 
-    // Fields: U[b][4][nc] = (N, Fh_x, Fh_y, Fh_z) / scale_b in the transport
-    // precision, double-buffered; gradients G[b][4][3][nc]; chemistry in FP64.
+    // Fields: U[b][nc][4] = (N, Fh_x, Fh_y, Fh_z) / scale_b in the transport
+    // precision, double-buffered; face states FV[b][entry][4]; chemistry FP64.
     DevMem U[2];
     int cur = 0;
-    DevMem G;
+    DevMem FV;
     DevMem X, Ue, nH;            // [5][nc], [nc], [nc]
     double scale[RT_MAX_BINS];
     DevMem d_scale, d_inv_scale, d_nv_scale;
@@ -114,8 +113,8 @@ rtk::GeomView<double> rt_geo64(const rt_mesh* m);
 rtk::SellView rt_sell(const rt_mesh* m);
 void rt_step_sources(rt_state* s, void* U, double dt, hipStream_t st);
 void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStream_t st);
-void rt_step_gradient(rt_state* s, const void* U, void* G, hipStream_t st);
-void rt_step_flux(rt_state* s, const void* U, const void* G, void* Un, double dt, hipStream_t st);
+void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st);
+void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st);
 void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st);
 void rt_reset_partials(rt_state* s, hipStream_t st);
 // Folds the partials and returns the status word (synchronises the stream).

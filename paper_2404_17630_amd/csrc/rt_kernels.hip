@@ -1,22 +1,25 @@
 // HIP kernels of the M1 radiative-transfer subcycle for gfx950 (CDNA4).
 //
-// One subcycle (Zier et al. 2024, Fig. 1) is five launches on one stream:
-//   k_sources   point-source injection, one lane per source cell
-//   k_chem      thermochemistry + absorption, one lane per cell (FP64)
-//   k_gradient  least-squares gradients + slope limiter, one lane per (cell, bin)
-//   k_flux      face fluxes + divergence update, one lane per (cell, bin)
-//   (k_reduce   diagnostics, once per call)
-// The path is a six-neighbour gather stencil bound by HBM bandwidth, so
-// there is no matrix-core work: lanes of a wavefront are 64 consecutive
-// cells of one bin (coalesced SoA loads of the cell's own fields), each
-// cell gathers its neighbours through a sliced-ELL face list, and each cell
-// recomputes the fluxes of its own faces from the states of both sides in
-// the face's canonical (L, R) orientation.  The two cells of a face thus
-// obtain bit-identical fluxes of opposite sign: accumulation is
+// One subcycle (Zier et al. 2024, Fig. 1) is four launches on one stream:
+//   k_sources    point-source injection, one lane per source cell
+//   k_chem       thermochemistry + absorption, one lane per cell (FP64)
+//   k_facestate  least-squares gradients + slope limiter in FP64 registers,
+//                then the limited state at each face centre, one lane per
+//                (cell, bin); writes one 4-value record per face side
+//   k_flux       face fluxes + divergence update, one lane per (cell, bin)
+//   (k_reduce    diagnostics, once per call)
+// The path is a six-neighbour gather stencil bound by memory traffic, so
+// there is no matrix-core work.  Lanes of a wavefront are 64 consecutive
+// cells of one bin; fields are 4-value records per (bin, cell) and geometry
+// is one record per face and per cell, so a gathered neighbour costs one or
+// two 16-byte loads.  Each cell computes the fluxes of its own faces from the
+// two face states in the face's canonical (L, R) orientation: the two cells
+// of a face obtain bit-identical fluxes of opposite sign, so accumulation is
 // deterministic and needs no atomics or face-flux array (the paper's GPU
 // design stores fluxes per interface and gathers them in a second kernel,
-// Sec. 4.1.3).  T is the transport precision (double, or float in the
-// mixed form); flux sums, photon sums and chemistry are always double.
+// Sec. 4.1.3).  T is the storage precision of the transport fields (double,
+// or float in the mixed form); gradients and face extrapolation are FP64 in
+// registers, flux sums and photon sums FP64, chemistry FP64.
 
 #include <hip/hip_runtime.h>
 
@@ -115,10 +118,10 @@ __global__ void k_sources(T* __restrict__ U, int64_t nc, int nb, int32_t n_cells
     if (c >= n_cells_src) return;
     const int64_t i = cell[c];
     for (int b = 0; b < nb; ++b) {
-        T* Nb = U + (int64_t)(b * 4) * nc;
-        double N = (double)Nb[i] * scale[b];
+        T* Nb = U + urec(b, nc, i);
+        double N = (double)Nb[0] * scale[b];
         for (int32_t k = ptr[c]; k < ptr[c + 1]; ++k) N = N + rate[(int64_t)b * n_src + k] * dt / vphys[k];
-        Nb[i] = (T)(N * inv_scale[b]);
+        Nb[0] = (T)(N * inv_scale[b]);
     }
 }
 
@@ -144,9 +147,11 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
         double N[NB], Fh[NB][3], x[5];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            N[b] = (double)U[(int64_t)(b * 4) * nc + i] * scale[b];
+            T r[4];
+            load4(U + urec(b, nc, i), r);
+            N[b] = (double)r[0] * scale[b];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) Fh[b][k] = (double)U[(int64_t)(b * 4 + 1 + k) * nc + i] * scale[b];
+            for (int k = 0; k < 3; ++k) Fh[b][k] = (double)r[1 + k] * scale[b];
         }
 #pragma unroll
         for (int s = 0; s < 5; ++s) x[s] = X[(int64_t)s * nc + i];
@@ -157,9 +162,9 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
         } else {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                U[(int64_t)(b * 4) * nc + i] = (T)(N[b] * inv_scale[b]);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) U[(int64_t)(b * 4 + 1 + k) * nc + i] = (T)(Fh[b][k] * inv_scale[b]);
+                T r[4] = {(T)(N[b] * inv_scale[b]), (T)(Fh[b][0] * inv_scale[b]), (T)(Fh[b][1] * inv_scale[b]),
+                          (T)(Fh[b][2] * inv_scale[b])};
+                store4(U + urec(b, nc, i), r);
             }
 #pragma unroll
             for (int s = 0; s < 5; ++s) X[(int64_t)s * nc + i] = x[s];
@@ -178,98 +183,56 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
 }
 
 // ---------------------------------------------------------------------------
-// k_gradient: g = M^-1 sum_j w_ij (phi_j - phi_i) for phi = N, Fh_x, Fh_y,
-// Fh_z of one bin (Sec. 2.3.2, eq. normalEquation), w_ij = A d / |d|^2 with
-// d = s_j - s_i taken through the face centre, then a Barth-Jespersen factor
-// per variable so that no face-centre extrapolation leaves [min, max] of the
-// cell and its neighbours.  Output layout g[b][v][k][nc].
+// k_facestate: limited gradients of N, Fh_x, Fh_y, Fh_z of one bin in FP64
+// (Sec. 2.3.2), then the extrapolated state U_i + g . r_if at each face
+// centre (Sec. 2.3.3), stored in the transport precision as one record per
+// face side: FV[b][e][4].  Keeping g in registers means a limited face
+// state is rounded once, relative to its own size (an FP32-stored gradient
+// would cancel at steep fronts, where U + g.r is much smaller than U).
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gradient(const T* __restrict__ U, T* __restrict__ G, int64_t nc, int nb,
-                                                     GeomView<T> geo, SellView sell, int use_limiter) {
+__global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T* __restrict__ FV, int64_t nc, int nb,
+                                                      int64_t n_entries, GeomView<T> geo, SellView sell,
+                                                      int use_limiter) {
     const int64_t blk = xcd_logical_block();
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
     if (i >= nc) return;
-    const int64_t nf = geo.nf;
-    const T* Ub = U + (int64_t)(b * 4) * nc;
-
-    T ui[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) ui[v] = Ub[(int64_t)v * nc + i];
-    T bs[4][3], umax[4], umin[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        bs[v][0] = bs[v][1] = bs[v][2] = T(0);
-        umax[v] = umin[v] = ui[v];
-    }
+    double ui[4], g[4][3];
+    limited_gradient<T>(i, b, nc, U, geo, sell, use_limiter, ui, g);
     const int64_t slice = i / kSlice;
     const int32_t deg = sell.deg[slice];
     const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
+    T* FVb = FV + (int64_t)b * n_entries * 4;
     for (int k = 0; k < deg; ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
-        const int32_t j = sell.nbr[e];
-        if (j < 0) continue;
+        if (sell.nbr[e] < 0) continue;
         const int32_t fs = sell.fsf[e];
         const bool isL = fs >= 0;
-        const int64_t f = isL ? fs : ~fs;
-        const T A = geo.face[f];
-        const T rl0 = geo.face[4 * nf + f], rl1 = geo.face[5 * nf + f], rl2 = geo.face[6 * nf + f];
-        const T rr0 = geo.face[7 * nf + f], rr1 = geo.face[8 * nf + f], rr2 = geo.face[9 * nf + f];
-        // d = r_if - r_jf = s_j - s_i
-        const T d0 = isL ? rl0 - rr0 : rr0 - rl0;
-        const T d1 = isL ? rl1 - rr1 : rr1 - rl1;
-        const T d2 = isL ? rl2 - rr2 : rr2 - rl2;
-        const T s = A / (d0 * d0 + d1 * d1 + d2 * d2);
-        const T w0 = d0 * s, w1 = d1 * s, w2 = d2 * s;
+        const FaceRec<T> fr = load_face(geo.face, isL ? fs : ~fs);
+        const double r0 = isL ? fr.rl0 : fr.rr0, r1 = isL ? fr.rl1 : fr.rr1, r2 = isL ? fr.rl2 : fr.rr2;
+        T s[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const T uj = Ub[(int64_t)v * nc + j];
-            const T dphi = uj - ui[v];
-            bs[v][0] += w0 * dphi;
-            bs[v][1] += w1 * dphi;
-            bs[v][2] += w2 * dphi;
-            umax[v] = uj > umax[v] ? uj : umax[v];
-            umin[v] = uj < umin[v] ? uj : umin[v];
-        }
+        for (int v = 0; v < 4; ++v) s[v] = (T)(ui[v] + (g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2));
+        store4(FVb + e * 4, s);
     }
-    const T mxx = geo.minv[i], myy = geo.minv[nc + i], mzz = geo.minv[2 * nc + i];
-    const T mxy = geo.minv[3 * nc + i], mxz = geo.minv[4 * nc + i], myz = geo.minv[5 * nc + i];
-    T g[4][3];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        g[v][0] = mxx * bs[v][0] + mxy * bs[v][1] + mxz * bs[v][2];
-        g[v][1] = mxy * bs[v][0] + myy * bs[v][1] + myz * bs[v][2];
-        g[v][2] = mxz * bs[v][0] + myz * bs[v][1] + mzz * bs[v][2];
-    }
-    if (use_limiter) {
-        T alpha[4] = {T(1), T(1), T(1), T(1)};
-        for (int k = 0; k < deg; ++k) {
-            const int64_t e = base + (int64_t)k * kSlice;
-            if (sell.nbr[e] < 0) continue;
-            const int32_t fs = sell.fsf[e];
-            const bool isL = fs >= 0;
-            const int64_t f = isL ? fs : ~fs;
-            const int64_t o = isL ? 4 * nf : 7 * nf;
-            const T r0 = geo.face[o + f], r1 = geo.face[o + nf + f], r2 = geo.face[o + 2 * nf + f];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const T delta = g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2;
-                T psi = T(1);
-                if (delta > T(0)) psi = (umax[v] - ui[v]) / delta;
-                else if (delta < T(0)) psi = (umin[v] - ui[v]) / delta;
-                alpha[v] = psi < alpha[v] ? psi : alpha[v];
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            g[v][0] *= alpha[v];
-            g[v][1] *= alpha[v];
-            g[v][2] *= alpha[v];
-        }
-    }
-    T* Gb = G + (int64_t)(b * 12) * nc;
+}
+
+// ---------------------------------------------------------------------------
+// k_gradient: the limited gradients themselves, G[b][v*3+c][nc] in FP64
+// (used by the adjoint, which differentiates through the extrapolation).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_gradient(const double* __restrict__ U, double* __restrict__ G, int64_t nc,
+                                                     int nb, GeomView<double> geo, SellView sell, int use_limiter) {
+    const int64_t blk = xcd_logical_block();
+    const int b = (int)(blk % nb);
+    const int64_t i = (blk / nb) * kBlock + threadIdx.x;
+    if (i >= nc) return;
+    double ui[4], g[4][3];
+    limited_gradient<double>(i, b, nc, U, geo, sell, use_limiter, ui, g);
+    double* Gb = G + (int64_t)(b * 12) * nc;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -277,19 +240,18 @@ __global__ __launch_bounds__(kBlock) void k_gradient(const T* __restrict__ U, T*
 }
 
 // ---------------------------------------------------------------------------
-// k_flux: for each face of the cell, both face states from the
-// start-of-transport fields and gradients, the HLL flux, the outflow cap
-// theta = min(1, N_up V_up / (n_faces(up) |Phi_N| dt A)); then
-// U_i <- U_i - (dt / V_i) sum_f sigma A Phi in face-index order, with
+// k_flux: for each face of the cell, the HLL flux of the two face states and
+// the outflow cap theta = min(1, N_up V_up / (n_faces(up) |Phi_N| dt A));
+// then U_i <- U_i - (dt / V_i) sum_f sigma A Phi in face-index order, with
 // post-update guards.  Writes the new fields to Unew (double buffering:
 // neighbours still read U).  Per-block partials: sum N V (this bin),
 // counters and status, accumulated across the subcycles of one call.
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ G, T* __restrict__ Unew,
-                                                 int64_t nc, int nb, GeomView<T> geo, SellView sell, T cdt,
-                                                 double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
+template <typename T, typename TA>
+__global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ FV, T* __restrict__ Unew,
+                                                 int64_t nc, int nb, int64_t n_entries, GeomView<T> geo, SellView sell,
+                                                 TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
                                                  int32_t* __restrict__ part_status, int64_t n_blocks) {
     __shared__ double ldsd[kBlock / 64];
     __shared__ int64_t ldsi[kBlock / 64];
@@ -297,35 +259,28 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
     const int64_t blk = xcd_logical_block();
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
-    const T* Ub = U + (int64_t)(b * 4) * nc;
-    const T* Gb = G + (int64_t)(b * 12) * nc;
 
     int cAdmN = 0, cAdmF = 0, cCap = 0, cGN = 0, cGF = 0, status = 0;
     double nv = 0.0;
     if (i < nc) {
-        T ui[4], gi[4][3];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            ui[v] = Ub[(int64_t)v * nc + i];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) gi[v][c] = Gb[(int64_t)(v * 3 + c) * nc + i];
-        }
-        const T vcap_i = geo.vcap[i];
+        T ui[4];
+        load4(U + urec(b, nc, i), ui);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        cell_flux_sum<T>(i, nc, Ub, Gb, geo, sell, cdt, ui, gi, vcap_i, acc, cAdmN, cAdmF, cCap);
-        const double coef = (double)cdt / (double)geo.vol[i];
+        cell_flux_sum<T, TA>(i, b, nc, n_entries, U, FV, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
+        const double vol = (double)geo.cell[i * kCellRec + 6];
+        const double coef = (double)cdt / vol;
         double un[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) un[v] = (double)ui[v] - coef * acc[v];
         update_guards<double>(un, cGN, cGF);
-        T* Ob = Unew + (int64_t)(b * 4) * nc;
+        T o[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const T o = (T)un[v];
-            Ob[(int64_t)v * nc + i] = o;
-            if (!isfinite((double)o)) status = 1;
+            o[v] = (T)un[v];
+            if (!isfinite((double)o[v])) status = 1;
         }
-        nv = (double)(T)un[0] * (double)geo.vol[i];
+        store4(Unew + urec(b, nc, i), o);
+        nv = (double)o[0] * vol;
     }
     const double snv = block_sum<double>(nv, ldsd);
     const int64_t s0 = block_sum<int64_t>(cAdmN, ldsi);
@@ -420,11 +375,11 @@ __global__ void k_get_fields(const T* __restrict__ U, const double* __restrict__
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nc) return;
     if (field == 0) {
-        for (int b = 0; b < nb; ++b) out[(int64_t)b * nc + i] = (double)U[(int64_t)(b * 4) * nc + i] * scale[b];
+        for (int b = 0; b < nb; ++b) out[(int64_t)b * nc + i] = (double)U[urec(b, nc, i)] * scale[b];
     } else if (field == 1) {
         for (int b = 0; b < nb; ++b)
             for (int k = 0; k < 3; ++k)
-                out[(int64_t)(b * 3 + k) * nc + i] = (double)U[(int64_t)(b * 4 + 1 + k) * nc + i] * scale[b] * c_red;
+                out[(int64_t)(b * 3 + k) * nc + i] = (double)U[urec(b, nc, i) + 1 + k] * scale[b] * c_red;
     } else if (field == 4) {
         double x[5];
         for (int s = 0; s < 5; ++s) x[s] = X[(int64_t)s * nc + i];
@@ -439,11 +394,11 @@ __global__ void k_set_fields(T* __restrict__ U, const double* __restrict__ X, do
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nc) return;
     if (field == 0) {
-        for (int b = 0; b < nb; ++b) U[(int64_t)(b * 4) * nc + i] = (T)(in[(int64_t)b * nc + i] * inv_scale[b]);
+        for (int b = 0; b < nb; ++b) U[urec(b, nc, i)] = (T)(in[(int64_t)b * nc + i] * inv_scale[b]);
     } else if (field == 1) {
         for (int b = 0; b < nb; ++b)
             for (int k = 0; k < 3; ++k)
-                U[(int64_t)(b * 4 + 1 + k) * nc + i] = (T)(in[(int64_t)(b * 3 + k) * nc + i] / c_red * inv_scale[b]);
+                U[urec(b, nc, i) + 1 + k] = (T)(in[(int64_t)(b * 3 + k) * nc + i] / c_red * inv_scale[b]);
     } else if (field == 4) {
         // thermal energy from T and the current fractions
         double x[5];
@@ -498,18 +453,25 @@ int64_t chem_blocks(int64_t nc) { return (int64_t)grid_for(nc, kBlock); }
 int64_t transport_blocks(int64_t nc, int nb) { return (int64_t)grid_for(nc, kBlock) * nb; }
 
 template <typename T>
-void launch_gradient(const T* U, T* G, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
+void launch_facestate(const T* U, T* FV, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
+                      const SellView& sell, int use_limiter, hipStream_t s) {
+    hipLaunchKernelGGL(k_facestate<T>, dim3((unsigned)transport_blocks(nc, nb)), dim3(kBlock), 0, s, U, FV, nc, nb,
+                       n_entries, geo, sell, use_limiter);
+}
+
+void launch_gradient(const double* U, double* G, int64_t nc, int nb, const GeomView<double>& geo, const SellView& sell,
                      int use_limiter, hipStream_t s) {
-    hipLaunchKernelGGL(k_gradient<T>, dim3((unsigned)transport_blocks(nc, nb)), dim3(kBlock), 0, s, U, G, nc, nb, geo,
+    hipLaunchKernelGGL(k_gradient, dim3((unsigned)transport_blocks(nc, nb)), dim3(kBlock), 0, s, U, G, nc, nb, geo,
                        sell, use_limiter);
 }
 
 template <typename T>
-void launch_flux(const T* U, const T* G, T* Unew, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
-                 double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
+void launch_flux(const T* U, const T* FV, T* Unew, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
+                 const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
+                 hipStream_t s) {
     const int64_t nblk = transport_blocks(nc, nb);
-    hipLaunchKernelGGL(k_flux<T>, dim3((unsigned)nblk), dim3(kBlock), 0, s, U, G, Unew, nc, nb, geo, sell, (T)cdt,
-                       part_nv, part_cnt, part_status, nblk);
+    hipLaunchKernelGGL((k_flux<T, T>), dim3((unsigned)nblk), dim3(kBlock), 0, s, U, FV, Unew, nc, nb, n_entries, geo,
+                       sell, (T)cdt, part_nv, part_cnt, part_status, nblk);
 }
 
 void launch_reduce(const double* part_nv, const int64_t* part_cnt, const int32_t* part_fstatus, int64_t n_fblocks,
@@ -547,10 +509,10 @@ void launch_set_fields(T* U, const double* X, double* Ue, int64_t nc, int nb, in
                                     int64_t, const double*, const double*, const double*, double, hipStream_t);    \
     template void launch_chem<T>(T*, double*, double*, const double*, int64_t, const ChemParams&, double,           \
                                  const double*, const double*, int64_t*, int64_t*, int32_t*, hipStream_t);          \
-    template void launch_gradient<T>(const T*, T*, int64_t, int, const GeomView<T>&, const SellView&, int,          \
-                                     hipStream_t);                                                                 \
-    template void launch_flux<T>(const T*, const T*, T*, int64_t, int, const GeomView<T>&, const SellView&, double, \
-                                 double*, int64_t*, int32_t*, hipStream_t);                                         \
+    template void launch_facestate<T>(const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, int, \
+                                      hipStream_t);                                                                \
+    template void launch_flux<T>(const T*, const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, \
+                                 double, double*, int64_t*, int32_t*, hipStream_t);                                 \
     template void launch_get_fields<T>(const T*, const double*, const double*, int64_t, int, int, const double*,   \
                                        double, const ChemParams&, double*, hipStream_t);                           \
     template void launch_set_fields<T>(T*, const double*, double*, int64_t, int, int, const double*, double,       \

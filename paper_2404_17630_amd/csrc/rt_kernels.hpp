@@ -35,12 +35,16 @@ void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, cons
                  int32_t* part_status, hipStream_t s);
 
 template <typename T>
-void launch_gradient(const T* U, T* G, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
+void launch_facestate(const T* U, T* FV, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
+                      const SellView& sell, int use_limiter, hipStream_t s);
+
+void launch_gradient(const double* U, double* G, int64_t nc, int nb, const GeomView<double>& geo, const SellView& sell,
                      int use_limiter, hipStream_t s);
 
 template <typename T>
-void launch_flux(const T* U, const T* G, T* Unew, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
-                 double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status, hipStream_t s);
+void launch_flux(const T* U, const T* FV, T* Unew, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
+                 const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
+                 hipStream_t s);
 
 void launch_reduce(const double* part_nv, const int64_t* part_cnt, const int32_t* part_fstatus, int64_t n_fblocks,
                    int nb, const int64_t* chem_sum, const int64_t* chem_max, const int32_t* chem_status,

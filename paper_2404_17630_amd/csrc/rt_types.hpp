@@ -20,27 +20,34 @@ struct ChemParams {
     double eheat[kMaxBins][3];
 };
 
+// Field layout: one record of four values per (bin, cell), U[(b nc + i) 4 + v]
+// with v = N, Fh_x, Fh_y, Fh_z, so a neighbour's state is one 16-byte (FP32)
+// or 32-byte (FP64) load.
+__host__ __device__ inline int64_t urec(int b, int64_t nc, int64_t i) { return ((int64_t)b * nc + i) * 4; }
+
 // Geometry of one precision variant (lengths in units of h_ref).
-//   face [10][nf]: A, n_x, n_y, n_z, rL_x, rL_y, rL_z, rR_x, rR_y, rR_z
-//     (rL = minimum-image offset from the L cell centre to the face centre)
-//   minv [6][nc]: xx, yy, zz, xy, xz, yz of the inverse geometry matrix
-//   vol  [nc]: V;  vcap [nc]: V / (number of faces of the cell)
+//   face [nf][kFaceRec]: A, n_x, n_y, n_z, rL_x, rL_y, rL_z, rR_x, rR_y, rR_z,
+//     vcap_L, vcap_R (rL = minimum-image offset from the L cell centre to the
+//     face centre; vcap = V / number of faces of the cell)
+//   cell [nc][kCellRec]: inverse geometry matrix xx, yy, zz, xy, xz, yz; V; vcap
+constexpr int kFaceRec = 12;
+constexpr int kCellRec = 8;
 template <typename T>
 struct GeomView {
     const T* face;
-    const T* minv;
-    const T* vol;
-    const T* vcap;
+    const T* cell;
     int64_t nf;
 };
 
 // Face sides of each cell in sliced-ELL order: slice s (cells 64s..64s+63)
 // holds deg[s] slots; slot k of lane l is entry ptr[s] + 64 k + l.  nbr is
 // the neighbour cell (-1 for padding), fsf the face index (f when the cell is
-// the face's L cell, ~f when it is R).  Slots are in increasing face index.
+// the face's L cell, ~f when it is R), opp the entry of the same face in the
+// neighbour's list.  Slots are in increasing face index.
 struct SellView {
     const int32_t* nbr;
     const int32_t* fsf;
+    const int32_t* opp;
     const int32_t* ptr;
     const int32_t* deg;
 };

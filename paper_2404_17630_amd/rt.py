@@ -22,7 +22,7 @@ RT_CHEM_NONE, RT_CHEM_H, RT_CHEM_HHE = 0, 1, 2
 RT_RATES_CASEB_CONST, RT_RATES_HG97 = 0, 1
 RT_FIELD_N, RT_FIELD_F, RT_FIELD_NH, RT_FIELD_SPECIES, RT_FIELD_T = 0, 1, 2, 3, 4
 RT_KERNEL_SOURCES, RT_KERNEL_CHEM, RT_KERNEL_GRADIENT, RT_KERNEL_FLUX, RT_KERNEL_REDUCE = 0, 1, 2, 3, 4
-KERNEL_NAMES = ("k_sources", "k_chem", "k_gradient", "k_flux", "k_reduce")
+KERNEL_NAMES = ("k_sources", "k_chem", "k_facestate", "k_flux", "k_reduce")
 
 ERROR_NAMES = {RT_EINVAL: "RT_EINVAL", RT_EMESH: "RT_EMESH", RT_ESTATE: "RT_ESTATE", RT_EDEVICE: "RT_EDEVICE",
                RT_ENOMEM: "RT_ENOMEM", RT_ENUMERIC: "RT_ENUMERIC"}
