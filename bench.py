@@ -203,15 +203,29 @@ def main() -> int:
         st64.close()
         v64 = nc * nb * args.steps / t64
         N64, Nm = f64["N"], fields_mixed["N"]
-        errN = 0.0
+        fc = cfg["mesh"]["face_cells"]
+        errN, errC, p999, frac = 0.0, 0.0, 0.0, 0.0
         for b in range(nb):
-            mask = N64[b] > 1e-10 * N64[b].max()
-            errN = max(errN, float((np.abs(Nm[b][mask] - N64[b][mask]) / N64[b][mask]).max()))
+            r = N64[b]
+            mask = r > 1e-10 * r.max()
+            rel = np.abs(Nm[b][mask] - r[mask]) / r[mask]
+            errN = max(errN, float(rel.max()))
+            p999 = max(p999, float(np.quantile(rel, 0.999)))
+            frac = max(frac, float(np.mean(rel > 1e-3)))
+            # against max(N, 1e-4 of the stencil maximum, 1e-10 of the maximum)
+            m = r.copy()
+            np.maximum.at(m, fc[0], r[fc[1]])
+            np.maximum.at(m, fc[1], r[fc[0]])
+            scale = np.maximum(np.maximum(r, 1e-4 * m), 1e-10 * r.max())
+            errC = max(errC, float((np.abs(Nm[b] - r) / np.where(scale > 0, scale, 1.0)).max()))
         out["fp64_value"] = v64
         out["fp64_ms_per_step"] = t64 / args.steps * 1e3
         out["mixed_speedup_vs_fp64"] = value / v64
         out["mixed_error_vs_fp64"] = {
             "N_rel_max(N>1e-10 max)": errN,
+            "N_rel_p99.9(N>1e-10 max)": p999,
+            "N_frac_cells_rel>1e-3": frac,
+            "N_rel_max(stencil floor 1e-4)": errC,
             "x_HII_abs_max": float(np.abs(fields_mixed["species"][1] - f64["species"][1]).max()),
             "y_HeII_abs_max": float(np.abs(fields_mixed["species"][3] - f64["species"][3]).max()),
             "T_rel_max": float((np.abs(fields_mixed["T"] - f64["T"]) / f64["T"]).max()),

@@ -327,30 +327,34 @@ __global__ __launch_bounds__(kBlock) void k_adj_chem(const double* __restrict__ 
     const int64_t blk = xcd_logical_block();
     const int64_t i = blk * kBlock + threadIdx.x;
     if (i >= nc) return;
-    Dual<K> N[NB], Fh[NB][3], x[5], u, nHd;
+    ChemState<NB, Dual<K>> s;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        N[b] = Dual<K>(Upre[urec(b, nc, i)]);
-        N[b].d[6 + b] = 1.0;
-        Fh[b][0] = Dual<K>(1.0);
-        Fh[b][1] = Dual<K>(0.0);
-        Fh[b][2] = Dual<K>(0.0);
+        s.N[b] = Dual<K>(Upre[urec(b, nc, i)]);
+        s.N[b].d[6 + b] = 1.0;
+        s.Fh[b][0] = Dual<K>(1.0);
+        s.Fh[b][1] = Dual<K>(0.0);
+        s.Fh[b][2] = Dual<K>(0.0);
     }
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
-        x[s] = Dual<K>(Xpre[(int64_t)s * nc + i]);
-        x[s].d[s] = 1.0;
+    for (int q = 0; q < 5; ++q) {
+        s.x[q] = Dual<K>(Xpre[(int64_t)q * nc + i]);
+        s.x[q].d[q] = 1.0;
     }
-    u = Dual<K>(Upre_u[i]);
-    u.d[5] = 1.0;
+    s.u = Dual<K>(Upre_u[i]);
+    s.u.d[5] = 1.0;
     const double nh = nH[i];
-    nHd = Dual<K>(nh);
+    Dual<K> nHd(nh);
     nHd.d[6 + NB] = 1.0;
-    const int att = integrate_cell<NB, Dual<K>>(P, dt, nHd, N, Fh, x, u);
+    const int att = integrate_cell<NB, Dual<K>>(P, dt, nHd, s);
     if (att > P.max_sub) {
         fail[blockIdx.x] = 1;
         return;
     }
+    const Dual<K>* x = s.x;
+    const Dual<K>& u = s.u;
+    const Dual<K>* N = s.N;
+    const Dual<K> (*Fh)[3] = s.Fh;
     double lin[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) lin[k] = 0.0;

@@ -124,88 +124,117 @@ __device__ inline R temperature(const ChemParams& P, const R& u, const R* x) {
     return P.gm1 * mean_mass(P, x) * kProtonMass * u / kBoltz;
 }
 
-// Integrate one cell over the subcycle Dt.  N[b], Fh[b][3], x[5] and u are
-// updated in place; returns the number of attempts (> max_sub on failure).
+// Integration state of one cell within a subcycle.
 template <int NB, typename R>
-__device__ inline int integrate_cell(const ChemParams& P, double Dt, const R& nH, R* N, R (*Fh)[3], R* x, R& u) {
+struct ChemState {
+    R N[NB];
+    R Fh[NB][3];
+    R x[5];
+    R u;
+    R tau;       // time integrated so far
+    R d;         // proposed step
+    int attempts;
+};
+
+template <int NB, typename R>
+__device__ inline void chem_begin(double Dt, ChemState<NB, R>& s) {
+    s.tau = R(0.0);
+    s.d = R(Dt);
+    s.attempts = 0;
+}
+
+// One attempt of the adaptive semi-implicit step.  Returns 1 when the
+// subcycle is complete, 0 to continue, -1 when the attempt cap is exceeded.
+template <int NB, typename R>
+__device__ inline int chem_attempt(const ChemParams& P, double Dt, const R& nH, ChemState<NB, R>& s) {
     const bool hhe = P.chem_mode == 2;
     const double ct = P.c;
     const double yhe = P.yhe;
-    const R rho = kProtonMass * nH * (1.0 + 4.0 * yhe);
-    R tau = 0.0;
-    R d = Dt;
-    int attempts = 0;
-    while (true) {
-        bool last = false;
-        if (val(d) >= val(Dt - tau)) { d = Dt - tau; last = true; }
-        if (++attempts > P.max_sub) return attempts;
+    bool last = false;
+    if (val(s.d) >= val(Dt - s.tau)) { s.d = Dt - s.tau; last = true; }
+    if (++s.attempts > P.max_sub) return -1;
+    const R d = s.d;
+    R* x = s.x;
 
-        const R T = P.isothermal ? R(P.T_iso) : temperature(P, u, x);
-        const Rates<R> r = network_rates(P, T);
-        const R ne = nH * (x[1] + yhe * (x[3] + 2.0 * x[4]));
-        const R nHI = nH * x[0];
-        const R nHeI = yhe * nH * x[2];
-        const R nHeII = yhe * nH * x[3];
+    const R T = P.isothermal ? R(P.T_iso) : temperature(P, s.u, x);
+    const Rates<R> r = network_rates(P, T);
+    const R ne = nH * (x[1] + yhe * (x[3] + 2.0 * x[4]));
+    const R nHI = nH * x[0];
+    const R nHeI = yhe * nH * x[2];
+    const R nHeII = yhe * nH * x[3];
 
-        R fac[NB], Nn[NB];
-        R G0 = 0.0, G1 = 0.0, G2 = 0.0, heat = 0.0;
+    R fac[NB], Nn[NB];
+    R G0 = 0.0, G1 = 0.0, G2 = 0.0, heat = 0.0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const R kap = P.sigma[b][0] * nHI + P.sigma[b][1] * nHeI + P.sigma[b][2] * nHeII;
-            fac[b] = 1.0 + ct * d * kap;
-            Nn[b] = N[b] / fac[b];
-            G0 += ct * P.sigma[b][0] * Nn[b];
-            G1 += ct * P.sigma[b][1] * Nn[b];
-            G2 += ct * P.sigma[b][2] * Nn[b];
-            heat += ct * Nn[b] * (P.sigma[b][0] * nHI * P.eheat[b][0] + P.sigma[b][1] * nHeI * P.eheat[b][1] +
-                                  P.sigma[b][2] * nHeII * P.eheat[b][2]);
-        }
-
-        R xn[5];
-        const R den = 1.0 + (G0 + r.col_HI * ne + r.rec_HII * ne) * d;
-        xn[0] = (x[0] + r.rec_HII * ne * d) / den;
-        xn[1] = (x[1] + (G0 + r.col_HI * ne) * d) / den;
-        if (hhe) {
-            xn[2] = (x[2] + r.rec_HeII * ne * x[3] * d) / (1.0 + (G1 + r.col_HeI * ne) * d);
-            xn[4] = (x[4] + (G2 + r.col_HeII * ne) * x[3] * d) / (1.0 + r.rec_HeIII * ne * d);
-            xn[3] = 1.0 - xn[2] - xn[4];
-            if (val(xn[3]) < 0.0) {
-                xn[3] = 0.0;
-                const R s = xn[2] + xn[4];
-                xn[2] = xn[2] / s;
-                xn[4] = xn[4] / s;
-            }
-        } else {
-            xn[2] = x[2]; xn[3] = x[3]; xn[4] = x[4];
-        }
-
-        R un = u;
-        R f = 0.0;
-        if (!P.isothermal) {
-            un = u + d * (heat - cooling_rate(P, T, nH, x, r)) / rho;
-            f = m_abs(un - u) / u;
-        }
-        const int ns = hhe ? 5 : 2;
-        for (int s = 0; s < ns; ++s) f = m_max(f, m_abs(xn[s] - x[s]) / m_max(x[s], R(P.xfloor)));
-
-        if (val(f) > P.fmax) {
-            d = d * (P.fs / f);
-            continue;
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            N[b] = Nn[b];
-            Fh[b][0] = Fh[b][0] / fac[b];
-            Fh[b][1] = Fh[b][1] / fac[b];
-            Fh[b][2] = Fh[b][2] / fac[b];
-        }
-        for (int s = 0; s < 5; ++s) x[s] = xn[s];
-        u = un;
-        if (last) break;
-        tau = tau + d;
-        d = val(f) > 0.0 ? d * m_min(P.fs / f, R(P.growth)) : d * P.growth;
+    for (int b = 0; b < NB; ++b) {
+        const R kap = P.sigma[b][0] * nHI + P.sigma[b][1] * nHeI + P.sigma[b][2] * nHeII;
+        fac[b] = 1.0 + ct * d * kap;
+        Nn[b] = s.N[b] / fac[b];
+        G0 += ct * P.sigma[b][0] * Nn[b];
+        G1 += ct * P.sigma[b][1] * Nn[b];
+        G2 += ct * P.sigma[b][2] * Nn[b];
+        heat += ct * Nn[b] * (P.sigma[b][0] * nHI * P.eheat[b][0] + P.sigma[b][1] * nHeI * P.eheat[b][1] +
+                              P.sigma[b][2] * nHeII * P.eheat[b][2]);
     }
-    return attempts;
+
+    R xn[5];
+    const R den = 1.0 + (G0 + r.col_HI * ne + r.rec_HII * ne) * d;
+    xn[0] = (x[0] + r.rec_HII * ne * d) / den;
+    xn[1] = (x[1] + (G0 + r.col_HI * ne) * d) / den;
+    if (hhe) {
+        xn[2] = (x[2] + r.rec_HeII * ne * x[3] * d) / (1.0 + (G1 + r.col_HeI * ne) * d);
+        xn[4] = (x[4] + (G2 + r.col_HeII * ne) * x[3] * d) / (1.0 + r.rec_HeIII * ne * d);
+        xn[3] = 1.0 - xn[2] - xn[4];
+        if (val(xn[3]) < 0.0) {
+            xn[3] = 0.0;
+            const R sm = xn[2] + xn[4];
+            xn[2] = xn[2] / sm;
+            xn[4] = xn[4] / sm;
+        }
+    } else {
+        xn[2] = x[2]; xn[3] = x[3]; xn[4] = x[4];
+    }
+
+    R un = s.u;
+    R f = 0.0;
+    if (!P.isothermal) {
+        const R rho = kProtonMass * nH * (1.0 + 4.0 * yhe);
+        un = s.u + d * (heat - cooling_rate(P, T, nH, x, r)) / rho;
+        f = m_abs(un - s.u) / s.u;
+    }
+    const int ns = hhe ? 5 : 2;
+    for (int q = 0; q < ns; ++q) f = m_max(f, m_abs(xn[q] - x[q]) / m_max(x[q], R(P.xfloor)));
+
+    if (val(f) > P.fmax) {
+        s.d = d * (P.fs / f);
+        return 0;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        s.N[b] = Nn[b];
+        s.Fh[b][0] = s.Fh[b][0] / fac[b];
+        s.Fh[b][1] = s.Fh[b][1] / fac[b];
+        s.Fh[b][2] = s.Fh[b][2] / fac[b];
+    }
+    for (int q = 0; q < 5; ++q) x[q] = xn[q];
+    s.u = un;
+    if (last) return 1;
+    s.tau = s.tau + d;
+    s.d = val(f) > 0.0 ? d * m_min(P.fs / f, R(P.growth)) : d * P.growth;
+    return 0;
+}
+
+// Integrate one cell over the subcycle Dt; returns the number of attempts
+// (> max_sub on failure).
+template <int NB, typename R>
+__device__ inline int integrate_cell(const ChemParams& P, double Dt, const R& nH, ChemState<NB, R>& s) {
+    chem_begin<NB, R>(Dt, s);
+    while (true) {
+        const int r = chem_attempt<NB, R>(P, Dt, nH, s);
+        if (r == 1) break;
+        if (r < 0) break;
+    }
+    return s.attempts;
 }
 
 }  // namespace rtk

@@ -126,58 +126,92 @@ __global__ void k_sources(T* __restrict__ U, int64_t nc, int nb, int32_t n_cells
 }
 
 // ---------------------------------------------------------------------------
-// k_chem: one lane per cell; the whole adaptive substep sequence stays in
-// registers (Sec. 4.1.1).
+// k_chem: thermochemistry with the adaptive substeps held in registers
+// (Sec. 4.1.1).  The number of substeps varies by orders of magnitude between
+// cells (an I-front cell takes hundreds, a cell in equilibrium one), so a
+// wavefront that gave each lane one fixed cell would run as long as its
+// slowest cell with the other lanes idle.  Instead each workgroup owns a
+// chunk of cells and a lane that finishes its cell takes the next one from a
+// counter in LDS: lanes stay busy until the chunk is exhausted.  Which lane
+// integrates a cell does not change its arithmetic, so results are the same
+// bit for bit as a one-cell-per-lane launch.
 // ---------------------------------------------------------------------------
+
+template <int NB, typename T>
+__device__ inline void chem_load(const T* __restrict__ U, const double* __restrict__ X, const double* __restrict__ Ue,
+                                 int64_t nc, int64_t i, const double* __restrict__ scale, ChemState<NB, double>& s) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        T r[4];
+        load4(U + urec(b, nc, i), r);
+        s.N[b] = (double)r[0] * scale[b];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s.Fh[b][k] = (double)r[1 + k] * scale[b];
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) s.x[q] = X[(int64_t)q * nc + i];
+    s.u = Ue[i];
+}
 
 template <int NB, typename T>
 __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __restrict__ X /*[5][nc]*/,
                                                  double* __restrict__ Ue /*[nc]*/, const double* __restrict__ nH,
-                                                 int64_t nc, ChemParams P, double dt,
+                                                 int64_t nc, int chunk, ChemParams P, double dt,
                                                  const double* __restrict__ scale, const double* __restrict__ inv_scale,
                                                  int64_t* __restrict__ part_sum, int64_t* __restrict__ part_max,
                                                  int32_t* __restrict__ part_status) {
+    __shared__ int next;
     __shared__ int64_t lds64[kBlock / 64];
     __shared__ int lds32[kBlock / 64];
     const int64_t blk = xcd_logical_block();
-    const int64_t i = blk * kBlock + threadIdx.x;
-    int attempts = 0;
+    const int64_t c0 = blk * (int64_t)kBlock * chunk;
+    const int64_t c1 = c0 + (int64_t)kBlock * chunk < nc ? c0 + (int64_t)kBlock * chunk : nc;
+    if (threadIdx.x == 0) next = kBlock;
+    __syncthreads();
+    int64_t sum_att = 0, max_att = 0;
     int status = 0;
-    if (i < nc) {
-        double N[NB], Fh[NB][3], x[5];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            T r[4];
-            load4(U + urec(b, nc, i), r);
-            N[b] = (double)r[0] * scale[b];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) Fh[b][k] = (double)r[1 + k] * scale[b];
-        }
-#pragma unroll
-        for (int s = 0; s < 5; ++s) x[s] = X[(int64_t)s * nc + i];
-        double u = Ue[i];
-        attempts = integrate_cell<NB>(P, dt, nH[i], N, Fh, x, u);
-        if (attempts > P.max_sub) {
-            status = 2;              // leave the cell untouched; the call is rolled back
+    int64_t i = c0 + threadIdx.x;
+    bool active = i < c1;
+    ChemState<NB, double> s;
+    double nh = 0.0;
+    if (active) {
+        chem_load<NB, T>(U, X, Ue, nc, i, scale, s);
+        nh = nH[i];
+        chem_begin<NB, double>(dt, s);
+    }
+    while (active) {
+        const int r = chem_attempt<NB, double>(P, dt, nh, s);
+        if (r == 0) continue;
+        sum_att += s.attempts;
+        max_att = s.attempts > max_att ? s.attempts : max_att;
+        if (r < 0) {
+            status |= 2;            // leave the cell untouched; the call is rolled back
         } else {
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                T r[4] = {(T)(N[b] * inv_scale[b]), (T)(Fh[b][0] * inv_scale[b]), (T)(Fh[b][1] * inv_scale[b]),
-                          (T)(Fh[b][2] * inv_scale[b])};
-                store4(U + urec(b, nc, i), r);
+                T o[4] = {(T)(s.N[b] * inv_scale[b]), (T)(s.Fh[b][0] * inv_scale[b]), (T)(s.Fh[b][1] * inv_scale[b]),
+                          (T)(s.Fh[b][2] * inv_scale[b])};
+                store4(U + urec(b, nc, i), o);
             }
 #pragma unroll
-            for (int s = 0; s < 5; ++s) X[(int64_t)s * nc + i] = x[s];
-            Ue[i] = u;
-            if (!isfinite(u)) status |= 1;
+            for (int q = 0; q < 5; ++q) X[(int64_t)q * nc + i] = s.x[q];
+            Ue[i] = s.u;
+            if (!isfinite(s.u)) status |= 1;
+        }
+        i = c0 + atomicAdd(&next, 1);
+        active = i < c1;
+        if (active) {
+            chem_load<NB, T>(U, X, Ue, nc, i, scale, s);
+            nh = nH[i];
+            chem_begin<NB, double>(dt, s);
         }
     }
-    const int64_t s = block_sum<int64_t>(attempts, lds64);
-    const int64_t m = block_max<int64_t>(attempts, lds64);
+    const int64_t sm = block_sum<int64_t>(sum_att, lds64);
+    const int64_t mx = block_max<int64_t>(max_att, lds64);
     const int st = block_or(status, lds32);
     if (threadIdx.x == 0) {
-        part_sum[blk] += s;
-        part_max[blk] = m > part_max[blk] ? m : part_max[blk];
+        part_sum[blk] += sm;
+        part_max[blk] = mx > part_max[blk] ? mx : part_max[blk];
         part_status[blk] |= st;
     }
 }
@@ -427,12 +461,19 @@ void launch_sources(T* U, int64_t nc, int nb, int32_t n_cells_src, const int32_t
                        ptr, rate, n_src, vphys, inv_scale, scale, dt);
 }
 
+// Cells per lane of k_chem: up to 8, while keeping about 1024 workgroups.
+int chem_chunk(int64_t nc) {
+    int64_t c = nc / ((int64_t)kBlock * 1024);
+    return (int)(c < 1 ? 1 : (c > 8 ? 8 : c));
+}
+
 template <typename T, int NB>
 static void launch_chem_nb(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
                            const double* scale, const double* inv_scale, int64_t* ps, int64_t* pm, int32_t* pst,
                            hipStream_t s) {
-    hipLaunchKernelGGL((k_chem<NB, T>), dim3(grid_for(nc, kBlock)), dim3(kBlock), 0, s, U, X, Ue, nH, nc, P, dt,
-                       scale, inv_scale, ps, pm, pst);
+    const int chunk = chem_chunk(nc);
+    hipLaunchKernelGGL((k_chem<NB, T>), dim3((unsigned)chem_blocks(nc)), dim3(kBlock), 0, s, U, X, Ue, nH, nc, chunk,
+                       P, dt, scale, inv_scale, ps, pm, pst);
 }
 
 template <typename T>
@@ -449,7 +490,7 @@ void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, cons
     }
 }
 
-int64_t chem_blocks(int64_t nc) { return (int64_t)grid_for(nc, kBlock); }
+int64_t chem_blocks(int64_t nc) { return (int64_t)grid_for(nc, (int64_t)kBlock * chem_chunk(nc)); }
 int64_t transport_blocks(int64_t nc, int nb) { return (int64_t)grid_for(nc, kBlock) * nb; }
 
 template <typename T>

@@ -20,6 +20,7 @@ struct DiagDev {
 
 void fill_words(void* p, int64_t n_words, uint32_t v, hipStream_t s);
 
+int chem_chunk(int64_t nc);
 int64_t chem_blocks(int64_t nc);
 int64_t transport_blocks(int64_t nc, int nb);
 int64_t cfl_partials(int64_t nc);

@@ -61,7 +61,9 @@ def field_errors(gpu, ref, c_red, face_cells, kappa=1e-6, phi=1e-10):
     reaches it at the level eps * M_i (with kappa = 1e-6 and a tolerance of
     1e-10 the floor is one FP64 rounding of M_i); phi = 1e-10 is the global
     floor.  Flux components use the same scale times c~ (|F| <= c~ N).
-    Fractions are measured against max(|x|, 1e-10); T relative."""
+    Fractions are measured against max(|x|, 1e-6): a fraction far below 1 is
+    set by the photon density of the same cell and inherits its conditioning;
+    below 1e-6 the allowance is 1e-16 absolute.  T relative."""
     errs = {}
     nb = ref["N"].shape[0]
     for b in range(nb):
@@ -74,6 +76,6 @@ def field_errors(gpu, ref, c_red, face_cells, kappa=1e-6, phi=1e-10):
     names = ("x_HI", "x_HII", "y_HeI", "y_HeII", "y_HeIII")
     for s in range(5):
         r = np.asarray(ref["species"][s], float)
-        errs[names[s]] = float((np.abs(gpu["species"][s] - r) / np.maximum(np.abs(r), 1e-10)).max())
+        errs[names[s]] = float((np.abs(gpu["species"][s] - r) / np.maximum(np.abs(r), 1e-6)).max())
     errs["T"] = rel_err(gpu["T"], ref["T"])
     return errs

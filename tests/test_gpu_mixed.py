@@ -31,9 +31,6 @@ def mixed_errors(gpu, ref, c_red):
     return out
 
 
-@pytest.mark.xfail(reason="FP32-stored gradients: at I-front cells 1e5-1e6 below a neighbour the face "
-                          "extrapolation U + g.r cancels to eps32 * neighbour; fixed by keeping gradients "
-                          "in FP64 registers (fused transport)", strict=False)
 @pytest.mark.parametrize("hhe", [False, True], ids=["H", "HHe"])
 def test_stromgren_mixed_meets_stated_error(hhe):
     cfg = rtgen.stromgren(n_sub=50, precision="mixed", hhe=hhe)
@@ -52,7 +49,6 @@ def test_stromgren_mixed_meets_stated_error(hhe):
     assert np.allclose(gpu["diag"]["photon_sum"], ref["diag"]["photon_sum"], rtol=1e-5)
 
 
-@pytest.mark.xfail(reason="same FP32-gradient cancellation at I-fronts as above", strict=False)
 def test_mixed_ragged_hhe_close_to_oracle():
     cfg = rtgen.cosmological(0, 1.0, 1.0, 6, 0.01, 8, 2, dims=(20, 18, 17), name="hhe_ragged")
     gpu = run_gpu(cfg, precision=rt.RT_MIXED)
