@@ -30,7 +30,6 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ("k_sources", "k_chem", "k_facestate", "k_flux", "k_reduce")
 TRAFFIC_FILE = ROOT / "profiles" / "traffic.json"
 
 
@@ -48,6 +47,12 @@ def algorithmic_bytes(kernel: str, nc: int, nb: int, nf: int, n_sides: int, n_sr
         # fields (4) in, one 4-value face state per face side out;
         # cell record (M^-1, V, V/n_f), face record (12 values), neighbour + face index
         return nb * (4 * nc + 4 * n_sides) * p + nc * 8 * g + nf * 12 * g + n_sides * 8
+    if kernel == "k_transport":
+        # fused gradient + face states + fluxes: fields in and out; cell and
+        # face records; neighbour, face and opposite-slot index per face side
+        # (the face states stay in LDS; the halo tables, about a tenth of
+        # the side count, are not counted)
+        return nb * 8 * nc * p + nc * 8 * g + nf * 12 * g + n_sides * 12
     if kernel == "k_flux":
         # fields in and out, face states of every face side in; cell volume,
         # face record, neighbour + face + opposite-side index
@@ -67,9 +72,11 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def timed_run(rt, mesh, cfg, precision, steps, warmup, torch):
+def timed_run(rt, mesh, cfg, precision, steps, warmup, torch, transport=None):
     """Warm up on a clone, then time `steps` subcycles from the initial state."""
     state = rt.State.from_config(mesh, cfg, precision=precision)
+    if transport is not None:
+        state.set_transport(transport)
     stream = torch.cuda.current_stream()
     if warmup > 0:
         w = state.clone()
@@ -82,7 +89,7 @@ def timed_run(rt, mesh, cfg, precision, steps, warmup, torch):
     state.subcycle(steps, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = {KERNELS[k]: rt.rt_profile_read(state.h, k) for k in range(len(KERNELS))}
+    prof = {rt.KERNEL_NAMES[k]: rt.rt_profile_read(state.h, k) for k in range(rt.RT_N_KERNELS)}
     return state, t1 - t0, prof
 
 
@@ -113,8 +120,7 @@ def main() -> int:
                          "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the design of one is in "
-              "DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only (there is no multi-GPU path); run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
@@ -188,6 +194,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"throughput_{args.n}", "cells": nc, "bins": nb, "sources": int(n_src),
                    "subcycles": args.steps, "order": "hilbert", "precision": "mixed", "c_reduced": "0.1c",
+                   "transport": "fused" if st_mixed.fused else "split",
                    "sigma_ln": 1.5},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic},
@@ -197,9 +204,17 @@ def main() -> int:
     if not args.no_extras:
         fields_mixed = st_mixed.fields()
         st_mixed.close()
+        if out["config"]["transport"] == "fused":
+            log(f"mixed, hilbert, split transport: {args.steps} subcycles")
+            st_s, t_s, prof_s = timed_run(rt, mesh, cfg, rt.RT_MIXED, args.steps, args.warmup, torch,
+                                          transport=rt.RT_TRANSPORT_SPLIT)
+            st_s.close()
+            out["split_transport_value"] = nc * nb * args.steps / t_s
+            out["kernels_mixed_split"] = kernel_table(prof_s, 4, 4)
         log(f"fp64, hilbert: {args.steps} subcycles")
         st64, t64, prof64 = timed_run(rt, mesh, cfg, rt.RT_FP64, args.steps, args.warmup, torch)
         f64 = st64.fields()
+        st64_fused = st64.fused
         st64.close()
         v64 = nc * nb * args.steps / t64
         N64, Nm = f64["N"], fields_mixed["N"]
@@ -231,12 +246,14 @@ def main() -> int:
             "T_rel_max": float((np.abs(fields_mixed["T"] - f64["T"]) / f64["T"]).max()),
         }
         out["kernels_fp64"] = kernel_table(prof64, 8, 8)
+        out["fp64_transport"] = "fused" if st64_fused else "split"
         del fields_mixed, f64
         mesh.close()
         log("random cell order (mixed)")
         cfg_r = rtgen.random_order(cfg)
         mesh_r = rt.Mesh(cfg_r["mesh"])
         st_r, t_r, prof_r = timed_run(rt, mesh_r, cfg_r, rt.RT_MIXED, args.steps, args.warmup, torch)
+        out["random_order_transport"] = "fused" if st_r.fused else "split"
         st_r.close()
         mesh_r.close()
         out["random_order_value"] = nc * nb * args.steps / t_r

@@ -79,7 +79,17 @@ extern "C" {
 #define RT_KERNEL_GRADIENT 2
 #define RT_KERNEL_FLUX     3
 #define RT_KERNEL_REDUCE   4
-#define RT_N_KERNELS       5
+#define RT_KERNEL_TRANSPORT 5   /* fused gradient + face states + fluxes */
+#define RT_N_KERNELS       6
+
+/* Transport path (rt_state_set_transport).  The split path runs the
+ * gradient/face-state kernel and the flux kernel with the face states in
+ * device memory; the fused path runs both per 256-cell tile in one kernel
+ * with the face states in LDS.  Both give the same fluxes to rounding. */
+#define RT_TRANSPORT_AUTO  0   /* fused when the tiles fit in LDS and their halos are
+                                  small (a locality-preserving cell order), else split */
+#define RT_TRANSPORT_FUSED 1   /* fused whenever the tiles fit in LDS */
+#define RT_TRANSPORT_SPLIT 2   /* always split */
 
 /* ---- parameters ------------------------------------------------------ */
 /* Every constant the paper leaves open.  rt_params_default fills the values
@@ -131,6 +141,11 @@ const char* rt_last_error(void);
  * 1e5, gamma = 5/3, zero cross-sections). */
 int rt_params_default(int32_t nb, rt_params* p);
 
+/* `device` value of rt_mesh_create that builds and validates the mesh's
+ * host tables only (for inspection with rt_mesh_table; no state can be
+ * created on such a mesh). */
+#define RT_DEVICE_HOST_ONLY (-1)
+
 /* Create a static mesh on HIP device `device`.
  *   volume [nc] cm^3, centre [3][nc] cm (the point gradients are taken about,
  *   s_i of Sec. 2.3.2), face_cells [2][nf] (L, R) cell indices, area [nf] cm^2,
@@ -147,6 +162,30 @@ int rt_mesh_create(int64_t n_cells, const double* volume, const double* centre,
                    const double* normal, const double* face_centre, const double box[3],
                    int device, rt_mesh** out);
 int rt_mesh_destroy(rt_mesh* mesh);
+
+/* Read-only view of one of the mesh's int32 index tables (host memory owned
+ * by the mesh, valid until rt_mesh_destroy).  Sliced ELL with 64-cell
+ * slices: slice s holds sdeg[s] slots from sptr[s]; slot k of cell i is entry
+ * sptr[i/64] + 64 k + i%64, with nbr (neighbour, -1 for padding), fsf (face
+ * index f, or ~f when the cell is the face's R cell) and opp (the entry of
+ * the same face in the neighbour's slots).  Tiles of the fused transport
+ * kernel (cells 256 t .. 256 t + 255, face states in LDS): lds_opp (LDS slot
+ * of the opposite state of each entry; the tile's own entries occupy slots
+ * 0 .. ptr[4t+4] - ptr[4t] - 1 in entry order, its halo sides follow),
+ * halo_ptr [n_tiles + 1] into halo_cell (cells outside the tile that share
+ * a face with it), hside_ptr [n_halo + 1] into hside_entry (the entries of
+ * each halo cell that face the tile, in the order of their LDS slots). */
+#define RT_TABLE_NBR         0
+#define RT_TABLE_FSF         1
+#define RT_TABLE_OPP         2
+#define RT_TABLE_SPTR        3
+#define RT_TABLE_SDEG        4
+#define RT_TABLE_LDS_OPP     5
+#define RT_TABLE_HALO_PTR    6
+#define RT_TABLE_HALO_CELL   7
+#define RT_TABLE_HSIDE_PTR   8
+#define RT_TABLE_HSIDE_ENTRY 9
+int rt_mesh_table(const rt_mesh* mesh, int table, const int32_t** data, int64_t* length);
 
 /* Create a radiation + gas state on a mesh.
  *   precision: RT_FP64 or RT_MIXED.
@@ -193,6 +232,14 @@ int rt_state_set_field(rt_state* state, int field, const double* in, int in_on_d
 /* Sizes and the subcycle length of a state. */
 int rt_state_info(const rt_state* state, int64_t* n_cells, int32_t* nb, int64_t* n_src,
                   int32_t* precision, double* dt_cfl);
+
+/* Choose the transport path of a state (RT_TRANSPORT_*; default AUTO).
+ * RT_ESTATE if RT_TRANSPORT_FUSED is asked for and the mesh's tiles do not
+ * fit in the device's LDS at the state's precision.  rt_state_transport
+ * reports the path the next subcycle takes (1 fused, 0 split).  The adjoint
+ * recomputes its forward pass on the split path. */
+int rt_state_set_transport(rt_state* state, int mode);
+int rt_state_transport(const rt_state* state, int32_t* fused);
 
 /* Diagnostics of the last rt_subcycle call. */
 int rt_state_diagnostics(const rt_state* state, rt_diag* out);

@@ -61,7 +61,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard(const double* __restrict__
     load4(U + urec(b, nc, i), ui);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int c0 = 0, c1 = 0, c2 = 0;
-    cell_flux_sum<double, double>(i, b, nc, n_entries, U, FV, geo, sell, cdt, ui[0], acc, c0, c1, c2);
+    const GlobalFaceStates<double> fsv{FV + (int64_t)b * n_entries * 4, sell.opp};
+    cell_flux_sum<double, double>(i, b, nc, U, fsv, geo, sell, cdt, ui[0], acc, c0, c1, c2);
     const double coef = cdt / geo.cell[i * kCellRec + 6];
     Dual<4> un[4];
 #pragma unroll
@@ -467,6 +468,10 @@ extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int
         rt_state* s;
         ~Owner() { if (s) rt_state_destroy(s); }
     } owner{w};
+    // The adjoint recomputes the forward pass on the split path, whose face
+    // states it differentiates.
+    w->transport_mode = RT_TRANSPORT_SPLIT;
+    if ((rc = w->ensure_face_states())) return rc;
     const int64_t nc = w->nc;
     const int nb = w->nb;
     const double dt = w->dt_cfl;

@@ -85,6 +85,7 @@ bool finite_all(const std::vector<double>& v) {
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev) {
+        if (dev < 0) return;    // host-only mesh: no device to select
         if (hipGetDevice(&prev) != hipSuccess) prev = -1;
         if (prev != dev) (void)hipSetDevice(dev);
     }
@@ -173,6 +174,56 @@ int rt_mesh::build_float_geometry() {
     if ((rc = d_cell32.upload(c.data(), c.size() * 4))) return rc;
     geo32_ready = true;
     return RT_OK;
+}
+
+// Tiles of 256 cells for the fused transport kernel: the LDS slot of every
+// face side's opposite state, and the halo cells with the sides they
+// contribute, grouped per tile in (cell, entry) order.
+void rt_mesh::build_tiles() {
+    const int64_t ns = (int64_t)sdeg.size();
+    const int64_t ntiles = (nc + kBlock - 1) / kBlock;
+    lds_opp.assign(n_entries, -1);
+    halo_ptr.assign(ntiles + 1, 0);
+    halo_cell.clear();
+    hside_ptr.clear();
+    hside_entry.clear();
+    tile_max_sides = 0;
+    struct Ext {
+        int32_t j, eo;
+        int64_t e;
+    };
+    std::vector<Ext> ext;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int64_t c0 = t * kBlock, c1 = std::min<int64_t>(nc, c0 + kBlock);
+        const int64_t e0 = sptr[t * kTileSlices];
+        const int64_t tile_sides = (int64_t)sptr[std::min<int64_t>(ns, (t + 1) * kTileSlices)] - e0;
+        ext.clear();
+        for (int64_t i = c0; i < c1; ++i) {
+            const int64_t sl = i / kSlice;
+            for (int64_t k = 0; k < sdeg[sl]; ++k) {
+                const int64_t e = sptr[sl] + k * kSlice + i % kSlice;
+                const int32_t j = nbr[e];
+                if (j < 0) continue;
+                if (j >= c0 && j < c1) lds_opp[e] = (int32_t)(opp[e] - e0);
+                else ext.push_back({j, opp[e], e});
+            }
+        }
+        std::stable_sort(ext.begin(), ext.end(),
+                         [](const Ext& a, const Ext& b) { return a.j != b.j ? a.j < b.j : a.eo < b.eo; });
+        const int64_t hs0 = (int64_t)hside_entry.size();
+        for (size_t q = 0; q < ext.size(); ++q) {
+            if (q == 0 || ext[q].j != ext[q - 1].j) {
+                halo_cell.push_back(ext[q].j);
+                hside_ptr.push_back((int32_t)hside_entry.size());
+            }
+            lds_opp[ext[q].e] = (int32_t)(tile_sides + (int64_t)hside_entry.size() - hs0);
+            hside_entry.push_back(ext[q].eo);
+        }
+        halo_ptr[t + 1] = (int32_t)halo_cell.size();
+        tile_max_sides = std::max<int64_t>(tile_max_sides, tile_sides + (int64_t)ext.size());
+    }
+    hside_ptr.push_back((int32_t)hside_entry.size());
+    halo_ratio = (double)halo_cell.size() / (double)nc;
 }
 
 extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const double* centre, int64_t n_faces,
@@ -346,6 +397,16 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
     }
     m->max_deg = *std::max_element(deg.begin(), deg.end());
     m->deg = std::move(deg);
+    if ((int64_t)m->n_entries + (int64_t)2 * nf >= INT32_MAX / 2) {
+        delete m;
+        return rt_fail(RT_EINVAL, "too many face sides for the tile tables");
+    }
+    m->build_tiles();
+    if (device == RT_DEVICE_HOST_ONLY) {
+        m->refs.store(1);
+        *out = m;
+        return RT_OK;
+    }
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess) {
@@ -365,9 +426,23 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
         (rc = m->d_fsf.upload(m->fsf.data(), m->fsf.size() * 4)) ||
         (rc = m->d_opp.upload(m->opp.data(), m->opp.size() * 4)) ||
         (rc = m->d_sptr.upload(m->sptr.data(), m->sptr.size() * 4)) ||
-        (rc = m->d_sdeg.upload(m->sdeg.data(), m->sdeg.size() * 4))) {
+        (rc = m->d_sdeg.upload(m->sdeg.data(), m->sdeg.size() * 4)) ||
+        (rc = m->d_lds_opp.upload(m->lds_opp.data(), m->lds_opp.size() * 4)) ||
+        (rc = m->d_halo_ptr.upload(m->halo_ptr.data(), m->halo_ptr.size() * 4)) ||
+        (rc = m->d_halo_cell.upload(m->halo_cell.data(), m->halo_cell.size() * 4)) ||
+        (rc = m->d_hside_ptr.upload(m->hside_ptr.data(), m->hside_ptr.size() * 4)) ||
+        (rc = m->d_hside_entry.upload(m->hside_entry.data(), m->hside_entry.size() * 4))) {
         delete m;
         return rc;
+    }
+    {
+        // LDS available to one workgroup, less the fused kernel's static use.
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+            (void)hipGetLastError();
+            lds = 0;
+        }
+        m->lds_limit = lds > 1024 ? (size_t)lds - 1024 : 0;
     }
     // CFL length min_i (3V/4pi)^(1/3) by the device min-reduction.
     {
@@ -390,6 +465,27 @@ void rt_mesh_release(rt_mesh* m) {
         DeviceGuard dg(m->device);
         delete m;
     }
+}
+
+extern "C" int rt_mesh_table(const rt_mesh* m, int table, const int32_t** data, int64_t* length) {
+    if (!m || !data || !length) return rt_fail(RT_EINVAL, "null argument");
+    const std::vector<int32_t>* v = nullptr;
+    switch (table) {
+        case RT_TABLE_NBR: v = &m->nbr; break;
+        case RT_TABLE_FSF: v = &m->fsf; break;
+        case RT_TABLE_OPP: v = &m->opp; break;
+        case RT_TABLE_SPTR: v = &m->sptr; break;
+        case RT_TABLE_SDEG: v = &m->sdeg; break;
+        case RT_TABLE_LDS_OPP: v = &m->lds_opp; break;
+        case RT_TABLE_HALO_PTR: v = &m->halo_ptr; break;
+        case RT_TABLE_HALO_CELL: v = &m->halo_cell; break;
+        case RT_TABLE_HSIDE_PTR: v = &m->hside_ptr; break;
+        case RT_TABLE_HSIDE_ENTRY: v = &m->hside_entry; break;
+        default: return rt_fail(RT_EINVAL, "table %d", table);
+    }
+    *data = v->data();
+    *length = (int64_t)v->size();
+    return RT_OK;
 }
 
 extern "C" int rt_mesh_destroy(rt_mesh* m) {
@@ -464,12 +560,17 @@ static double pow2_at_least(double m) {
 
 size_t rt_state::tbytes() const { return precision == RT_MIXED ? 4 : 8; }
 
+// The face-state array of the split path, allocated on first use.
+int rt_state::ensure_face_states() {
+    if (FV.ptr) return RT_OK;
+    return FV.alloc((size_t)nb * 4 * mesh->n_entries * tbytes());
+}
+
 int rt_state::alloc_buffers() {
     const size_t t = tbytes();
     int rc;
     if ((rc = U[0].alloc((size_t)nb * 4 * nc * t)) || (rc = U[1].alloc((size_t)nb * 4 * nc * t)) ||
-        (rc = FV.alloc((size_t)nb * 4 * mesh->n_entries * t)) || (rc = X.alloc(5 * nc * 8)) ||
-        (rc = Ue.alloc(nc * 8)) || (rc = nH.alloc(nc * 8)))
+        (rc = X.alloc(5 * nc * 8)) || (rc = Ue.alloc(nc * 8)) || (rc = nH.alloc(nc * 8)))
         return rc;
     n_fblk = transport_blocks(nc, nb);
     n_cblk = chem_blocks(nc);
@@ -528,6 +629,7 @@ extern "C" int rt_state_create(const rt_mesh* mesh_c, const rt_params* params, i
     *out = nullptr;
     if (!mesh_c) return rt_fail(RT_EINVAL, "null mesh");
     rt_mesh* mesh = const_cast<rt_mesh*>(mesh_c);
+    if (mesh->device < 0) return rt_fail(RT_EDEVICE, "the mesh was created host-only");
     int rc;
     if ((rc = check_params(params))) return rc;
     if (precision != RT_FP64 && precision != RT_MIXED) return rt_fail(RT_EINVAL, "precision=%d", precision);
@@ -670,6 +772,7 @@ extern "C" int rt_state_clone(const rt_state* src, rt_state** out) {
     s->params = src->params;
     s->cp = src->cp;
     s->precision = src->precision;
+    s->transport_mode = src->transport_mode;
     s->nb = src->nb;
     s->nc = src->nc;
     s->dt_cfl = src->dt_cfl;
@@ -804,16 +907,71 @@ void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double d
     s->prof_end(st);
 }
 
+TileView rt_tiles(const rt_mesh* m) {
+    return TileView{(const int32_t*)m->d_lds_opp.ptr, (const int32_t*)m->d_halo_ptr.ptr,
+                    (const int32_t*)m->d_halo_cell.ptr, (const int32_t*)m->d_hside_ptr.ptr,
+                    (const int32_t*)m->d_hside_entry.ptr, (int64_t)m->sdeg.size()};
+}
+
+// Halo cells per cell above which AUTO keeps the split path: the fused
+// kernel computes the gradient of every halo cell once more per tile, so a
+// cell order without locality (halo ~ all face neighbours) would multiply
+// the gradient work.
+static constexpr double kMaxHaloRatio = 2.0;
+
+bool rt_state::fused() const {
+    if (transport_mode == RT_TRANSPORT_SPLIT) return false;
+    if (mesh->tile_lds_bytes(tbytes()) > mesh->lds_limit) return false;
+    return transport_mode == RT_TRANSPORT_FUSED || mesh->halo_ratio <= kMaxHaloRatio;
+}
+
+void rt_step_transport(rt_state* s, const void* U, void* Un, double dt, hipStream_t st) {
+    const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
+    const size_t lds = s->mesh->tile_lds_bytes(s->tbytes());
+    s->prof_begin(RT_KERNEL_TRANSPORT, st);
+    if (s->precision == RT_MIXED)
+        launch_transport<float>((const float*)U, (float*)Un, s->nc, s->nb, geom_view<float>(s->mesh),
+                                rt_sell(s->mesh), rt_tiles(s->mesh), lds, s->params.use_limiter, cdt,
+                                (double*)s->part_nv.ptr, (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
+    else
+        launch_transport<double>((const double*)U, (double*)Un, s->nc, s->nb, geom_view<double>(s->mesh),
+                                 rt_sell(s->mesh), rt_tiles(s->mesh), lds, s->params.use_limiter, cdt,
+                                 (double*)s->part_nv.ptr, (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
+    s->prof_end(st);
+}
+
 void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st) {
+    const bool fused = s->fused();
     for (int it = 0; it < n; ++it) {
         void* U = s->U[s->cur].ptr;
         void* Un = s->U[s->cur ^ 1].ptr;
         rt_step_sources(s, U, dt, st);
         rt_step_chem(s, U, (double*)s->X.ptr, (double*)s->Ue.ptr, dt, st);
-        rt_step_facestate(s, U, s->FV.ptr, st);
-        rt_step_flux(s, U, s->FV.ptr, Un, dt, st);
+        if (fused) {
+            rt_step_transport(s, U, Un, dt, st);
+        } else {
+            rt_step_facestate(s, U, s->FV.ptr, st);
+            rt_step_flux(s, U, s->FV.ptr, Un, dt, st);
+        }
         s->cur ^= 1;
     }
+}
+
+extern "C" int rt_state_set_transport(rt_state* s, int mode) {
+    if (!s) return rt_fail(RT_EINVAL, "null state");
+    if (mode != RT_TRANSPORT_AUTO && mode != RT_TRANSPORT_FUSED && mode != RT_TRANSPORT_SPLIT)
+        return rt_fail(RT_EINVAL, "transport mode %d", mode);
+    if (mode == RT_TRANSPORT_FUSED && s->mesh->tile_lds_bytes(s->tbytes()) > s->mesh->lds_limit)
+        return rt_fail(RT_ESTATE, "fused transport needs %zu bytes of LDS per workgroup, the device has %zu",
+                       s->mesh->tile_lds_bytes(s->tbytes()), s->mesh->lds_limit);
+    s->transport_mode = mode;
+    return RT_OK;
+}
+
+extern "C" int rt_state_transport(const rt_state* s, int32_t* fused) {
+    if (!s || !fused) return rt_fail(RT_EINVAL, "null argument");
+    *fused = s->fused() ? 1 : 0;
+    return RT_OK;
 }
 
 void rt_reset_partials(rt_state* s, hipStream_t st) {
@@ -856,6 +1014,7 @@ extern "C" int rt_subcycle(rt_state* s, int n, double dt, void* hip_stream) {
     RT_HIP(hipMemcpyAsync(s->bU.ptr, s->U[cur0].ptr, ubytes, hipMemcpyDeviceToDevice, st));
     RT_HIP(hipMemcpyAsync(s->bX.ptr, s->X.ptr, 5 * s->nc * 8, hipMemcpyDeviceToDevice, st));
     RT_HIP(hipMemcpyAsync(s->bUe.ptr, s->Ue.ptr, s->nc * 8, hipMemcpyDeviceToDevice, st));
+    if (!s->fused() && (rc = s->ensure_face_states())) return rc;
     rt_reset_partials(s, st);
     rt_run_subcycles(s, n, step, st);
     s->prof_begin(RT_KERNEL_REDUCE, st);

@@ -37,27 +37,44 @@ constexpr double kTHI = 157807.0;
 constexpr double kTHeI = 285335.0;
 constexpr double kTHeII = 631515.0;
 
+// Every temperature-dependent coefficient of the network: the rates, and
+// the cooling per pair of colliding species (erg cm^3/s), so that the
+// cooling rate is a sum of products with the current densities.  Powers of
+// the same base share one logarithm: x^p = exp(p ln x).
 template <typename R>
 struct Rates {
     R rec_HII, rec_HeII, rec_HeIII;    // recombination coefficients, cm^3/s
     R col_HI, col_HeI, col_HeII;       // collisional ionisation, cm^3/s
+    // cooling coefficients: recombination of H II, He II, He III, dielectronic
+    // recombination of He II, collisional excitation of H I and He II, and
+    // free-free emission per ion charge weight
+    R cr_HII, cr_HeII, cr_HeIII, cd_HeII, ce_HI, ce_HeII, cff;
 };
 
-// Case-B hydrogenic recombination of Hui & Gnedin in terms of
-// lambda = 2 T_ion / T.
+// x^p from ln x.
 template <typename R>
-__device__ inline R hg_rec_caseB(const R& lam) {
-    return 2.753e-14 * m_pow(lam, 1.5) / m_pow(1.0 + m_pow(lam * (1.0 / 2.740), 0.407), 2.242);
+__device__ inline R pow_ln(const R& lnx, double p) {
+    return m_exp(p * lnx);
+}
+
+// Case-B hydrogenic recombination of Hui & Gnedin in terms of
+// lambda = 2 T_ion / T (ln lambda given).
+template <typename R>
+__device__ inline R hg_rec_caseB(const R& ln_lam) {
+    return 2.753e-14 * pow_ln(ln_lam, 1.5) / m_pow(1.0 + pow_ln(ln_lam - 1.007957920399979 /* ln 2.740 */, 0.407), 2.242);
 }
 // Matching case-B recombination cooling coefficient (erg cm^3/s).
 template <typename R>
-__device__ inline R hg_rec_cool_caseB(const R& T, const R& lam) {
-    return 3.435e-30 * T * m_pow(lam, 1.970) / m_pow(1.0 + m_pow(lam * (1.0 / 2.250), 0.376), 3.720);
+__device__ inline R hg_rec_cool_caseB(const R& T, const R& ln_lam) {
+    return 3.435e-30 * T * pow_ln(ln_lam, 1.970) /
+           m_pow(1.0 + pow_ln(ln_lam - 0.8109302162163288 /* ln 2.250 */, 0.376), 3.720);
 }
-// Temperature shape of dielectronic He II recombination (Cen 1992).
+// Hui & Gnedin collisional ionisation, A T^-3/2 e^(-lambda/2) lambda^-a /
+// (1 + (lambda/l0)^b)^c.
 template <typename R>
-__device__ inline R cen_dielectronic(const R& T) {
-    return m_pow(T, -1.5) * m_exp(-470000.0 / T) * (1.0 + 0.3 * m_exp(-94000.0 / T));
+__device__ inline R hg_col(double A, const R& t32, const R& lam, const R& ln_lam, double a, double ln_l0, double b,
+                           double c) {
+    return A * t32 * m_exp(-0.5 * lam) * pow_ln(ln_lam, -a) / m_pow(1.0 + pow_ln(ln_lam - ln_l0, b), c);
 }
 
 template <typename R>
@@ -67,48 +84,58 @@ __device__ inline Rates<R> network_rates(const ChemParams& P, R T) {
         r.rec_HII = P.alpha_B;
         r.rec_HeII = 0.0; r.rec_HeIII = 0.0;
         r.col_HI = 0.0; r.col_HeI = 0.0; r.col_HeII = 0.0;
+        r.cr_HII = 0.0; r.cr_HeII = 0.0; r.cr_HeIII = 0.0; r.cd_HeII = 0.0;
+        r.ce_HI = 0.0; r.ce_HeII = 0.0; r.cff = 0.0;
         return r;
     }
     T = m_max(T, R(1.0));
-    const R lH = 2.0 * kTHI / T, lHe1 = 2.0 * kTHeI / T, lHe2 = 2.0 * kTHeII / T;
-    const R t32 = m_pow(T, -1.5);
-    r.rec_HII = hg_rec_caseB(lH);
-    r.rec_HeII = 1.26e-14 * m_pow(lHe1, 0.75) + 1.9e-3 * cen_dielectronic(T);
-    r.rec_HeIII = 2.0 * hg_rec_caseB(lHe2);
-    r.col_HI = 21.11 * t32 * m_exp(-0.5 * lH) * m_pow(lH, -1.089) /
-               m_pow(1.0 + m_pow(lH * (1.0 / 0.354), 0.874), 1.101);
-    r.col_HeI = 32.38 * t32 * m_exp(-0.5 * lHe1) * m_pow(lHe1, -1.146) /
-                m_pow(1.0 + m_pow(lHe1 * (1.0 / 0.416), 0.987), 1.056);
-    r.col_HeII = 19.95 * t32 * m_exp(-0.5 * lHe2) * m_pow(lHe2, -1.089) /
-                 m_pow(1.0 + m_pow(lHe2 * (1.0 / 0.553), 0.735), 1.275);
+    const R iT = 1.0 / T;
+    const R lnT = m_log(T);
+    const R lH = (2.0 * kTHI) * iT, lHe1 = (2.0 * kTHeI) * iT, lHe2 = (2.0 * kTHeII) * iT;
+    const R ln_lH = 12.662275226919286 /* ln(2 T_HI) */ - lnT;
+    const R ln_lHe1 = 13.254566388120152 /* ln(2 T_HeI) */ - lnT;
+    const R ln_lHe2 = 14.049024154019651 /* ln(2 T_HeII) */ - lnT;
+    const R t32 = pow_ln(lnT, -1.5);
+    const R sqT = m_sqrt(T);
+    // Cen (1992) dielectronic recombination shape T^-3/2 e^(-470000/T) (1 + 0.3 e^(-94000/T))
+    const R diel = t32 * m_exp(-470000.0 * iT) * (1.0 + 0.3 * m_exp(-94000.0 * iT));
+    const R rHe1 = 1.26e-14 * pow_ln(ln_lHe1, 0.75);
+    r.rec_HII = hg_rec_caseB(ln_lH);
+    r.rec_HeII = rHe1 + 1.9e-3 * diel;
+    r.rec_HeIII = 2.0 * hg_rec_caseB(ln_lHe2);
+    r.col_HI = hg_col(21.11, t32, lH, ln_lH, 1.089, -1.0384583658483626 /* ln 0.354 */, 0.874, 1.101);
+    r.col_HeI = hg_col(32.38, t32, lHe1, ln_lHe1, 1.146, -0.8770700187208739 /* ln 0.416 */, 0.987, 1.056);
+    r.col_HeII = hg_col(19.95, t32, lHe2, ln_lHe2, 1.089, -0.5923972774598022 /* ln 0.553 */, 0.735, 1.275);
+    const R sq = 1.0 + 0.0031622776601683794 * sqT;   // 1 + (T / 1e5)^1/2
+    const R isq = 1.0 / sq;
+    r.cr_HII = hg_rec_cool_caseB(T, ln_lH);
+    r.cr_HeII = kBoltz * T * rHe1;
+    r.cr_HeIII = 8.0 * hg_rec_cool_caseB(T, ln_lHe2);
+    r.cd_HeII = 1.24e-13 * diel;
+    r.ce_HI = 7.5e-19 * m_exp(-118348.0 * iT) * isq;
+    r.ce_HeII = 5.54e-17 * pow_ln(lnT, -0.397) * m_exp(-473638.0 * iT) * isq;
+    const R lg = 0.43429448190325182765 * lnT - 5.5;    // log10 T - 5.5
+    r.cff = 1.42e-27 * (1.1 + 0.34 * m_exp(-lg * lg * (1.0 / 3.0))) * sqT;
     return r;
 }
 
 // Radiative cooling per volume (erg cm^-3 s^-1).  x = x_HI, x_HII, y_I, y_II, y_III.
 template <typename R>
-__device__ inline R cooling_rate(const ChemParams& P, R T, const R& nH, const R* x, const Rates<R>& r) {
+__device__ inline R cooling_rate(const ChemParams& P, const R& nH, const R* x, const Rates<R>& r) {
     if (P.rate_set == 0) return R(0.0);
-    T = m_max(T, R(1.0));
     const double yhe = P.yhe;
     const R ne = nH * (x[1] + yhe * (x[3] + 2.0 * x[4]));
     const R nHI = nH * x[0], nHII = nH * x[1];
     const R nHe = yhe * nH;
     const R nHeI = nHe * x[2], nHeII = nHe * x[3], nHeIII = nHe * x[4];
-    const R lH = 2.0 * kTHI / T, lHe1 = 2.0 * kTHeI / T, lHe2 = 2.0 * kTHeII / T;
-    const R sq = 1.0 + m_sqrt(T * 1.0e-5);
     // recombination (radiative, case B) and dielectronic recombination
-    R L = hg_rec_cool_caseB(T, lH) * nHII
-        + kBoltz * T * 1.26e-14 * m_pow(lHe1, 0.75) * nHeII
-        + 8.0 * hg_rec_cool_caseB(T, lHe2) * nHeIII
-        + 1.24e-13 * cen_dielectronic(T) * nHeII;
+    R L = r.cr_HII * nHII + r.cr_HeII * nHeII + r.cr_HeIII * nHeIII + r.cd_HeII * nHeII;
     // collisional ionisation: one ionisation energy per event
     L += kBoltz * (kTHI * r.col_HI * nHI + kTHeI * r.col_HeI * nHeI + kTHeII * r.col_HeII * nHeII);
     // collisional excitation of H I and He II
-    L += 7.5e-19 * m_exp(-118348.0 / T) / sq * nHI + 5.54e-17 * m_pow(T, -0.397) * m_exp(-473638.0 / T) / sq * nHeII;
+    L += r.ce_HI * nHI + r.ce_HeII * nHeII;
     // free-free emission
-    const R lg = m_log10(T) - 5.5;
-    const R gff = 1.1 + 0.34 * m_exp(-lg * lg * (1.0 / 3.0));
-    L += 1.42e-27 * gff * m_sqrt(T) * (nHII + nHeII + 4.0 * nHeIII);
+    L += r.cff * (nHII + nHeII + 4.0 * nHeIII);
     return ne * L;
 }
 
@@ -199,7 +226,7 @@ __device__ inline int chem_attempt(const ChemParams& P, double Dt, const R& nH, 
     R f = 0.0;
     if (!P.isothermal) {
         const R rho = kProtonMass * nH * (1.0 + 4.0 * yhe);
-        un = s.u + d * (heat - cooling_rate(P, T, nH, x, r)) / rho;
+        un = s.u + d * (heat - cooling_rate(P, nH, x, r)) / rho;
         f = m_abs(un - s.u) / s.u;
     }
     const int ns = hhe ? 5 : 2;

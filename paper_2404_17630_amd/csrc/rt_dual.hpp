@@ -100,6 +100,8 @@ template <int K> __device__ inline Dual<K> m_pow(const Dual<K>& a, double p) {
     const double r = pow(a.v, p);
     return chain(a, r, p * pow(a.v, p - 1.0));
 }
+__device__ inline double m_log(double x) { return log(x); }
+template <int K> __device__ inline Dual<K> m_log(const Dual<K>& a) { return chain(a, log(a.v), 1.0 / a.v); }
 __device__ inline double m_log10(double x) { return log10(x); }
 template <int K> __device__ inline Dual<K> m_log10(const Dual<K>& a) {
     return chain(a, log10(a.v), 0.43429448190325182765 / a.v);

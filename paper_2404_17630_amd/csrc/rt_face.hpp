@@ -44,16 +44,20 @@ __device__ inline void radiation_pressure_n(const R* U, G n0, G n1, G n2, R* P) 
         P[0] = third * n0; P[1] = third * n1; P[2] = third * n2;
         return;
     }
+    // D = (1 - chi)/2 I + (3 chi - 1)/2 u u with the unit vector u = Fh / |Fh|
+    // (dividing by |Fh| rather than |Fh|^2 keeps the derivative finite down to
+    // the smallest |Fh| whose square is still nonzero).
     const R Fm = m_sqrt(F2);
     R f = Fm / N;
     if (val(f) > 1) f = R(G(1));
     const R f2 = f * f;
     const R chi = (G(3) + G(4) * f2) / (G(5) + G(2) * m_sqrt(G(4) - G(3) * f2));
     const R iso = G(0.5) * (G(1) - chi);
-    const R dir = G(0.5) * (G(3) * chi - G(1)) * (U[1] * n0 + U[2] * n1 + U[3] * n2) / F2;
-    P[0] = N * (iso * n0 + dir * U[1]);
-    P[1] = N * (iso * n1 + dir * U[2]);
-    P[2] = N * (iso * n2 + dir * U[3]);
+    const R u0 = U[1] / Fm, u1 = U[2] / Fm, u2 = U[3] / Fm;
+    const R dir = G(0.5) * (G(3) * chi - G(1)) * (u0 * n0 + u1 * n1 + u2 * n2);
+    P[0] = N * (iso * n0 + dir * u0);
+    P[1] = N * (iso * n1 + dir * u1);
+    P[2] = N * (iso * n2 + dir * u2);
 }
 
 template <typename R, typename G>
@@ -82,9 +86,18 @@ __device__ inline bool face_flux(R* sL, R* sR, const R& NL, const R& NR, G vcL, 
         const bool upL = val(Phi[0]) > 0;
         const R Nup = upL ? NL : NR;
         const G vc = upL ? vcL : vcR;
-        const R cap = Nup * vc / (m_abs(Phi[0]) * cdt * A);
-        if (val(cap) < 1) {
-            Phi[0] = cap * Phi[0]; Phi[1] = cap * Phi[1]; Phi[2] = cap * Phi[2]; Phi[3] = cap * Phi[3];
+        const R q = m_abs(Phi[0]) * cdt * A;
+        if (val(Nup) * vc < val(q)) {
+            if (val(Nup) == 0) {
+                // theta = 0: the capped flux is N_up times a face factor, whose
+                // own derivative does not contribute (it is multiplied by 0).
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Phi[v] = Nup * (vc * (val(Phi[v]) / val(q)));
+            } else {
+                const R cap = Nup * vc / q;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Phi[v] = cap * Phi[v];
+            }
             return true;
         }
     }

@@ -47,8 +47,16 @@ struct rt_mesh {
     DevMem d_face32, d_cell32;
     bool geo32_ready = false;
     DevMem d_nbr, d_fsf, d_opp, d_sptr, d_sdeg;
+    // Tiles of the fused transport kernel (rtk::TileView).
+    std::vector<int32_t> lds_opp, halo_ptr, halo_cell, hside_ptr, hside_entry;
+    int64_t tile_max_sides = 0;  // largest tile + halo side count
+    double halo_ratio = 0.0;     // halo cells / cells, over all tiles
+    size_t lds_limit = 0;        // LDS bytes a workgroup may use on the device
+    DevMem d_lds_opp, d_halo_ptr, d_halo_cell, d_hside_ptr, d_hside_entry;
 
     int build_float_geometry();
+    void build_tiles();
+    size_t tile_lds_bytes(size_t tbytes) const { return (size_t)tile_max_sides * 4 * tbytes; }
 };
 
 void rt_mesh_release(rt_mesh* m);
@@ -58,12 +66,14 @@ struct rt_state {
     rt_params params{};
     rtk::ChemParams cp{};
     int precision = RT_FP64;
+    int transport_mode = RT_TRANSPORT_AUTO;
     int nb = 1;
     int64_t nc = 0;
     double dt_cfl = 0.0;
 
     // Fields: U[b][nc][4] = (N, Fh_x, Fh_y, Fh_z) / scale_b in the transport
-    // precision, double-buffered; face states FV[b][entry][4]; chemistry FP64.
+    // precision, double-buffered; face states FV[b][entry][4] (split path
+    // only, allocated on first use); chemistry FP64.
     DevMem U[2];
     int cur = 0;
     DevMem FV;
@@ -94,11 +104,13 @@ struct rt_state {
     int prof_open = -1;
     int prof_kernel = 0;
     std::vector<std::pair<int, int>> ev_marks;
-    int64_t launches[RT_N_KERNELS] = {0, 0, 0, 0, 0};
-    double total_ms[RT_N_KERNELS] = {0, 0, 0, 0, 0};
+    int64_t launches[RT_N_KERNELS] = {0, 0, 0, 0, 0, 0};
+    double total_ms[RT_N_KERNELS] = {0, 0, 0, 0, 0, 0};
 
     ~rt_state();
+    bool fused() const;
     size_t tbytes() const;
+    int ensure_face_states();
     int alloc_buffers();
     int upload_scales();
     int upload_sources();
@@ -115,6 +127,8 @@ void rt_step_sources(rt_state* s, void* U, double dt, hipStream_t st);
 void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStream_t st);
 void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st);
 void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st);
+void rt_step_transport(rt_state* s, const void* U, void* Un, double dt, hipStream_t st);
+rtk::TileView rt_tiles(const rt_mesh* m);
 void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st);
 void rt_reset_partials(rt_state* s, hipStream_t st);
 // Folds the partials and returns the status word (synchronises the stream).

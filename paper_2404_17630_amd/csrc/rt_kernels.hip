@@ -8,6 +8,9 @@
 //                (cell, bin); writes one 4-value record per face side
 //   k_flux       face fluxes + divergence update, one lane per (cell, bin)
 //   (k_reduce    diagnostics, once per call)
+// k_facestate and k_flux are the split form of the transport step; the
+// fused k_transport does both per 256-cell tile with the face states in LDS
+// and is used whenever the mesh's tiles fit (see k_transport).
 // The path is a six-neighbour gather stencil bound by memory traffic, so
 // there is no matrix-core work.  Lanes of a wavefront are 64 consecutive
 // cells of one bin; fields are 4-value records per (bin, cell) and geometry
@@ -245,10 +248,8 @@ __global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T
         const int32_t fs = sell.fsf[e];
         const bool isL = fs >= 0;
         const FaceRec<T> fr = load_face(geo.face, isL ? fs : ~fs);
-        const double r0 = isL ? fr.rl0 : fr.rr0, r1 = isL ? fr.rl1 : fr.rr1, r2 = isL ? fr.rl2 : fr.rr2;
         T s[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) s[v] = (T)(ui[v] + (g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2));
+        face_state<T>(ui, g, isL ? fr.rl0 : fr.rr0, isL ? fr.rl1 : fr.rr1, isL ? fr.rl2 : fr.rr2, s);
         store4(FVb + e * 4, s);
     }
 }
@@ -282,25 +283,21 @@ __global__ __launch_bounds__(kBlock) void k_gradient(const double* __restrict__ 
 // counters and status, accumulated across the subcycles of one call.
 // ---------------------------------------------------------------------------
 
+// Divergence update of cell i from its flux sum, post-update guards, the new
+// record, and the block's partials (sum N V of this bin, counters, status)
+// accumulated across the subcycles of one call.  Called by every thread of
+// the block (i >= nc contributes nothing).
 template <typename T, typename TA>
-__global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ FV, T* __restrict__ Unew,
-                                                 int64_t nc, int nb, int64_t n_entries, GeomView<T> geo, SellView sell,
-                                                 TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
-                                                 int32_t* __restrict__ part_status, int64_t n_blocks) {
+__device__ inline void finish_cell(int64_t i, int b, int64_t nc, const T* ui, const double* acc, TA cdt,
+                                   const GeomView<T>& geo, T* __restrict__ Unew, int cAdmN, int cAdmF, int cCap,
+                                   int64_t blk, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
+                                   int32_t* __restrict__ part_status, int64_t n_blocks) {
     __shared__ double ldsd[kBlock / 64];
     __shared__ int64_t ldsi[kBlock / 64];
     __shared__ int ldss[kBlock / 64];
-    const int64_t blk = xcd_logical_block();
-    const int b = (int)(blk % nb);
-    const int64_t i = (blk / nb) * kBlock + threadIdx.x;
-
-    int cAdmN = 0, cAdmF = 0, cCap = 0, cGN = 0, cGF = 0, status = 0;
+    int cGN = 0, cGF = 0, status = 0;
     double nv = 0.0;
     if (i < nc) {
-        T ui[4];
-        load4(U + urec(b, nc, i), ui);
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        cell_flux_sum<T, TA>(i, b, nc, n_entries, U, FV, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
         const double vol = (double)geo.cell[i * kCellRec + 6];
         const double coef = (double)cdt / vol;
         double un[4];
@@ -332,6 +329,91 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
         part_cnt[4 * n_blocks + blk] += s4;
         part_status[blk] |= st;
     }
+}
+
+template <typename T, typename TA>
+__global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ FV, T* __restrict__ Unew,
+                                                 int64_t nc, int nb, int64_t n_entries, GeomView<T> geo, SellView sell,
+                                                 TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
+                                                 int32_t* __restrict__ part_status, int64_t n_blocks) {
+    const int64_t blk = xcd_logical_block();
+    const int b = (int)(blk % nb);
+    const int64_t i = (blk / nb) * kBlock + threadIdx.x;
+    int cAdmN = 0, cAdmF = 0, cCap = 0;
+    T ui[4] = {0, 0, 0, 0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < nc) {
+        load4(U + urec(b, nc, i), ui);
+        const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp};
+        cell_flux_sum<T, TA>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
+    }
+    finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt, part_status,
+                       n_blocks);
+}
+
+// ---------------------------------------------------------------------------
+// k_transport: gradients, face states and fluxes of one 256-cell tile and
+// one bin in a single launch, with the face states in LDS instead of HBM.
+// The work items are the tile's cells (all their sides) and its halo cells
+// (only their sides that face the tile); both go through the same code, so
+// a face state is bit-identical in every tile that computes it and the two
+// cells of a face still obtain fluxes of exactly opposite sign.
+// ---------------------------------------------------------------------------
+
+template <typename T, typename TA>
+__global__ __launch_bounds__(kBlock) void k_transport(const T* __restrict__ U, T* __restrict__ Unew, int64_t nc,
+                                                      int nb, GeomView<T> geo, SellView sell, TileView tile,
+                                                      int use_limiter, TA cdt, double* __restrict__ part_nv,
+                                                      int64_t* __restrict__ part_cnt,
+                                                      int32_t* __restrict__ part_status, int64_t n_blocks) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw);
+    const int64_t blk = xcd_logical_block();
+    const int b = (int)(blk % nb);
+    const int64_t t = blk / nb;
+    const int64_t c0 = t * kBlock;
+    const int64_t e0 = sell.ptr[t * kTileSlices];
+    const int64_t sl_end = (t + 1) * kTileSlices < tile.n_slices ? (t + 1) * kTileSlices : tile.n_slices;
+    const int64_t tile_sides = (int64_t)sell.ptr[sl_end] - e0;
+    const int32_t hq0 = tile.halo_ptr[t], hq1 = tile.halo_ptr[t + 1];
+    const int32_t hs0 = tile.hside_ptr[hq0];
+    const int64_t n_items = kBlock + (hq1 - hq0);
+
+    for (int64_t item = threadIdx.x; item < n_items; item += kBlock) {
+        const bool own = item < kBlock;
+        const int64_t c = own ? c0 + item : (int64_t)tile.halo_cell[hq0 + (item - kBlock)];
+        if (c >= nc) continue;
+        double uc[4], g[4][3];
+        limited_gradient<T>(c, b, nc, U, geo, sell, use_limiter, uc, g);
+        const int64_t slice = c / kSlice;
+        const int64_t base = (int64_t)sell.ptr[slice] + (c % kSlice);
+        const int32_t sp = own ? 0 : tile.hside_ptr[hq0 + (item - kBlock)];
+        const int32_t n_sides = own ? sell.deg[slice] : tile.hside_ptr[hq0 + (item - kBlock) + 1] - sp;
+        for (int32_t q = 0; q < n_sides; ++q) {
+            const int64_t e = own ? base + (int64_t)q * kSlice : (int64_t)tile.hside_entry[sp + q];
+            const int32_t fs = sell.fsf[e];
+            if (sell.nbr[e] < 0) continue;
+            const int64_t dst = own ? e - e0 : tile_sides + (sp + q - hs0);
+            const bool isL = fs >= 0;
+            const FaceRec<T> fr = load_face(geo.face, isL ? fs : ~fs);
+            T s[4];
+            face_state<T>(uc, g, isL ? fr.rl0 : fr.rr0, isL ? fr.rl1 : fr.rr1, isL ? fr.rl2 : fr.rr2, s);
+            store4(lds + dst * 4, s);
+        }
+    }
+    __syncthreads();
+
+    const int64_t i = c0 + threadIdx.x;
+    int cAdmN = 0, cAdmF = 0, cCap = 0;
+    T ui[4] = {0, 0, 0, 0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < nc) {
+        load4(U + urec(b, nc, i), ui);
+        const TileFaceStates<T> fsv{lds, e0, tile.lds_opp};
+        cell_flux_sum<T, TA>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
+    }
+    finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt, part_status,
+                       n_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -515,6 +597,18 @@ void launch_flux(const T* U, const T* FV, T* Unew, int64_t nc, int nb, int64_t n
                        sell, (T)cdt, part_nv, part_cnt, part_status, nblk);
 }
 
+template <typename T>
+void launch_transport(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
+                      const TileView& tile, size_t lds_bytes, int use_limiter, double cdt, double* part_nv,
+                      int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
+    const int64_t nblk = transport_blocks(nc, nb);
+    if (lds_bytes > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport<T, T>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    hipLaunchKernelGGL((k_transport<T, T>), dim3((unsigned)nblk), dim3(kBlock), lds_bytes, s, U, Unew, nc, nb, geo,
+                       sell, tile, use_limiter, (T)cdt, part_nv, part_cnt, part_status, nblk);
+}
+
 void launch_reduce(const double* part_nv, const int64_t* part_cnt, const int32_t* part_fstatus, int64_t n_fblocks,
                    int nb, const int64_t* chem_sum, const int64_t* chem_max, const int32_t* chem_status,
                    int64_t n_cblocks, const double* nv_scale, DiagDev* out, hipStream_t s) {
@@ -554,6 +648,9 @@ void launch_set_fields(T* U, const double* X, double* Ue, int64_t nc, int nb, in
                                       hipStream_t);                                                                \
     template void launch_flux<T>(const T*, const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, \
                                  double, double*, int64_t*, int32_t*, hipStream_t);                                 \
+    template void launch_transport<T>(const T*, T*, int64_t, int, const GeomView<T>&, const SellView&,             \
+                                      const TileView&, size_t, int, double, double*, int64_t*, int32_t*,           \
+                                      hipStream_t);                                                                \
     template void launch_get_fields<T>(const T*, const double*, const double*, int64_t, int, int, const double*,   \
                                        double, const ChemParams&, double*, hipStream_t);                           \
     template void launch_set_fields<T>(T*, const double*, double*, int64_t, int, int, const double*, double,       \

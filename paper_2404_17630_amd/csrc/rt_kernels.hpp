@@ -47,6 +47,11 @@ void launch_flux(const T* U, const T* FV, T* Unew, int64_t nc, int nb, int64_t n
                  const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
                  hipStream_t s);
 
+template <typename T>
+void launch_transport(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
+                      const TileView& tile, size_t lds_bytes, int use_limiter, double cdt, double* part_nv,
+                      int64_t* part_cnt, int32_t* part_status, hipStream_t s);
+
 void launch_reduce(const double* part_nv, const int64_t* part_cnt, const int32_t* part_fstatus, int64_t n_fblocks,
                    int nb, const int64_t* chem_sum, const int64_t* chem_max, const int32_t* chem_status,
                    int64_t n_cblocks, const double* nv_scale, DiagDev* out, hipStream_t s);

@@ -44,18 +44,36 @@ __device__ inline FaceRec<T> load_face(const T* __restrict__ face, int64_t f) {
     return FaceRec<T>{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9], v[10], v[11]};
 }
 
-// Flux sum of cell i (bin b) from the limited face states FV[b][e][4]:
-// each face's flux in its canonical (L, R) orientation with the upwind cap,
-// accumulated as sigma A Phi in face-index order in FP64.  TA is the
-// arithmetic precision of the face physics.
-template <typename T, typename TA>
-__device__ inline void cell_flux_sum(int64_t i, int b, int64_t nc, int64_t n_entries, const T* __restrict__ U,
-                                     const T* __restrict__ FV, const GeomView<T>& geo, const SellView& sell, TA cdt,
-                                     TA Ni, double* acc, int& cAdmN, int& cAdmF, int& cCap) {
+// Where the limited face states of a cell's sides are read from: the
+// face-state array FV[b][e][4] of the split path, or the LDS tile of the
+// fused kernel.
+template <typename T>
+struct GlobalFaceStates {
+    const T* FVb;          // FV of bin b
+    const int32_t* opp;
+    __device__ const T* own(int64_t e) const { return FVb + e * 4; }
+    __device__ const T* other(int64_t e) const { return FVb + (int64_t)opp[e] * 4; }
+};
+template <typename T>
+struct TileFaceStates {
+    const T* lds;
+    int64_t e0;            // first entry of the tile
+    const int32_t* lds_opp;
+    __device__ const T* own(int64_t e) const { return lds + (e - e0) * 4; }
+    __device__ const T* other(int64_t e) const { return lds + (int64_t)lds_opp[e] * 4; }
+};
+
+// Flux sum of cell i (bin b) from the limited face states: each face's
+// flux in its canonical (L, R) orientation with the upwind cap, accumulated
+// as sigma A Phi in face-index order in FP64.  TA is the arithmetic
+// precision of the face physics.
+template <typename T, typename TA, typename FS>
+__device__ inline void cell_flux_sum(int64_t i, int b, int64_t nc, const T* __restrict__ U, const FS& fsv,
+                                     const GeomView<T>& geo, const SellView& sell, TA cdt, TA Ni, double* acc,
+                                     int& cAdmN, int& cAdmF, int& cCap) {
     const int64_t slice = i / kSlice;
     const int32_t deg = sell.deg[slice];
     const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
-    const T* FVb = FV + (int64_t)b * n_entries * 4;
     for (int k = 0; k < deg; ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
         const int32_t j = sell.nbr[e];
@@ -63,11 +81,10 @@ __device__ inline void cell_flux_sum(int64_t i, int b, int64_t nc, int64_t n_ent
         const int32_t fs = sell.fsf[e];
         const bool isL = fs >= 0;
         const int64_t f = isL ? fs : ~fs;
-        const int64_t eo = sell.opp[e];
         const FaceRec<T> fr = load_face(geo.face, f);
         T so[4], sn[4];
-        load4(FVb + e * 4, so);
-        load4(FVb + eo * 4, sn);
+        load4(fsv.own(e), so);
+        load4(fsv.other(e), sn);
         const TA Nj = (TA)U[urec(b, nc, j)];
         // Canonical orientation: L then R, whichever lane computes it.
         TA sL[4], sR[4];
@@ -88,6 +105,14 @@ __device__ inline void cell_flux_sum(int64_t i, int b, int64_t nc, int64_t n_ent
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += (double)(sA * Phi[v]);
     }
+}
+
+// The limited state of a cell at one of its faces, U_i + g . r_if, rounded
+// to the storage precision once.
+template <typename T>
+__device__ inline void face_state(const double* ui, const double (*g)[3], double r0, double r1, double r2, T* s) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s[v] = (T)(ui[v] + (g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2));
 }
 
 // Limited least-squares gradient of the four fields of cell i (bin b) in

@@ -52,6 +52,28 @@ struct SellView {
     const int32_t* deg;
 };
 
+// Tiles of the fused transport kernel: tile t is cells [256 t, 256 t + 256)
+// (four slices, so its face sides are the contiguous entries
+// ptr[4t] .. ptr[4t+4]).  Face states live in LDS: first the tile's own
+// sides at (entry - ptr[4t]), then the halo sides: the sides of cells
+// outside the tile that face a tile cell, grouped by halo cell.
+//   lds_opp[e]     LDS slot of the state on the other side of entry e
+//   halo_ptr[t]    first halo cell of tile t in halo_cell / hside_ptr
+//   halo_cell[q]   halo cell id
+//   hside_ptr[q]   first halo side of halo cell q in hside_entry; the LDS
+//                  slot of halo side s of tile t is
+//                  (tile sides) + s - hside_ptr[halo_ptr[t]]
+//   hside_entry[s] sliced-ELL entry of the halo side
+constexpr int kTileSlices = kBlock / kSlice;
+struct TileView {
+    const int32_t* lds_opp;
+    const int32_t* halo_ptr;
+    const int32_t* halo_cell;
+    const int32_t* hside_ptr;
+    const int32_t* hside_entry;
+    int64_t n_slices;
+};
+
 // Workgroup id -> logical block: hardware hands workgroups to the 8 XCDs in
 // turn, so consecutive logical blocks (neighbouring cells in a locality
 // order) are remapped to run on the same XCD and share its L2.

@@ -22,7 +22,12 @@ RT_CHEM_NONE, RT_CHEM_H, RT_CHEM_HHE = 0, 1, 2
 RT_RATES_CASEB_CONST, RT_RATES_HG97 = 0, 1
 RT_FIELD_N, RT_FIELD_F, RT_FIELD_NH, RT_FIELD_SPECIES, RT_FIELD_T = 0, 1, 2, 3, 4
 RT_KERNEL_SOURCES, RT_KERNEL_CHEM, RT_KERNEL_GRADIENT, RT_KERNEL_FLUX, RT_KERNEL_REDUCE = 0, 1, 2, 3, 4
-KERNEL_NAMES = ("k_sources", "k_chem", "k_facestate", "k_flux", "k_reduce")
+RT_KERNEL_TRANSPORT = 5
+RT_N_KERNELS = 6
+KERNEL_NAMES = ("k_sources", "k_chem", "k_facestate", "k_flux", "k_reduce", "k_transport")
+RT_TRANSPORT_AUTO, RT_TRANSPORT_FUSED, RT_TRANSPORT_SPLIT = 0, 1, 2
+RT_DEVICE_HOST_ONLY = -1
+TABLES = ("nbr", "fsf", "opp", "sptr", "sdeg", "lds_opp", "halo_ptr", "halo_cell", "hside_ptr", "hside_entry")
 
 ERROR_NAMES = {RT_EINVAL: "RT_EINVAL", RT_EMESH: "RT_EMESH", RT_ESTATE: "RT_ESTATE", RT_EDEVICE: "RT_EDEVICE",
                RT_ENOMEM: "RT_ENOMEM", RT_ENUMERIC: "RT_ENUMERIC"}
@@ -65,6 +70,7 @@ _SIGNATURES = [
     ("rt_mesh_create", C.c_int, [C.c_int64, _vp, _vp, C.c_int64, _vp, _vp, _vp, _vp, C.POINTER(C.c_double),
                                  C.c_int, C.POINTER(_vp)]),
     ("rt_mesh_destroy", C.c_int, [_vp]),
+    ("rt_mesh_table", C.c_int, [_vp, C.c_int, C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.c_int64)]),
     ("rt_state_create", C.c_int, [_vp, C.POINTER(rt_params), C.c_int, _vp, _vp, _vp, _vp, _vp, C.c_int64, _vp,
                                   _vp, C.POINTER(_vp)]),
     ("rt_state_clone", C.c_int, [_vp, C.POINTER(_vp)]),
@@ -75,6 +81,8 @@ _SIGNATURES = [
     ("rt_state_set_field", C.c_int, [_vp, C.c_int, _vp, C.c_int]),
     ("rt_state_info", C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("rt_state_set_transport", C.c_int, [_vp, C.c_int]),
+    ("rt_state_transport", C.c_int, [_vp, C.POINTER(C.c_int32)]),
     ("rt_state_diagnostics", C.c_int, [_vp, C.POINTER(rt_diag)]),
     ("rt_profile_enable", C.c_int, [_vp, C.c_int]),
     ("rt_profile_reset", C.c_int, [_vp]),
@@ -223,6 +231,26 @@ def rt_profile_enable(state, enable: bool = True):
     _check(lib().rt_profile_enable(state, int(enable)))
 
 
+def rt_mesh_table(mesh, name: str) -> np.ndarray:
+    """Copy of one of the mesh's index tables (see TABLES)."""
+    p = C.POINTER(C.c_int32)()
+    n = C.c_int64()
+    _check(lib().rt_mesh_table(mesh, TABLES.index(name), C.byref(p), C.byref(n)))
+    if n.value == 0:
+        return np.zeros(0, np.int32)
+    return np.ctypeslib.as_array(p, shape=(n.value,)).copy()
+
+
+def rt_state_set_transport(state, mode: int):
+    _check(lib().rt_state_set_transport(state, int(mode)))
+
+
+def rt_state_transport(state) -> bool:
+    f = C.c_int32()
+    _check(lib().rt_state_transport(state, C.byref(f)))
+    return bool(f.value)
+
+
 def rt_profile_reset(state):
     _check(lib().rt_profile_reset(state))
 
@@ -248,6 +276,9 @@ class Mesh:
         self.h = rt_mesh_create(self.n_cells, _c64(m["volume"]), _c64(m["centre"]), self.n_faces,
                                 _c64(m["face_cells"], np.int64), _c64(m["area"]), _c64(m["normal"]),
                                 _c64(m["face_centre"]), m["box"], device)
+
+    def table(self, name: str) -> np.ndarray:
+        return rt_mesh_table(self.h, name)
 
     def close(self):
         if self.h is not None and _lib is not None:
@@ -312,6 +343,13 @@ class State:
 
     def diagnostics(self) -> dict:
         return rt_state_diagnostics(self.h, self.nb)
+
+    def set_transport(self, mode: int):
+        rt_state_set_transport(self.h, mode)
+
+    @property
+    def fused(self) -> bool:
+        return rt_state_transport(self.h)
 
     def info(self) -> dict:
         return rt_state_info(self.h)

@@ -3,12 +3,12 @@ periodic lattice meshes in Peano-Hilbert (or random) order, lognormal density
 fields, density-peak point sources with power-law rates and per-bin
 cross-sections.  Holds no step of the method itself."""
 from .configs import (CHEM_H, CHEM_HHE, CHEM_NONE, RATES_CASEB_CONST, RATES_HG97, adjoint_262k,
-                      by_name, cosmological, default_params, hhe_2m, neutral_state, random_order,
+                      by_name, cosmological, default_params, expanding_hii, hhe_2m, neutral_state, random_order,
                       reorder, stromgren, throughput_16m, travelling_wave)
 from .hilbert import bits_for, hilbert_key
-from .mesh import Mesh, jittered_lattice
+from .mesh import Mesh, jittered_lattice, staggered_bcc
 
 __all__ = ["CHEM_H", "CHEM_HHE", "CHEM_NONE", "RATES_CASEB_CONST", "RATES_HG97", "Mesh",
-           "adjoint_262k", "bits_for", "by_name", "cosmological", "default_params", "hhe_2m",
-           "hilbert_key", "jittered_lattice", "neutral_state", "random_order", "reorder", "stromgren", "throughput_16m",
+           "adjoint_262k", "bits_for", "by_name", "cosmological", "default_params", "expanding_hii", "hhe_2m",
+           "hilbert_key", "jittered_lattice", "neutral_state", "staggered_bcc", "random_order", "reorder", "stromgren", "throughput_16m",
            "travelling_wave"]

@@ -35,7 +35,7 @@ import numpy as np
 from . import fields
 from .fields import C_LIGHT, KPC
 from .hilbert import bits_for, hilbert_key
-from .mesh import jittered_lattice
+from .mesh import jittered_lattice, staggered_bcc
 
 CHEM_NONE, CHEM_H, CHEM_HHE = 0, 1, 2
 RATES_CASEB_CONST, RATES_HG97 = 0, 1
@@ -175,6 +175,37 @@ def travelling_wave(n: int = 16, n_sub: int = 64, amplitude: float = 1.0e-6,
                  n_sub, "fp64", amplitude=amplitude)
 
 
+def expanding_hii(n: int = 44, n_sub: int = 64, precision: str = "fp64", c_frac: float = 1.0e-3,
+                  order: str = "hilbert", jitter: float = 0.1) -> dict:
+    """The paper's expanding H II region with hydrogen and helium (Sections
+    3.1 and 4.2.2) on its staggered 2 n^3 grid: a 1.6 kpc periodic box of
+    neutral gas at 100 K with n_H = n0 inside r0 and n0 (r0 / r)^2 outside
+    (n0 = 3.2 cm^-3, r0 = 91.5 pc); photons injected uniformly in a 0.05 kpc
+    sphere about the centre at 1e50, 5e48 and 3e48 s^-1 in the three bins;
+    cross-sections and heating of a 5e4 K black body; reduced light speed
+    1e-3 c."""
+    L = 1.6 * KPC
+    a = L / n
+    mesh = staggered_bcc(n, a, jitter, 1000 + 7, order)
+    c = np.full(3, 0.5 * L)
+    # distance of each generating point from the box centre
+    rel = mesh.centre - c[:, None]
+    r = np.linalg.norm(rel, axis=0)
+    n0, r0 = 3.2, 0.0915 * KPC
+    n_h = np.where(r < r0, n0, n0 * (r0 / np.maximum(r, 1e-30)) ** 2)
+    src = np.flatnonzero(r < 0.05 * KPC)
+    if src.size == 0:
+        src = np.array([int(np.argmin(r))])
+    rate = np.array([1.0e50, 5.0e48, 3.0e48])[:, None] * np.full((1, src.size), 1.0 / src.size)
+    nb = 3
+    p = default_params(nb)
+    sig, eh = fields.blackbody_bin_constants(T_BLACKBODY, BIN_EDGES_EV)
+    p.update(chem_mode=CHEM_HHE, isothermal=0, rate_set=RATES_HG97, Y_He=Y_HE, sigma=sig, e_heat=eh,
+             c_reduced=c_frac * C_LIGHT)
+    state = neutral_state(nb, mesh.n_cells, n_h, 100.0)
+    return _pack("expanding_hii", mesh, p, state, src, rate, n_sub, precision, radius=r)
+
+
 def by_name(name: str, **kw) -> dict:
     table = {
         "stromgren": lambda **k: stromgren(**k),
@@ -185,6 +216,7 @@ def by_name(name: str, **kw) -> dict:
         "throughput_16m": throughput_16m,
         "adjoint_262k": adjoint_262k,
         "travelling_wave": travelling_wave,
+        "expanding_hii": expanding_hii,
     }
     return table[name](**kw)
 

@@ -101,3 +101,75 @@ def jittered_lattice(dims, h: float, jitter: float, seed: int, order: str = "hil
     box = dims_arr.astype(np.float64) * h
     return Mesh(nc, volume, np.ascontiguousarray(centre), 3 * nc, face_cells, area,
                 normal, face_centre, box, idx, (nx, ny, nz), float(h))
+
+
+def staggered_bcc(n: int, a: float, jitter: float, seed: int, order: str = "hilbert") -> Mesh:
+    """The paper's "staggered" 2 n^3 grid (Sections 3.1, 4.2.2): points of a
+    periodic body-centred cubic lattice with cube edge a, i.e. a corner point
+    (i, j, k) a and a body-centre point (i+1/2, j+1/2, k+1/2) a per cube.  Its
+    Voronoi cells are truncated octahedra of volume a^3/2 with 14 faces: 8
+    regular hexagons (area 3 sqrt(3) a^2 / 16) towards the nearest points
+    along the cube diagonals, and 6 squares (area a^2 / 8) towards the next
+    nearest points along the axes.  Faces are those of the unjittered lattice
+    (centre at the midpoint of the two points, normal along their
+    separation); the generating points are jittered by at most jitter*a per
+    axis.  Cells are ordered along the Hilbert curve of the doubled lattice."""
+    nn = n
+    nc = 2 * nn ** 3
+    t = np.repeat([0, 1], nn ** 3)                     # sublattice: 0 corner, 1 body centre
+    lex = np.tile(np.arange(nn ** 3), 2)
+    ix, iy, iz = lex % nn, (lex // nn) % nn, lex // (nn * nn)
+    d2 = np.stack([2 * ix + t, 2 * iy + t, 2 * iz + t])   # doubled-lattice coordinates
+    if order == "hilbert":
+        key = hilbert_key(d2[0], d2[1], d2[2], bits_for(2 * nn))
+        site_of_cell = np.argsort(key, kind="stable")
+    elif order == "random":
+        site_of_cell = np.random.default_rng(4000).permutation(nc)
+    else:
+        site_of_cell = np.arange(nc)
+    cell_of_site = np.empty(nc, dtype=np.int64)
+    cell_of_site[site_of_cell] = np.arange(nc)
+
+    def site(tt, i, j, k):
+        return tt * nn ** 3 + (i % nn) + nn * ((j % nn) + nn * (k % nn))
+
+    pos0 = d2 * (0.5 * a)                               # unjittered positions, sites order
+    rng = np.random.default_rng(seed)
+    jit = rng.uniform(-jitter, jitter, size=(3, nc)) * a
+    centre = (pos0 + 0.5 * a + jit)[:, site_of_cell]    # +a/2 keeps corner points off the box edge
+
+    L_sites, R_sites, kinds = [], [], []
+    corner = np.arange(nn ** 3)
+    ci, cj, ck = corner % nn, (corner // nn) % nn, corner // (nn * nn)
+    # squares: every site to its +x, +y, +z neighbour on the same sublattice
+    for tt in (0, 1):
+        s0 = tt * nn ** 3 + corner
+        for k, (di, dj, dk) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+            L_sites.append(s0)
+            R_sites.append(site(tt, ci + di, cj + dj, ck + dk))
+            kinds.append(np.full(nn ** 3, k))
+    # hexagons: every corner to its 8 surrounding body centres
+    for di in (0, -1):
+        for dj in (0, -1):
+            for dk in (0, -1):
+                L_sites.append(corner)
+                R_sites.append(site(1, ci + di, cj + dj, ck + dk))
+                kinds.append(np.full(nn ** 3, 3))
+    Ls = np.concatenate(L_sites)
+    Rs = np.concatenate(R_sites)
+    kind = np.concatenate(kinds)
+    box = np.full(3, nn * a)
+    sep = pos0[:, Rs] - pos0[:, Ls]
+    sep -= box[:, None] * np.round(sep / box[:, None])
+    dist = np.linalg.norm(sep, axis=0)
+    normal = sep / dist
+    fc = pos0[:, Ls] + 0.5 * a + 0.5 * sep
+    area = np.where(kind == 3, 3 * np.sqrt(3.0) * a * a / 16, a * a / 8)
+    # faces grouped by their L cell in cell order, then in generation order
+    Lc, Rc = cell_of_site[Ls], cell_of_site[Rs]
+    fo = np.lexsort((np.arange(Lc.size), Lc))
+    face_cells = np.stack([Lc[fo], Rc[fo]])
+    idx = np.stack([ix, iy, iz])[:, site_of_cell]
+    return Mesh(nc, np.full(nc, 0.5 * a ** 3), np.ascontiguousarray(centre), int(Lc.size), face_cells,
+                np.ascontiguousarray(area[fo]), np.ascontiguousarray(normal[:, fo]),
+                np.ascontiguousarray(fc[:, fo]), box, idx, (nn, nn, nn), float(a))

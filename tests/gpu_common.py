@@ -12,10 +12,14 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_gpu(cfg, n_sub=None, precision=None, dt=0.0, mesh=None, rate_scale=None, n_H=None, profile=False):
-    """Create mesh + state from a config, advance, return fields and diagnostics."""
+def run_gpu(cfg, n_sub=None, precision=None, dt=0.0, mesh=None, rate_scale=None, n_H=None, profile=False,
+            transport=None):
+    """Create mesh + state from a config, advance, return fields and diagnostics.
+    transport: None (the library's default), or an RT_TRANSPORT_* mode."""
     m = mesh if mesh is not None else rt.Mesh(cfg["mesh"])
     s = rt.State.from_config(m, cfg, precision=precision, rate_scale=rate_scale, n_H=n_H)
+    if transport is not None:
+        s.set_transport(transport)
     if profile:
         rt.rt_profile_enable(s.h, True)
     n = cfg["n_subcycles"] if n_sub is None else n_sub
@@ -23,8 +27,9 @@ def run_gpu(cfg, n_sub=None, precision=None, dt=0.0, mesh=None, rate_scale=None,
     out = s.fields()
     out["diag"] = s.diagnostics()
     out["info"] = s.info()
+    out["fused"] = s.fused
     if profile:
-        out["profile"] = {k: rt.rt_profile_read(s.h, k) for k in range(5)}
+        out["profile"] = {k: rt.rt_profile_read(s.h, k) for k in range(rt.RT_N_KERNELS)}
     s.close()
     if mesh is None:
         m.close()

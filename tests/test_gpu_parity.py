@@ -36,8 +36,14 @@ def test_stromgren_fp64_matches_oracle():
     # same controller path: identical attempt counts
     assert gpu["diag"]["substeps"] == ref["diag"]["substeps"]
     assert gpu["diag"]["max_substeps"] == ref["diag"]["max_substeps"]
+    # The guard and cap counters count decisions taken on values at rounding
+    # level: an update that lands on N = -1e-30 on one side and +1e-30 on the
+    # other, or a free-streaming cell whose |Fh| equals N to the last bit
+    # (about a third of the cells of this test are free-streaming), so they
+    # agree to a few per cent, not exactly.
     for k in ("guard_N", "guard_F", "adm_N", "adm_F", "flux_caps"):
-        assert abs(gpu["diag"][k] - ref["diag"][k]) <= 0.01 * max(ref["diag"][k], 100), k
+        say(f"  {k}: gpu {gpu['diag'][k]} oracle {ref['diag'][k]}")
+        assert abs(gpu["diag"][k] - ref["diag"][k]) <= 0.05 * ref["diag"][k] + 16, k
 
 
 @pytest.mark.parametrize("order", ["hilbert", "random"])
@@ -202,10 +208,22 @@ def test_no_sources_and_zero_subcycles():
     assert rel_err(gpu["N"][0], ref["N"][0]) < TOL
 
 
-def test_profile_counters():
+@pytest.mark.parametrize("mode", [rt.RT_TRANSPORT_FUSED, rt.RT_TRANSPORT_SPLIT], ids=["fused", "split"])
+def test_profile_counters(mode):
     cfg = rtgen.stromgren(n=8, n_sub=5)
-    g = run_gpu(cfg, profile=True)
+    g = run_gpu(cfg, profile=True, transport=mode)
     prof = g["profile"]
-    for k in (rt.RT_KERNEL_SOURCES, rt.RT_KERNEL_CHEM, rt.RT_KERNEL_GRADIENT, rt.RT_KERNEL_FLUX):
+    assert g["fused"] == (mode == rt.RT_TRANSPORT_FUSED)
+    ran = [rt.RT_KERNEL_SOURCES, rt.RT_KERNEL_CHEM]
+    idle = []
+    if g["fused"]:
+        ran.append(rt.RT_KERNEL_TRANSPORT)
+        idle += [rt.RT_KERNEL_GRADIENT, rt.RT_KERNEL_FLUX]
+    else:
+        ran += [rt.RT_KERNEL_GRADIENT, rt.RT_KERNEL_FLUX]
+        idle.append(rt.RT_KERNEL_TRANSPORT)
+    for k in ran:
         assert prof[k][0] == 5 and prof[k][1] > 0
+    for k in idle:
+        assert prof[k][0] == 0
     assert prof[rt.RT_KERNEL_REDUCE][0] == 1

@@ -1,5 +1,6 @@
 """The seeded input generator: Hilbert order, mesh geometry, determinism."""
 import numpy as np
+import pytest
 
 import rtgen
 from rtgen.hilbert import hilbert_key
@@ -63,3 +64,27 @@ def test_bin_constants_are_physical():
     assert np.all(sig >= 0) and np.all(eh >= 0)
     assert sig[0, 1] == 0 and sig[0, 2] == 0 and sig[1, 2] == 0     # below He thresholds
     assert 1e-18 < sig[0, 0] < 6.3e-18
+
+
+def test_staggered_bcc_cells_are_truncated_octahedra():
+    m = rtgen.staggered_bcc(4, 2.0, 0.1, 3, "hilbert")
+    nc, nf = m.n_cells, m.n_faces
+    assert nc == 2 * 4 ** 3 and nf == 7 * nc
+    s = np.zeros((3, nc))
+    cnt = np.zeros(nc, int)
+    surf = np.zeros(nc)
+    for f in range(nf):
+        L, R = m.face_cells[:, f]
+        s[:, L] += m.area[f] * m.normal[:, f]
+        s[:, R] -= m.area[f] * m.normal[:, f]
+        cnt[L] += 1
+        cnt[R] += 1
+        surf[L] += m.area[f]
+        surf[R] += m.area[f]
+    a = 2.0
+    assert np.all(cnt == 14)
+    assert np.allclose(s, 0, atol=1e-12)
+    # truncated octahedron of a BCC Voronoi cell: volume a^3/2, surface (3 sqrt(3)/2 + 3/4) a^2
+    assert np.allclose(m.volume, a ** 3 / 2)
+    assert np.allclose(surf, (1.5 * np.sqrt(3) + 0.75) * a * a)
+    assert m.volume.sum() == pytest.approx(np.prod(m.box))

@@ -1,0 +1,124 @@
+"""Host-side mesh preparation (no GPU): the sliced-ELL face lists and the
+tile tables of the fused transport kernel, read back from a host-only mesh
+and checked against the mesh they were built from."""
+import numpy as np
+import pytest
+
+import rtgen
+from paper_2404_17630_amd import rt
+
+SLICE, TILE = 64, 256
+
+
+def meshes():
+    return {
+        "lattice_ragged_hilbert": rtgen.jittered_lattice((12, 10, 9), 1.0, 0.2, 3, "hilbert").as_dict(),
+        "lattice_random": rtgen.jittered_lattice((9, 8, 7), 1.0, 0.2, 3, "random").as_dict(),
+        "bcc_hilbert": rtgen.staggered_bcc(5, 1.0, 0.1, 4, "hilbert").as_dict(),
+        "lattice_small": rtgen.jittered_lattice((3, 3, 3), 1.0, 0.1, 2, "lattice").as_dict(),
+    }
+
+
+@pytest.fixture(scope="module", params=list(meshes()))
+def mesh(request):
+    m = meshes()[request.param]
+    h = rt.Mesh(m, device=rt.RT_DEVICE_HOST_ONLY)
+    tabs = {name: h.table(name) for name in rt.TABLES}
+    h.close()
+    return m, tabs
+
+
+def entries_of(tabs, nc):
+    """cell -> list of (entry, slot) from the sliced ELL."""
+    sptr, sdeg = tabs["sptr"], tabs["sdeg"]
+    out = []
+    for i in range(nc):
+        s = i // SLICE
+        out.append([(sptr[s] + k * SLICE + i % SLICE, k) for k in range(sdeg[s])])
+    return out
+
+
+def test_sliced_ell_matches_faces(mesh):
+    m, t = mesh
+    nc, nf = m["n_cells"], m["n_faces"]
+    fc = m["face_cells"]
+    ent = entries_of(t, nc)
+    seen = np.zeros((2, nf), int)
+    for i in range(nc):
+        faces = []
+        for e, _ in ent[i]:
+            j = t["nbr"][e]
+            if j < 0:
+                continue
+            fs = t["fsf"][e]
+            f = fs if fs >= 0 else ~fs
+            side = 0 if fs >= 0 else 1
+            assert fc[side, f] == i and fc[1 - side, f] == j
+            seen[side, f] += 1
+            faces.append(f)
+            # the opposite entry is the same face seen from the neighbour
+            eo = t["opp"][e]
+            assert t["nbr"][eo] == i and t["opp"][eo] == e
+            assert (t["fsf"][eo] if t["fsf"][eo] >= 0 else ~t["fsf"][eo]) == f
+        assert faces == sorted(faces)          # face-index order within a cell
+    assert np.all(seen == 1)
+
+
+def test_tile_tables_route_every_opposite_state(mesh):
+    """Every face side of a tile cell finds the state on the other side of its
+    face in an LDS slot that exactly one work item writes: the neighbour's own
+    entry when it is in the tile, else the halo side listed for it."""
+    m, t = mesh
+    nc = m["n_cells"]
+    sptr, nbr, opp = t["sptr"], t["nbr"], t["opp"]
+    ns = len(t["sdeg"])
+    ntiles = (nc + TILE - 1) // TILE
+    assert len(t["halo_ptr"]) == ntiles + 1 and t["halo_ptr"][0] == 0
+    assert len(t["hside_ptr"]) == len(t["halo_cell"]) + 1
+    cell_of_entry = np.full(len(nbr), -1)
+    for i, lst in enumerate(entries_of(t, nc)):
+        for e, _ in lst:
+            cell_of_entry[e] = i
+    for tt in range(ntiles):
+        c0, c1 = tt * TILE, min(nc, tt * TILE + TILE)
+        e0 = sptr[tt * 4]
+        n_own = sptr[min(ns, tt * 4 + 4)] - e0
+        q0, q1 = t["halo_ptr"][tt], t["halo_ptr"][tt + 1]
+        hs0, hs1 = t["hside_ptr"][q0], t["hside_ptr"][q1]
+        writes = np.zeros(n_own + (hs1 - hs0), int)
+        # own slots: every real entry of a tile cell
+        for e in range(e0, e0 + n_own):
+            if nbr[e] >= 0 and c0 <= cell_of_entry[e] < c1:
+                writes[e - e0] += 1
+        # halo slots
+        halo = t["halo_cell"][q0:q1]
+        assert np.all((halo < c0) | (halo >= c1))
+        assert len(set(halo.tolist())) == len(halo)
+        for q in range(q0, q1):
+            for s in range(t["hside_ptr"][q], t["hside_ptr"][q + 1]):
+                e = t["hside_entry"][s]
+                assert cell_of_entry[e] == t["halo_cell"][q]
+                assert c0 <= nbr[e] < c1            # the side faces a tile cell
+                writes[n_own + s - hs0] += 1
+        assert np.all(writes <= 1)
+        # every tile entry reads a written slot holding its opposite state
+        for i in range(c0, c1):
+            for e, _ in entries_of(t, nc)[i]:
+                if nbr[e] < 0:
+                    continue
+                slot = t["lds_opp"][e]
+                assert 0 <= slot < len(writes) and writes[slot] == 1
+                eo = opp[e]
+                if c0 <= nbr[e] < c1:
+                    assert slot == eo - e0
+                else:
+                    assert t["hside_entry"][hs0 + slot - n_own] == eo
+
+
+def test_host_only_mesh_cannot_hold_a_state():
+    cfg = rtgen.stromgren(n=4, n_sub=1)
+    m = rt.Mesh(cfg["mesh"], device=rt.RT_DEVICE_HOST_ONLY)
+    with pytest.raises(rt.RtError) as ei:
+        rt.State.from_config(m, cfg)
+    assert ei.value.code == rt.RT_EDEVICE
+    m.close()

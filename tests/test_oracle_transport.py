@@ -114,10 +114,11 @@ def test_hll_flux_is_rusanov_of_physical_flux():
 
 # --- gradients ----------------------------------------------------------------
 
-@pytest.mark.parametrize("dims", [(6, 6, 6), (2, 2, 2), (5, 3, 4)])
+@pytest.mark.parametrize("dims", [(6, 6, 6), (2, 2, 2), (5, 3, 4), "bcc"])
 def test_gradient_minimises_weighted_least_squares(dims):
-    """Unlimited gradient = argmin of S_tot (Section 2.3.2) solved by numpy's lstsq."""
-    mesh = small_mesh(dims)
+    """Unlimited gradient = argmin of S_tot (Section 2.3.2) solved by numpy's lstsq,
+    on jittered lattices and on the staggered (BCC, 14-face) grid."""
+    mesh = rtgen.staggered_bcc(3, 1.0, 0.15, 5) if dims == "bcc" else small_mesh(dims)
     rng = np.random.default_rng(11)
     phi = rng.normal(size=mesh.n_cells)
     g = oracle.gradients(mesh.as_dict(), phi, use_limiter=False)
