@@ -115,6 +115,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=256, help="cells per side (256 = the throughput workload)")
     ap.add_argument("--no-extras", action="store_true", help="time only the mixed Hilbert-order run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--transport", choices=("auto", "fused", "split"), default="auto",
+                    help="transport path of the headline run (the library's default is auto)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="first copy a GIB-sized device buffer three times (a plain copy kernel of known size, "
                          "for scaling hardware byte counters)")
@@ -151,7 +153,9 @@ def main() -> int:
     mesh = rt.Mesh(cfg["mesh"])
 
     log(f"mixed, hilbert: {args.steps} subcycles")
-    st_mixed, t_mixed, prof_mixed = timed_run(rt, mesh, cfg, rt.RT_MIXED, args.steps, args.warmup, torch)
+    mode = {"auto": None, "fused": rt.RT_TRANSPORT_FUSED, "split": rt.RT_TRANSPORT_SPLIT}[args.transport]
+    st_mixed, t_mixed, prof_mixed = timed_run(rt, mesh, cfg, rt.RT_MIXED, args.steps, args.warmup, torch,
+                                              transport=mode)
     value = nc * nb * args.steps / t_mixed
     diag = st_mixed.diagnostics()
     if diag["status"] != 0:
@@ -199,40 +203,68 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic},
         "kernels_mixed": kt_mixed,
+        "chem_attempts_per_cell_subcycle": diag["substeps"] / (nc * args.steps),
     }
 
     if not args.no_extras:
         fields_mixed = st_mixed.fields()
         st_mixed.close()
-        if out["config"]["transport"] == "fused":
-            log(f"mixed, hilbert, split transport: {args.steps} subcycles")
+        other = "split" if out["config"]["transport"] == "fused" else "fused"
+        log(f"mixed, hilbert, {other} transport: {args.steps} subcycles")
+        try:
             st_s, t_s, prof_s = timed_run(rt, mesh, cfg, rt.RT_MIXED, args.steps, args.warmup, torch,
-                                          transport=rt.RT_TRANSPORT_SPLIT)
+                                          transport=rt.RT_TRANSPORT_SPLIT if other == "split"
+                                          else rt.RT_TRANSPORT_FUSED)
             st_s.close()
-            out["split_transport_value"] = nc * nb * args.steps / t_s
-            out["kernels_mixed_split"] = kernel_table(prof_s, 4, 4)
+            out[f"{other}_transport_value"] = nc * nb * args.steps / t_s
+            out[f"kernels_mixed_{other}"] = kernel_table(prof_s, 4, 4)
+        except rt.RtError as e:
+            out[f"{other}_transport_value"] = f"unavailable: {e}"
         log(f"fp64, hilbert: {args.steps} subcycles")
         st64, t64, prof64 = timed_run(rt, mesh, cfg, rt.RT_FP64, args.steps, args.warmup, torch)
         f64 = st64.fields()
         st64_fused = st64.fused
         st64.close()
         v64 = nc * nb * args.steps / t64
-        N64, Nm = f64["N"], fields_mixed["N"]
         fc = cfg["mesh"]["face_cells"]
-        errN, errC, p999, frac = 0.0, 0.0, 0.0, 0.0
-        for b in range(nb):
-            r = N64[b]
-            mask = r > 1e-10 * r.max()
-            rel = np.abs(Nm[b][mask] - r[mask]) / r[mask]
-            errN = max(errN, float(rel.max()))
-            p999 = max(p999, float(np.quantile(rel, 0.999)))
-            frac = max(frac, float(np.mean(rel > 1e-3)))
-            # against max(N, 1e-4 of the stencil maximum, 1e-10 of the maximum)
-            m = r.copy()
-            np.maximum.at(m, fc[0], r[fc[1]])
-            np.maximum.at(m, fc[1], r[fc[0]])
-            scale = np.maximum(np.maximum(r, 1e-4 * m), 1e-10 * r.max())
-            errC = max(errC, float((np.abs(Nm[b] - r) / np.where(scale > 0, scale, 1.0)).max()))
+
+        def n_errors(Na, Nr):
+            """Relative error of N against a reference, the way the stated bar
+            measures it, plus the share of cells above 1e-3 and the error with
+            a floor of 1e-4 of the stencil maximum."""
+            errN, errC, p999, frac = 0.0, 0.0, 0.0, 0.0
+            for b in range(nb):
+                r = Nr[b]
+                mask = r > 1e-10 * r.max()
+                rel = np.abs(Na[b][mask] - r[mask]) / r[mask]
+                errN = max(errN, float(rel.max()))
+                p999 = max(p999, float(np.quantile(rel, 0.999)))
+                frac = max(frac, float(np.mean(rel > 1e-3)))
+                m = r.copy()
+                np.maximum.at(m, fc[0], r[fc[1]])
+                np.maximum.at(m, fc[1], r[fc[0]])
+                scale = np.maximum(np.maximum(r, 1e-4 * m), 1e-10 * r.max())
+                errC = max(errC, float((np.abs(Na[b] - r) / np.where(scale > 0, scale, 1.0)).max()))
+            return errN, p999, frac, errC
+
+        errN, p999, frac, errC = n_errors(fields_mixed["N"], f64["N"])
+        # The same FP64 run on the other transport path differs from the first
+        # only in the order of its roundings: the spread it shows is what the
+        # problem itself does to a relative change of 1e-16.
+        other64 = rt.RT_TRANSPORT_FUSED if not st64_fused else rt.RT_TRANSPORT_SPLIT
+        try:
+            st_o, _, _ = timed_run(rt, mesh, cfg, rt.RT_FP64, args.steps, 0, torch, transport=other64)
+            f_o = st_o.fields()
+            st_o.close()
+            oN, op999, ofrac, oC = n_errors(f_o["N"], f64["N"])
+            out["fp64_reordered_vs_fp64"] = {
+                "N_rel_max(N>1e-10 max)": oN, "N_rel_p99.9(N>1e-10 max)": op999, "N_frac_cells_rel>1e-3": ofrac,
+                "N_rel_max(stencil floor 1e-4)": oC,
+                "x_HII_abs_max": float(np.abs(f_o["species"][1] - f64["species"][1]).max()),
+            }
+            del f_o
+        except rt.RtError as e:
+            out["fp64_reordered_vs_fp64"] = f"unavailable: {e}"
         out["fp64_value"] = v64
         out["fp64_ms_per_step"] = t64 / args.steps * 1e3
         out["mixed_speedup_vs_fp64"] = value / v64

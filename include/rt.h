@@ -87,7 +87,7 @@ extern "C" {
  * device memory; the fused path runs both per 256-cell tile in one kernel
  * with the face states in LDS.  Both give the same fluxes to rounding. */
 #define RT_TRANSPORT_AUTO  0   /* fused when the tiles fit in LDS and their halos are
-                                  small (a locality-preserving cell order), else split */
+                                  at most half the tile size, else split */
 #define RT_TRANSPORT_FUSED 1   /* fused whenever the tiles fit in LDS */
 #define RT_TRANSPORT_SPLIT 2   /* always split */
 

@@ -45,6 +45,56 @@ namespace rtk {
 
 constexpr int kFaceDirs = 10;   // sL[4], sR[4], N_L, N_R
 
+// Input states of the transport step whose photon density is below
+// kAdjFloor times the bin's largest (the leading edge of a front, where
+// neighbours differ by tens of orders of magnitude) are held constant: the
+// adjoint of the cell's input state and of its gradient is zero (the adjoint
+// of its output, which the flux from lit neighbours fills, is kept).  A
+// perturbation of the luminosities or densities moves such a state by a
+// relative amount of the order of its own, which cannot reach x_HI in FP64;
+// the ratio-type local derivatives there (limiter, closure) would otherwise
+// multiply the adjoint by up to 1e12 per subcycle and overflow it.  Cells
+// with N = 0 are beyond the stencil's reach, so their adjoint is exactly
+// zero anyway.
+constexpr double kAdjFloor = 1.0e-20;
+
+// Largest N of each bin over the cells: per-block maxima, then one block per
+// bin; writes tau[b] = kAdjFloor * max.
+__global__ __launch_bounds__(kBlock) void k_adj_binmax(const double* __restrict__ U, int64_t nc, int nb,
+                                                       double* __restrict__ part) {
+    __shared__ double red[kBlock];
+    const int b = (int)(blockIdx.x % nb);
+    const int64_t blk = blockIdx.x / nb;
+    const int64_t i = blk * kBlock + threadIdx.x;
+    red[threadIdx.x] = i < nc ? U[urec(b, nc, i)] : 0.0;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(kBlock) void k_adj_tau(const double* __restrict__ part, int64_t n_blk, int nb,
+                                                    double* __restrict__ tau) {
+    __shared__ double red[kBlock];
+    const int b = blockIdx.x;
+    double m = 0.0;
+    for (int64_t q = threadIdx.x; q < n_blk; q += kBlock) m = fmax(m, part[q * nb + b]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tau[b] = kAdjFloor * red[0];
+}
+
+__device__ inline bool adj_active(const double* __restrict__ U, const double* __restrict__ tau, int b, int64_t nc,
+                                  int64_t i) {
+    const double n = U[urec(b, nc, i)];
+    return n > 0.0 && n >= tau[b];
+}
+
 // ---------------------------------------------------------------------------
 // k_adj_guard: lambda_pre = J_guard^T lambda_new, with the pre-guard update
 // recomputed from the transport inputs.
@@ -62,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard(const double* __restrict__
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int c0 = 0, c1 = 0, c2 = 0;
     const GlobalFaceStates<double> fsv{FV + (int64_t)b * n_entries * 4, sell.opp};
-    cell_flux_sum<double, double>(i, b, nc, U, fsv, geo, sell, cdt, ui[0], acc, c0, c1, c2);
+    cell_flux_sum_s<double, double, 0>(i, b, nc, U, fsv, geo, sell, cdt, ui[0], acc, c0, c1, c2);
     const double coef = cdt / geo.cell[i * kCellRec + 6];
     Dual<4> un[4];
 #pragma unroll
@@ -95,11 +145,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard(const double* __restrict__
 __global__ __launch_bounds__(kBlock) void k_adj_flux(const double* __restrict__ U, const double* __restrict__ G,
                                                      const double* __restrict__ lam_pre, double* __restrict__ lam_dir,
                                                      double* __restrict__ lam_g, int64_t nc, int nb,
-                                                     GeomView<double> geo, SellView sell, double cdt) {
+                                                     GeomView<double> geo, SellView sell, double cdt,
+                                                     const double* __restrict__ tau) {
     const int64_t blk = xcd_logical_block();
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
     if (i >= nc) return;
+    if (!adj_active(U, tau, b, nc, i)) {
+        double* Ld = lam_dir + (int64_t)(b * 4) * nc;
+        double* Lg = lam_g + (int64_t)(b * 12) * nc;
+        for (int v = 0; v < 4; ++v) Ld[(int64_t)v * nc + i] = 0.0;
+        for (int v = 0; v < 12; ++v) Lg[(int64_t)v * nc + i] = 0.0;
+        return;
+    }
     const double* Gb = G + (int64_t)(b * 12) * nc;
     const double* Lp = lam_pre + (int64_t)(b * 4) * nc;
     double ui[4], gi[4][3], li[4];
@@ -198,7 +256,7 @@ template <int KG>
 __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ U, const double* __restrict__ lam_g,
                                                      double* __restrict__ c_self, double* __restrict__ c_slot,
                                                      int64_t n_entries, int64_t nc, int nb, GeomView<double> geo,
-                                                     SellView sell, int use_limiter) {
+                                                     SellView sell, int use_limiter, const double* __restrict__ tau) {
     const int64_t blk = xcd_logical_block();
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
@@ -207,6 +265,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
     const int64_t slice = i / kSlice;
     const int32_t deg = sell.deg[slice];
     const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
+    if (!adj_active(U, tau, b, nc, i)) {
+        for (int v = 0; v < 4; ++v) {
+            c_self[(int64_t)(b * 4 + v) * nc + i] = 0.0;
+            for (int k = 0; k < deg; ++k)
+                c_slot[(int64_t)(b * 4 + v) * n_entries + base + (int64_t)k * kSlice] = 0.0;
+        }
+        return;
+    }
     const double* cr = geo.cell + i * kCellRec;
     const double mxx = cr[0], myy = cr[1], mzz = cr[2], mxy = cr[3], mxz = cr[4], myz = cr[5];
     for (int v = 0; v < 4; ++v) {
@@ -276,11 +342,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
 __global__ __launch_bounds__(kBlock) void k_adj_gather(const double* __restrict__ lam_dir,
                                                        const double* __restrict__ c_self,
                                                        const double* __restrict__ c_slot, int64_t n_entries,
-                                                       double* __restrict__ lam_U, int64_t nc, int nb, SellView sell) {
+                                                       double* __restrict__ lam_U, int64_t nc, int nb, SellView sell,
+                                                       const double* __restrict__ U, const double* __restrict__ tau) {
     const int64_t blk = xcd_logical_block();
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
     if (i >= nc) return;
+    if (!adj_active(U, tau, b, nc, i)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) lam_U[(int64_t)(b * 4 + v) * nc + i] = 0.0;
+        return;
+    }
     double acc[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -493,11 +565,12 @@ extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int
             return rc;
     // Adjoint buffers.
     const int64_t n_entries = m->n_entries;
-    DevMem lU, lX, lu, lnn, lq, lpre, ldir, lg, cself, cslot, fail, d_cell, d_rate, d_vp, d_dL, G;
+    DevMem lU, lX, lu, lnn, lq, lpre, ldir, lg, cself, cslot, fail, d_cell, d_rate, d_vp, d_dL, G, tmax, tau;
     if ((rc = lU.alloc(ub)) || (rc = lX.alloc(5 * nc * 8)) || (rc = lu.alloc(nc * 8)) || (rc = lnn.alloc(nc * 8)) ||
         (rc = lq.alloc(std::max<int64_t>(w->n_src, 1) * 8)) || (rc = lpre.alloc(ub)) || (rc = ldir.alloc(ub)) ||
         (rc = lg.alloc(3 * ub)) || (rc = cself.alloc(ub)) || (rc = cslot.alloc((size_t)nb * 4 * n_entries * 8)) ||
-        (rc = fail.alloc(grid1(nc, kBlock) * 4)) || (rc = G.alloc(3 * ub)))
+        (rc = fail.alloc(grid1(nc, kBlock) * 4)) || (rc = G.alloc(3 * ub)) ||
+        (rc = tmax.alloc((size_t)grid1(nc, kBlock) * nb * 8)) || (rc = tau.alloc((size_t)nb * 8)))
         return rc;
     {
         std::vector<int32_t> cell(w->n_src);
@@ -574,23 +647,28 @@ extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int
         // Reverse sweep over the segment.
         for (int j = len - 1; j >= 0; --j) {
             const double* Um = (const double*)mid_U[j].ptr;
+            const double* tv = (const double*)tau.ptr;
             rt_step_facestate(w, Um, w->FV.ptr, st);
             launch_gradient(Um, (double*)G.ptr, nc, nb, geo, sell, w->params.use_limiter, st);
+            hipLaunchKernelGGL(k_adj_binmax, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, nc, nb, (double*)tmax.ptr);
+            hipLaunchKernelGGL(k_adj_tau, dim3((unsigned)nb), dim3(kBlock), 0, st, (const double*)tmax.ptr,
+                               (int64_t)grid1(nc, kBlock), nb, (double*)tau.ptr);
             hipLaunchKernelGGL(k_adj_guard, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, (const double*)w->FV.ptr,
                                (const double*)lU.ptr, (double*)lpre.ptr, nc, nb, n_entries, geo, sell, cdt);
             hipLaunchKernelGGL(k_adj_flux, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, (const double*)G.ptr,
-                               (const double*)lpre.ptr, (double*)ldir.ptr, (double*)lg.ptr, nc, nb, geo, sell, cdt);
+                               (const double*)lpre.ptr, (double*)ldir.ptr, (double*)lg.ptr, nc, nb, geo, sell, cdt,
+                               tv);
             if (m->max_deg <= 6)
                 hipLaunchKernelGGL(k_adj_grad<7>, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, (const double*)lg.ptr,
                                    (double*)cself.ptr, (double*)cslot.ptr, n_entries, nc, nb, geo, sell,
-                                   w->params.use_limiter);
+                                   w->params.use_limiter, tv);
             else
                 hipLaunchKernelGGL(k_adj_grad<17>, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um,
                                    (const double*)lg.ptr, (double*)cself.ptr, (double*)cslot.ptr, n_entries, nc, nb,
-                                   geo, sell, w->params.use_limiter);
+                                   geo, sell, w->params.use_limiter, tv);
             hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)tblk), dim3(kBlock), 0, st, (const double*)ldir.ptr,
                                (const double*)cself.ptr, (const double*)cslot.ptr, n_entries, (double*)lU.ptr, nc, nb,
-                               sell);
+                               sell, Um, tv);
             if (w->params.chem_mode != RT_CHEM_NONE) {
                 const double* Up = (const double*)pre_U[j].ptr;
                 const double* Xp = (const double*)pre_X[j].ptr;

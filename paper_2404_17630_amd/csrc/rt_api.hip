@@ -226,6 +226,53 @@ void rt_mesh::build_tiles() {
     halo_ratio = (double)halo_cell.size() / (double)nc;
 }
 
+// Per face side records in the transport precision (rtk::SideComp), one
+// component at a time.
+int rt_mesh::build_side_geometry(size_t tbytes) {
+    DevMem& d = tbytes == 4 ? d_side32 : d_side64;
+    if (d.ptr) return RT_OK;
+    const int64_t ne = n_entries;
+    int rc;
+    if ((rc = d.alloc((size_t)kSideComps * ne * tbytes))) return rc;
+    std::vector<double> comp(ne);
+    std::vector<float> comp32(tbytes == 4 ? ne : 0);
+    for (int c = 0; c < kSideComps; ++c) {
+        for (int64_t e = 0; e < ne; ++e) {
+            double v = 0.0;
+            if (nbr[e] >= 0) {
+                const bool isL = fsf[e] >= 0;
+                const double* rec = &face[(size_t)(isL ? fsf[e] : ~fsf[e]) * kFaceRec];
+                const double* ro = isL ? rec + 4 : rec + 7;     // own offset
+                const double* rn = isL ? rec + 7 : rec + 4;     // neighbour's offset
+                if (c <= kSW2) {
+                    const double d0 = ro[0] - rn[0], d1 = ro[1] - rn[1], d2 = ro[2] - rn[2];
+                    const double sc = rec[0] / (d0 * d0 + d1 * d1 + d2 * d2);
+                    v = (c == kSW0 ? d0 : c == kSW1 ? d1 : d2) * sc;
+                } else if (c <= kSR2) {
+                    v = ro[c - kSR0];
+                } else if (c == kSA) {
+                    v = rec[0];
+                } else if (c <= kSN2) {
+                    v = rec[1 + (c - kSN0)];
+                } else {
+                    v = rec[c == kSVL ? 10 : 11];
+                }
+            }
+            comp[e] = v;
+        }
+        void* dst = (char*)d.ptr + (size_t)c * ne * tbytes;
+        hipError_t err;
+        if (tbytes == 4) {
+            for (int64_t e = 0; e < ne; ++e) comp32[e] = (float)comp[e];
+            err = hipMemcpy(dst, comp32.data(), ne * 4, hipMemcpyHostToDevice);
+        } else {
+            err = hipMemcpy(dst, comp.data(), ne * 8, hipMemcpyHostToDevice);
+        }
+        if (err != hipSuccess) return rt_fail(RT_EDEVICE, "side geometry upload: %s", hipGetErrorString(err));
+    }
+    return RT_OK;
+}
+
 extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const double* centre, int64_t n_faces,
                               const int64_t* face_cells, const double* area, const double* normal,
                               const double* face_centre, const double box_in[3], int device, rt_mesh** out) {
@@ -396,6 +443,12 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
         }
     }
     m->max_deg = *std::max_element(deg.begin(), deg.end());
+    {
+        const int32_t d0 = m->sdeg[0];
+        bool uniform = (d0 == 6 || d0 == 14);
+        for (int64_t q = 0; q < nc && uniform; ++q) uniform = deg[q] == d0;
+        m->uniform_deg = uniform ? d0 : 0;
+    }
     m->deg = std::move(deg);
     if ((int64_t)m->n_entries + (int64_t)2 * nf >= INT32_MAX / 2) {
         delete m;
@@ -663,6 +716,7 @@ extern "C" int rt_state_create(const rt_mesh* mesh_c, const rt_params* params, i
         }
     }
     if (precision == RT_MIXED && (rc = mesh->build_float_geometry())) return rc;
+    if ((rc = mesh->build_side_geometry(precision == RT_MIXED ? 4 : 8))) return rc;
 
     rt_state* s = new (std::nothrow) rt_state();
     if (!s) return rt_fail(RT_ENOMEM, "state handle");
@@ -841,7 +895,9 @@ static GeomView<T> geom_view(const rt_mesh* m) {
         geo.face = (const T*)m->d_face32.ptr;
         geo.cell = (const T*)m->d_cell32.ptr;
     }
+    geo.side = (const T*)(sizeof(T) == 8 ? m->d_side64.ptr : m->d_side32.ptr);
     geo.nf = m->nf;
+    geo.ne = m->n_entries;
     return geo;
 }
 
@@ -849,7 +905,7 @@ GeomView<double> rt_geo64(const rt_mesh* m) { return geom_view<double>(m); }
 
 SellView rt_sell(const rt_mesh* m) {
     return SellView{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_opp.ptr,
-                    (const int32_t*)m->d_sptr.ptr, (const int32_t*)m->d_sdeg.ptr};
+                    (const int32_t*)m->d_sptr.ptr, (const int32_t*)m->d_sdeg.ptr, m->uniform_deg};
 }
 
 // One piece of a subcycle on explicit buffers (U, G in the state's precision).
@@ -913,11 +969,13 @@ TileView rt_tiles(const rt_mesh* m) {
                     (const int32_t*)m->d_hside_entry.ptr, (int64_t)m->sdeg.size()};
 }
 
-// Halo cells per cell above which AUTO keeps the split path: the fused
-// kernel computes the gradient of every halo cell once more per tile, so a
-// cell order without locality (halo ~ all face neighbours) would multiply
-// the gradient work.
-static constexpr double kMaxHaloRatio = 2.0;
+// Halo cells per cell up to which AUTO takes the fused path.  The fused
+// kernel computes the gradient of every halo cell once more per tile; a
+// 256-cell tile of a Hilbert-ordered lattice has 256 halo cells (ratio 1),
+// and there the split path is measured faster (the gradient, not the
+// face-state traffic, dominates), so AUTO keeps the split path unless the
+// halos are much smaller than the tiles.
+static constexpr double kMaxHaloRatio = 0.5;
 
 bool rt_state::fused() const {
     if (transport_mode == RT_TRANSPORT_SPLIT) return false;

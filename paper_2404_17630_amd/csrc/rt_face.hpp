@@ -19,6 +19,10 @@
 
 namespace rtk {
 
+// Relative size below which the flux of N through a face counts as
+// rounding noise of its two terms (see face_flux).
+constexpr double kCapNoise = 1.0e-12;
+
 template <typename R, typename G>
 __device__ inline void make_admissible(R* U, int& cN, int& cF) {
     if (val(U[0]) < 0) { U[0] = R(G(0)); ++cN; }
@@ -88,11 +92,16 @@ __device__ inline bool face_flux(R* sL, R* sR, const R& NL, const R& NR, G vcL, 
         const G vc = upL ? vcL : vcR;
         const R q = m_abs(Phi[0]) * cdt * A;
         if (val(Nup) * vc < val(q)) {
-            if (val(Nup) == 0) {
-                // theta = 0: the capped flux is N_up times a face factor, whose
-                // own derivative does not contribute (it is multiplied by 0).
+            // The flux of N is a difference of terms of size N_L + N_R; when it
+            // is at their rounding level (free streaming along n into an empty
+            // cell) its sign and size are noise, and so is the dependence of
+            // theta on the face states: theta is then held constant for the
+            // derivative.  The value is the same either way.
+            const bool noise = (double)val(m_abs(Phi[0])) <= kCapNoise * (double)(val(sL[0]) + val(sR[0]));
+            if (noise) {
+                const auto th = val(Nup) * vc / val(q);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Phi[v] = Nup * (vc * (val(Phi[v]) / val(q)));
+                for (int v = 0; v < 4; ++v) Phi[v] = Phi[v] * th;
             } else {
                 const R cap = Nup * vc / q;
 #pragma unroll

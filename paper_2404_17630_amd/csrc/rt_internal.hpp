@@ -46,6 +46,8 @@ struct rt_mesh {
     DevMem d_face64, d_cell64, d_vphys;
     DevMem d_face32, d_cell32;
     bool geo32_ready = false;
+    DevMem d_side32, d_side64;   // per face side records (rtk::SideComp), built on first use
+    int32_t uniform_deg = 0;     // rtk::SellView::uniform_deg
     DevMem d_nbr, d_fsf, d_opp, d_sptr, d_sdeg;
     // Tiles of the fused transport kernel (rtk::TileView).
     std::vector<int32_t> lds_opp, halo_ptr, halo_cell, hside_ptr, hside_entry;
@@ -55,6 +57,7 @@ struct rt_mesh {
     DevMem d_lds_opp, d_halo_ptr, d_halo_cell, d_hside_ptr, d_hside_entry;
 
     int build_float_geometry();
+    int build_side_geometry(size_t tbytes);
     void build_tiles();
     size_t tile_lds_bytes(size_t tbytes) const { return (size_t)tile_max_sides * 4 * tbytes; }
 };

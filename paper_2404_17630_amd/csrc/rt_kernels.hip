@@ -228,29 +228,68 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
 // would cancel at steep fronts, where U + g.r is much smaller than U).
 // ---------------------------------------------------------------------------
 
-template <typename T>
+// Store the limited state of cell i at each of its faces: entry e goes to
+// out[(e - e0) * 4].
+template <typename T, int DEG>
+__device__ inline void export_face_states(int64_t i, const double* ui, const double (*g)[3], const T (*rr)[3],
+                                          const bool* ok, const GeomView<T>& geo, const SellView& sell,
+                                          T* __restrict__ out, int64_t e0) {
+    const int64_t slice = i / kSlice;
+    const int32_t deg = DEG > 0 ? DEG : sell.deg[slice];
+    const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
+#pragma unroll(SlotCount<DEG>::kMax)
+    for (int k = 0; k < (DEG > 0 ? DEG : deg); ++k) {
+        const int64_t e = base + (int64_t)k * kSlice;
+        double r0, r1, r2;
+        if (DEG > 0) {
+            if (!ok[k]) continue;
+            r0 = rr[k][0]; r1 = rr[k][1]; r2 = rr[k][2];
+        } else {
+            if (sell.nbr[e] < 0) continue;
+            r0 = geo.sv(kSR0, e); r1 = geo.sv(kSR1, e); r2 = geo.sv(kSR2, e);
+        }
+        T st[4];
+        face_state<T>(ui, g, r0, r1, r2, st);
+        store4(out + (e - e0) * 4, st);
+    }
+}
+
+template <typename T, int DEG>
 __global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T* __restrict__ FV, int64_t nc, int nb,
                                                       int64_t n_entries, GeomView<T> geo, SellView sell,
                                                       int use_limiter) {
     const int64_t blk = xcd_logical_block();
-    const int b = (int)(blk % nb);
-    const int64_t i = (blk / nb) * kBlock + threadIdx.x;
-    if (i >= nc) return;
-    double ui[4], g[4][3];
-    limited_gradient<T>(i, b, nc, U, geo, sell, use_limiter, ui, g);
-    const int64_t slice = i / kSlice;
-    const int32_t deg = sell.deg[slice];
-    const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
-    T* FVb = FV + (int64_t)b * n_entries * 4;
-    for (int k = 0; k < deg; ++k) {
-        const int64_t e = base + (int64_t)k * kSlice;
-        if (sell.nbr[e] < 0) continue;
-        const int32_t fs = sell.fsf[e];
-        const bool isL = fs >= 0;
-        const FaceRec<T> fr = load_face(geo.face, isL ? fs : ~fs);
-        T s[4];
-        face_state<T>(ui, g, isL ? fr.rl0 : fr.rr0, isL ? fr.rl1 : fr.rr1, isL ? fr.rl2 : fr.rr2, s);
-        store4(FVb + e * 4, s);
+    if constexpr (DEG > 0) {
+        // One lane per cell for all bins: the side records are loaded once.
+        const int64_t i = blk * kBlock + threadIdx.x;
+        if (i >= nc) return;
+        CellSides<T, DEG> cs;
+        load_cell_sides<T, DEG>(i, geo, sell, cs);
+        T cell[8];
+        load4(geo.cell + i * kCellRec, cell);
+        load4(geo.cell + i * kCellRec + 4, cell + 4);
+        const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
+        for (int b = 0; b < nb; ++b) {
+            double ui[4], g[4][3];
+            limited_gradient_c<T, DEG>(i, b, nc, U, cell, cs, use_limiter, ui, g);
+            T* FVb = FV + (int64_t)b * n_entries * 4;
+#pragma unroll
+            for (int k = 0; k < DEG; ++k) {
+                if (cs.nbr[k] < 0) continue;
+                T st[4];
+                face_state<T>(ui, g, cs.r[k][0], cs.r[k][1], cs.r[k][2], st);
+                store4(FVb + (base + (int64_t)k * kSlice) * 4, st);
+            }
+        }
+    } else {
+        const int b = (int)(blk % nb);
+        const int64_t i = (blk / nb) * kBlock + threadIdx.x;
+        if (i >= nc) return;
+        double ui[4], g[4][3];
+        T rr[SlotCount<DEG>::kMax][3];
+        bool ok[SlotCount<DEG>::kMax];
+        limited_gradient_s<T, DEG>(i, b, nc, U, geo, sell, use_limiter, ui, g, rr, ok);
+        export_face_states<T, DEG>(i, ui, g, rr, ok, geo, sell, FV + (int64_t)b * n_entries * 4, 0);
     }
 }
 
@@ -266,7 +305,9 @@ __global__ __launch_bounds__(kBlock) void k_gradient(const double* __restrict__ 
     const int64_t i = (blk / nb) * kBlock + threadIdx.x;
     if (i >= nc) return;
     double ui[4], g[4][3];
-    limited_gradient<double>(i, b, nc, U, geo, sell, use_limiter, ui, g);
+    double rr[1][3];
+    bool ok[1];
+    limited_gradient_s<double, 0>(i, b, nc, U, geo, sell, use_limiter, ui, g, rr, ok);
     double* Gb = G + (int64_t)(b * 12) * nc;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -331,24 +372,44 @@ __device__ inline void finish_cell(int64_t i, int b, int64_t nc, const T* ui, co
     }
 }
 
-template <typename T, typename TA>
+template <typename T, typename TA, int DEG>
 __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ FV, T* __restrict__ Unew,
                                                  int64_t nc, int nb, int64_t n_entries, GeomView<T> geo, SellView sell,
                                                  TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
                                                  int32_t* __restrict__ part_status, int64_t n_blocks) {
     const int64_t blk = xcd_logical_block();
-    const int b = (int)(blk % nb);
-    const int64_t i = (blk / nb) * kBlock + threadIdx.x;
-    int cAdmN = 0, cAdmF = 0, cCap = 0;
-    T ui[4] = {0, 0, 0, 0};
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i < nc) {
-        load4(U + urec(b, nc, i), ui);
-        const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp};
-        cell_flux_sum<T, TA>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
+    if constexpr (DEG > 0) {
+        // One lane per (cell, bin); the geometry of the three or more bins of
+        // a tile is read by neighbouring workgroups on the same XCD.
+        const int b = (int)(blk % nb);
+        const int64_t i = (blk / nb) * kBlock + threadIdx.x;
+        int cAdmN = 0, cAdmF = 0, cCap = 0;
+        T ui[4] = {0, 0, 0, 0};
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (i < nc) {
+            CellFaces<T, DEG> cf;
+            load_cell_faces<T, DEG>(i, geo, sell, cf);
+            load4(U + urec(b, nc, i), ui);
+            const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp};
+            cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, (int64_t)sell.ptr[i / kSlice] + (i % kSlice), cf, cdt,
+                                        (TA)ui[0], acc, cAdmN, cAdmF, cCap);
+        }
+        finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
+                           part_status, n_blocks);
+    } else {
+        const int b = (int)(blk % nb);
+        const int64_t i = (blk / nb) * kBlock + threadIdx.x;
+        int cAdmN = 0, cAdmF = 0, cCap = 0;
+        T ui[4] = {0, 0, 0, 0};
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (i < nc) {
+            load4(U + urec(b, nc, i), ui);
+            const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp};
+            cell_flux_sum_s<T, TA, DEG>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
+        }
+        finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
+                           part_status, n_blocks);
     }
-    finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt, part_status,
-                       n_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
 // cells of a face still obtain fluxes of exactly opposite sign.
 // ---------------------------------------------------------------------------
 
-template <typename T, typename TA>
+template <typename T, typename TA, int DEG>
 __global__ __launch_bounds__(kBlock) void k_transport(const T* __restrict__ U, T* __restrict__ Unew, int64_t nc,
                                                       int nb, GeomView<T> geo, SellView sell, TileView tile,
                                                       int use_limiter, TA cdt, double* __restrict__ part_nv,
@@ -384,21 +445,34 @@ __global__ __launch_bounds__(kBlock) void k_transport(const T* __restrict__ U, T
         const int64_t c = own ? c0 + item : (int64_t)tile.halo_cell[hq0 + (item - kBlock)];
         if (c >= nc) continue;
         double uc[4], g[4][3];
-        limited_gradient<T>(c, b, nc, U, geo, sell, use_limiter, uc, g);
-        const int64_t slice = c / kSlice;
-        const int64_t base = (int64_t)sell.ptr[slice] + (c % kSlice);
-        const int32_t sp = own ? 0 : tile.hside_ptr[hq0 + (item - kBlock)];
-        const int32_t n_sides = own ? sell.deg[slice] : tile.hside_ptr[hq0 + (item - kBlock) + 1] - sp;
-        for (int32_t q = 0; q < n_sides; ++q) {
-            const int64_t e = own ? base + (int64_t)q * kSlice : (int64_t)tile.hside_entry[sp + q];
-            const int32_t fs = sell.fsf[e];
-            if (sell.nbr[e] < 0) continue;
-            const int64_t dst = own ? e - e0 : tile_sides + (sp + q - hs0);
-            const bool isL = fs >= 0;
-            const FaceRec<T> fr = load_face(geo.face, isL ? fs : ~fs);
-            T s[4];
-            face_state<T>(uc, g, isL ? fr.rl0 : fr.rr0, isL ? fr.rl1 : fr.rr1, isL ? fr.rl2 : fr.rr2, s);
-            store4(lds + dst * 4, s);
+        T rr[SlotCount<DEG>::kMax][3];
+        bool ok[SlotCount<DEG>::kMax];
+        if constexpr (DEG > 0) {
+            CellSides<T, DEG> cs;
+            load_cell_sides<T, DEG>(c, geo, sell, cs);
+            T cell[8];
+            load4(geo.cell + c * kCellRec, cell);
+            load4(geo.cell + c * kCellRec + 4, cell + 4);
+            limited_gradient_c<T, DEG>(c, b, nc, U, cell, cs, use_limiter, uc, g);
+#pragma unroll
+            for (int k = 0; k < DEG; ++k) {
+                rr[k][0] = cs.r[k][0]; rr[k][1] = cs.r[k][1]; rr[k][2] = cs.r[k][2];
+                ok[k] = cs.nbr[k] >= 0;
+            }
+        } else {
+            limited_gradient_s<T, DEG>(c, b, nc, U, geo, sell, use_limiter, uc, g, rr, ok);
+        }
+        if (own) {
+            export_face_states<T, DEG>(c, uc, g, rr, ok, geo, sell, lds, e0);
+        } else {
+            const int32_t sp = tile.hside_ptr[hq0 + (item - kBlock)];
+            const int32_t n_sides = tile.hside_ptr[hq0 + (item - kBlock) + 1] - sp;
+            for (int32_t q = 0; q < n_sides; ++q) {
+                const int64_t e = tile.hside_entry[sp + q];
+                T st[4];
+                face_state<T>(uc, g, geo.sv(kSR0, e), geo.sv(kSR1, e), geo.sv(kSR2, e), st);
+                store4(lds + (tile_sides + (sp + q - hs0)) * 4, st);
+            }
         }
     }
     __syncthreads();
@@ -410,7 +484,14 @@ __global__ __launch_bounds__(kBlock) void k_transport(const T* __restrict__ U, T
     if (i < nc) {
         load4(U + urec(b, nc, i), ui);
         const TileFaceStates<T> fsv{lds, e0, tile.lds_opp};
-        cell_flux_sum<T, TA>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
+        if constexpr (DEG > 0) {
+            CellFaces<T, DEG> cf;
+            load_cell_faces<T, DEG>(i, geo, sell, cf);
+            cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, (int64_t)sell.ptr[i / kSlice] + (i % kSlice), cf, cdt,
+                                        (TA)ui[0], acc, cAdmN, cAdmF, cCap);
+        } else {
+            cell_flux_sum_s<T, TA, DEG>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
+        }
     }
     finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt, part_status,
                        n_blocks);
@@ -575,11 +656,24 @@ void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, cons
 int64_t chem_blocks(int64_t nc) { return (int64_t)grid_for(nc, (int64_t)kBlock * chem_chunk(nc)); }
 int64_t transport_blocks(int64_t nc, int nb) { return (int64_t)grid_for(nc, kBlock) * nb; }
 
+// The transport kernels are specialised for meshes whose slices all have 6
+// slots (lattices) or 14 (the staggered BCC mesh); other meshes take the
+// general form.
+#define RT_DEG_DISPATCH(deg, CALL) \
+    switch (deg) {                 \
+        case 6: CALL(6); break;    \
+        case 14: CALL(14); break;  \
+        default: CALL(0); break;   \
+    }
+
 template <typename T>
 void launch_facestate(const T* U, T* FV, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
                       const SellView& sell, int use_limiter, hipStream_t s) {
-    hipLaunchKernelGGL(k_facestate<T>, dim3((unsigned)transport_blocks(nc, nb)), dim3(kBlock), 0, s, U, FV, nc, nb,
-                       n_entries, geo, sell, use_limiter);
+#define RT_CALL(D)                                                                                             \
+    hipLaunchKernelGGL((k_facestate<T, D>), dim3((unsigned)(D > 0 ? grid_for(nc, kBlock) : transport_blocks(nc, nb))), \
+                       dim3(kBlock), 0, s, U, FV, nc, nb, n_entries, geo, sell, use_limiter)
+    RT_DEG_DISPATCH(sell.uniform_deg, RT_CALL)
+#undef RT_CALL
 }
 
 void launch_gradient(const double* U, double* G, int64_t nc, int nb, const GeomView<double>& geo, const SellView& sell,
@@ -593,20 +687,34 @@ void launch_flux(const T* U, const T* FV, T* Unew, int64_t nc, int nb, int64_t n
                  const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
                  hipStream_t s) {
     const int64_t nblk = transport_blocks(nc, nb);
-    hipLaunchKernelGGL((k_flux<T, T>), dim3((unsigned)nblk), dim3(kBlock), 0, s, U, FV, Unew, nc, nb, n_entries, geo,
-                       sell, (T)cdt, part_nv, part_cnt, part_status, nblk);
+#define RT_CALL(D)                                                                                               \
+    hipLaunchKernelGGL((k_flux<T, T, D>), dim3((unsigned)nblk), dim3(kBlock), 0, s, U, FV, Unew, nc, nb, n_entries, \
+                       geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk)
+    RT_DEG_DISPATCH(sell.uniform_deg, RT_CALL)
+#undef RT_CALL
+}
+
+template <typename T, int D>
+static void launch_transport_deg(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>& geo,
+                                 const SellView& sell, const TileView& tile, size_t lds_bytes, int use_limiter,
+                                 double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
+    const int64_t nblk = transport_blocks(nc, nb);
+    if (lds_bytes > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport<T, T, D>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    hipLaunchKernelGGL((k_transport<T, T, D>), dim3((unsigned)nblk), dim3(kBlock), lds_bytes, s, U, Unew, nc, nb,
+                       geo, sell, tile, use_limiter, (T)cdt, part_nv, part_cnt, part_status, nblk);
 }
 
 template <typename T>
 void launch_transport(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
                       const TileView& tile, size_t lds_bytes, int use_limiter, double cdt, double* part_nv,
                       int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
-    const int64_t nblk = transport_blocks(nc, nb);
-    if (lds_bytes > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport<T, T>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    hipLaunchKernelGGL((k_transport<T, T>), dim3((unsigned)nblk), dim3(kBlock), lds_bytes, s, U, Unew, nc, nb, geo,
-                       sell, tile, use_limiter, (T)cdt, part_nv, part_cnt, part_status, nblk);
+#define RT_CALL(D)                                                                                            \
+    launch_transport_deg<T, D>(U, Unew, nc, nb, geo, sell, tile, lds_bytes, use_limiter, cdt, part_nv, part_cnt, \
+                               part_status, s)
+    RT_DEG_DISPATCH(sell.uniform_deg, RT_CALL)
+#undef RT_CALL
 }
 
 void launch_reduce(const double* part_nv, const int64_t* part_cnt, const int32_t* part_fstatus, int64_t n_fblocks,

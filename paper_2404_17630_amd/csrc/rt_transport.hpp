@@ -63,30 +63,155 @@ struct TileFaceStates {
     __device__ const T* other(int64_t e) const { return lds + (int64_t)lds_opp[e] * 4; }
 };
 
-// Flux sum of cell i (bin b) from the limited face states: each face's
-// flux in its canonical (L, R) orientation with the upwind cap, accumulated
-// as sigma A Phi in face-index order in FP64.  TA is the arithmetic
-// precision of the face physics.
-template <typename T, typename TA, typename FS>
-__device__ inline void cell_flux_sum(int64_t i, int b, int64_t nc, const T* __restrict__ U, const FS& fsv,
-                                     const GeomView<T>& geo, const SellView& sell, TA cdt, TA Ni, double* acc,
-                                     int& cAdmN, int& cAdmF, int& cCap) {
-    const int64_t slice = i / kSlice;
-    const int32_t deg = sell.deg[slice];
-    const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
-    for (int k = 0; k < deg; ++k) {
+// The limited state of a cell at one of its faces, U_i + g . r_if, rounded
+// to the storage precision once.
+template <typename T>
+__device__ inline void face_state(const double* ui, const double (*g)[3], double r0, double r1, double r2, T* s) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s[v] = (T)(ui[v] + (g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2));
+}
+
+// Barth-Jespersen factor alpha = min(1, min_k psi_k) of one variable, with
+// psi_k = (u_max - u_i) / delta_k for delta_k = g . r_k > 0 and
+// (u_min - u_i) / delta_k for delta_k < 0 (Sec. 2.3.2).  Each psi_k is kept
+// as a fraction num / den with den > 0, so choosing the smallest takes no
+// division (num_k den < num den_k); one division gives alpha at the end.
+struct BJFactor {
+    double num = 1.0, den = 1.0;
+    __device__ void add(double delta, double up, double down) {  // up = u_max - u_i, down = u_i - u_min
+        double n, d;
+        if (delta > 0.0) { n = up; d = delta; }
+        else if (delta < 0.0) { n = down; d = -delta; }
+        else return;
+        if (n * den < num * d) { num = n; den = d; }
+    }
+    __device__ double alpha() const { return num / den; }
+};
+
+// ---------------------------------------------------------------------------
+// The same two steps from the per-side records.  DEG > 0: every slice of the
+// mesh has exactly DEG slots, the slot loops are unrolled and the face
+// offsets stay in registers; DEG == 0: any degree.
+// ---------------------------------------------------------------------------
+
+template <int DEG>
+struct SlotCount {
+    static constexpr int kMax = DEG > 0 ? DEG : 1;
+};
+
+// Side records of one cell's DEG slots (DEG > 0), loaded once and reused
+// for every bin: the neighbours, the least-squares weights and face offsets
+// (gradient), and the face's orientation, A, n and V/n_faces (flux).
+template <typename T, int DEG>
+struct CellSides {
+    int32_t nbr[DEG];
+    T w[DEG][3], r[DEG][3];
+};
+template <typename T, int DEG>
+__device__ inline void load_cell_sides(int64_t i, const GeomView<T>& geo, const SellView& sell, CellSides<T, DEG>& cs) {
+    const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
+#pragma unroll
+    for (int k = 0; k < DEG; ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
-        const int32_t j = sell.nbr[e];
+        cs.nbr[k] = sell.nbr[e];
+        cs.w[k][0] = geo.sv(kSW0, e); cs.w[k][1] = geo.sv(kSW1, e); cs.w[k][2] = geo.sv(kSW2, e);
+        cs.r[k][0] = geo.sv(kSR0, e); cs.r[k][1] = geo.sv(kSR1, e); cs.r[k][2] = geo.sv(kSR2, e);
+    }
+}
+template <typename T, int DEG>
+struct CellFaces {
+    int32_t nbr[DEG];
+    bool isL[DEG];
+    T A[DEG], n[DEG][3], vL[DEG], vR[DEG];
+};
+template <typename T, int DEG>
+__device__ inline void load_cell_faces(int64_t i, const GeomView<T>& geo, const SellView& sell, CellFaces<T, DEG>& cf) {
+    const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
+#pragma unroll
+    for (int k = 0; k < DEG; ++k) {
+        const int64_t e = base + (int64_t)k * kSlice;
+        cf.nbr[k] = sell.nbr[e];
+        cf.isL[k] = sell.fsf[e] >= 0;
+        cf.A[k] = geo.sv(kSA, e);
+        cf.n[k][0] = geo.sv(kSN0, e); cf.n[k][1] = geo.sv(kSN1, e); cf.n[k][2] = geo.sv(kSN2, e);
+        cf.vL[k] = geo.sv(kSVL, e); cf.vR[k] = geo.sv(kSVR, e);
+    }
+}
+
+// Limited gradient of cell i (bin b) from its loaded side records (DEG > 0).
+template <typename T, int DEG>
+__device__ inline void limited_gradient_c(int64_t i, int b, int64_t nc, const T* __restrict__ U, const T* cell,
+                                          const CellSides<T, DEG>& cs, int use_limiter, double* ui, double (*g)[3]) {
+    T u0[4];
+    load4(U + urec(b, nc, i), u0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ui[v] = (double)u0[v];
+    double bs[4][3], umax[4], umin[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        bs[v][0] = bs[v][1] = bs[v][2] = 0.0;
+        umax[v] = umin[v] = ui[v];
+    }
+#pragma unroll
+    for (int k = 0; k < DEG; ++k) {
+        const int32_t j = cs.nbr[k];
         if (j < 0) continue;
-        const int32_t fs = sell.fsf[e];
-        const bool isL = fs >= 0;
-        const int64_t f = isL ? fs : ~fs;
-        const FaceRec<T> fr = load_face(geo.face, f);
+        const double w0 = (double)cs.w[k][0], w1 = (double)cs.w[k][1], w2 = (double)cs.w[k][2];
+        T uj[4];
+        load4(U + urec(b, nc, j), uj);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double ujv = (double)uj[v];
+            const double dphi = ujv - ui[v];
+            bs[v][0] += w0 * dphi;
+            bs[v][1] += w1 * dphi;
+            bs[v][2] += w2 * dphi;
+            umax[v] = ujv > umax[v] ? ujv : umax[v];
+            umin[v] = ujv < umin[v] ? ujv : umin[v];
+        }
+    }
+    const double mxx = cell[0], myy = cell[1], mzz = cell[2], mxy = cell[3], mxz = cell[4], myz = cell[5];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        g[v][0] = mxx * bs[v][0] + mxy * bs[v][1] + mxz * bs[v][2];
+        g[v][1] = mxy * bs[v][0] + myy * bs[v][1] + myz * bs[v][2];
+        g[v][2] = mxz * bs[v][0] + myz * bs[v][1] + mzz * bs[v][2];
+    }
+    if (!use_limiter) return;
+    BJFactor bj[4];
+#pragma unroll
+    for (int k = 0; k < DEG; ++k) {
+        if (cs.nbr[k] < 0) continue;
+        const double r0 = cs.r[k][0], r1 = cs.r[k][1], r2 = cs.r[k][2];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2, umax[v] - ui[v], ui[v] - umin[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const double alpha = bj[v].alpha();
+        g[v][0] *= alpha;
+        g[v][1] *= alpha;
+        g[v][2] *= alpha;
+    }
+}
+
+// Flux sum of cell i (bin b) from its loaded face records (DEG > 0).
+template <typename T, typename TA, int DEG, typename FS>
+__device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __restrict__ U, const FS& fsv,
+                                       int64_t base, const CellFaces<T, DEG>& cf, TA cdt, TA Ni, double* acc,
+                                       int& cAdmN, int& cAdmF, int& cCap) {
+#pragma unroll
+    for (int k = 0; k < DEG; ++k) {
+        const int32_t j = cf.nbr[k];
+        if (j < 0) continue;
+        const int64_t e = base + (int64_t)k * kSlice;
+        const bool isL = cf.isL[k];
+        const TA A = (TA)cf.A[k];
         T so[4], sn[4];
         load4(fsv.own(e), so);
         load4(fsv.other(e), sn);
         const TA Nj = (TA)U[urec(b, nc, j)];
-        // Canonical orientation: L then R, whichever lane computes it.
         TA sL[4], sR[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -96,32 +221,24 @@ __device__ inline void cell_flux_sum(int64_t i, int b, int64_t nc, const T* __re
         const TA NL = isL ? Ni : Nj, NR = isL ? Nj : Ni;
         int aN = 0, aF = 0;
         TA Phi[4];
-        const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)fr.vcL, (TA)fr.vcR, (TA)fr.n0, (TA)fr.n1,
-                                             (TA)fr.n2, (TA)fr.A, cdt, Phi, aN, aF);
+        const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)cf.vL[k], (TA)cf.vR[k], (TA)cf.n[k][0],
+                                             (TA)cf.n[k][1], (TA)cf.n[k][2], A, cdt, Phi, aN, aF);
         if (isL) {
             cAdmN += aN; cAdmF += aF; cCap += capped ? 1 : 0;
         }
-        const TA sA = isL ? (TA)fr.A : -(TA)fr.A;
+        const TA sA = isL ? A : -A;
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += (double)(sA * Phi[v]);
     }
 }
 
-// The limited state of a cell at one of its faces, U_i + g . r_if, rounded
-// to the storage precision once.
-template <typename T>
-__device__ inline void face_state(const double* ui, const double (*g)[3], double r0, double r1, double r2, T* s) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) s[v] = (T)(ui[v] + (g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2));
-}
-
-// Limited least-squares gradient of the four fields of cell i (bin b) in
-// FP64: g = M^-1 sum_j w_ij (phi_j - phi_i), w_ij = A d / |d|^2 with
-// d = s_j - s_i through the face, then a Barth-Jespersen factor per variable
-// (Sec. 2.3.2).  Returns the cell's fields in ui.
-template <typename T>
-__device__ inline void limited_gradient(int64_t i, int b, int64_t nc, const T* __restrict__ U, const GeomView<T>& geo,
-                                        const SellView& sell, int use_limiter, double* ui, double (*g)[3]) {
+// Limited gradient of the four fields of cell i (bin b) in FP64; ui the
+// cell's fields; for DEG > 0 the offsets r_if of its slots in rr and their
+// validity in ok.
+template <typename T, int DEG>
+__device__ inline void limited_gradient_s(int64_t i, int b, int64_t nc, const T* __restrict__ U, const GeomView<T>& geo,
+                                          const SellView& sell, int use_limiter, double* ui, double (*g)[3],
+                                          T (*rr)[3], bool* ok) {
     T u0[4];
     load4(U + urec(b, nc, i), u0);
 #pragma unroll
@@ -133,21 +250,18 @@ __device__ inline void limited_gradient(int64_t i, int b, int64_t nc, const T* _
         umax[v] = umin[v] = ui[v];
     }
     const int64_t slice = i / kSlice;
-    const int32_t deg = sell.deg[slice];
+    const int32_t deg = DEG > 0 ? DEG : sell.deg[slice];
     const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
-    for (int k = 0; k < deg; ++k) {
+#pragma unroll(SlotCount<DEG>::kMax)
+    for (int k = 0; k < (DEG > 0 ? DEG : deg); ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
         const int32_t j = sell.nbr[e];
+        if (DEG > 0) {
+            rr[k][0] = geo.sv(kSR0, e); rr[k][1] = geo.sv(kSR1, e); rr[k][2] = geo.sv(kSR2, e);
+            ok[k] = j >= 0;
+        }
         if (j < 0) continue;
-        const int32_t fs = sell.fsf[e];
-        const bool isL = fs >= 0;
-        const FaceRec<T> fr = load_face(geo.face, isL ? fs : ~fs);
-        // d = r_if - r_jf = s_j - s_i
-        const double d0 = isL ? (double)fr.rl0 - (double)fr.rr0 : (double)fr.rr0 - (double)fr.rl0;
-        const double d1 = isL ? (double)fr.rl1 - (double)fr.rr1 : (double)fr.rr1 - (double)fr.rl1;
-        const double d2 = isL ? (double)fr.rl2 - (double)fr.rr2 : (double)fr.rr2 - (double)fr.rl2;
-        const double s = (double)fr.A / (d0 * d0 + d1 * d1 + d2 * d2);
-        const double w0 = d0 * s, w1 = d1 * s, w2 = d2 * s;
+        const double w0 = (double)geo.sv(kSW0, e), w1 = (double)geo.sv(kSW1, e), w2 = (double)geo.sv(kSW2, e);
         T uj[4];
         load4(U + urec(b, nc, j), uj);
 #pragma unroll
@@ -172,28 +286,68 @@ __device__ inline void limited_gradient(int64_t i, int b, int64_t nc, const T* _
         g[v][2] = mxz * bs[v][0] + myz * bs[v][1] + mzz * bs[v][2];
     }
     if (!use_limiter) return;
-    double alpha[4] = {1.0, 1.0, 1.0, 1.0};
-    for (int k = 0; k < deg; ++k) {
-        const int64_t e = base + (int64_t)k * kSlice;
-        if (sell.nbr[e] < 0) continue;
-        const int32_t fs = sell.fsf[e];
-        const bool isL = fs >= 0;
-        const FaceRec<T> fr = load_face(geo.face, isL ? fs : ~fs);
-        const double r0 = isL ? fr.rl0 : fr.rr0, r1 = isL ? fr.rl1 : fr.rr1, r2 = isL ? fr.rl2 : fr.rr2;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const double delta = g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2;
-            double psi = 1.0;
-            if (delta > 0.0) psi = (umax[v] - ui[v]) / delta;
-            else if (delta < 0.0) psi = (umin[v] - ui[v]) / delta;
-            alpha[v] = psi < alpha[v] ? psi : alpha[v];
+    BJFactor bj[4];
+#pragma unroll(SlotCount<DEG>::kMax)
+    for (int k = 0; k < (DEG > 0 ? DEG : deg); ++k) {
+        double r0, r1, r2;
+        if (DEG > 0) {
+            if (!ok[k]) continue;
+            r0 = rr[k][0]; r1 = rr[k][1]; r2 = rr[k][2];
+        } else {
+            const int64_t e = base + (int64_t)k * kSlice;
+            if (sell.nbr[e] < 0) continue;
+            r0 = geo.sv(kSR0, e); r1 = geo.sv(kSR1, e); r2 = geo.sv(kSR2, e);
         }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2, umax[v] - ui[v], ui[v] - umin[v]);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        g[v][0] *= alpha[v];
-        g[v][1] *= alpha[v];
-        g[v][2] *= alpha[v];
+        const double alpha = bj[v].alpha();
+        g[v][0] *= alpha;
+        g[v][1] *= alpha;
+        g[v][2] *= alpha;
+    }
+}
+
+// Flux sum of cell i (bin b) from the face states and the per-side records.
+template <typename T, typename TA, int DEG, typename FS>
+__device__ inline void cell_flux_sum_s(int64_t i, int b, int64_t nc, const T* __restrict__ U, const FS& fsv,
+                                       const GeomView<T>& geo, const SellView& sell, TA cdt, TA Ni, double* acc,
+                                       int& cAdmN, int& cAdmF, int& cCap) {
+    const int64_t slice = i / kSlice;
+    const int32_t deg = DEG > 0 ? DEG : sell.deg[slice];
+    const int64_t base = (int64_t)sell.ptr[slice] + (i % kSlice);
+#pragma unroll(SlotCount<DEG>::kMax)
+    for (int k = 0; k < (DEG > 0 ? DEG : deg); ++k) {
+        const int64_t e = base + (int64_t)k * kSlice;
+        const int32_t j = sell.nbr[e];
+        if (j < 0) continue;
+        const bool isL = sell.fsf[e] >= 0;
+        const TA A = (TA)geo.sv(kSA, e);
+        const TA n0 = (TA)geo.sv(kSN0, e), n1 = (TA)geo.sv(kSN1, e), n2 = (TA)geo.sv(kSN2, e);
+        const TA vcL = (TA)geo.sv(kSVL, e), vcR = (TA)geo.sv(kSVR, e);
+        T so[4], sn[4];
+        load4(fsv.own(e), so);
+        load4(fsv.other(e), sn);
+        const TA Nj = (TA)U[urec(b, nc, j)];
+        TA sL[4], sR[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            sL[v] = (TA)(isL ? so[v] : sn[v]);
+            sR[v] = (TA)(isL ? sn[v] : so[v]);
+        }
+        const TA NL = isL ? Ni : Nj, NR = isL ? Nj : Ni;
+        int aN = 0, aF = 0;
+        TA Phi[4];
+        const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, vcL, vcR, n0, n1, n2, A, cdt, Phi, aN, aF);
+        if (isL) {
+            cAdmN += aN; cAdmF += aF; cCap += capped ? 1 : 0;
+        }
+        const TA sA = isL ? A : -A;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += (double)(sA * Phi[v]);
     }
 }
 

@@ -32,11 +32,20 @@ __host__ __device__ inline int64_t urec(int b, int64_t nc, int64_t i) { return (
 //   cell [nc][kCellRec]: inverse geometry matrix xx, yy, zz, xy, xz, yz; V; vcap
 constexpr int kFaceRec = 12;
 constexpr int kCellRec = 8;
+// Per face side (sliced-ELL entry e), structure of arrays side[c * ne + e]:
+//   w = A d / |d|^2 with d = s_j - s_i (least-squares weight vector),
+//   r = r_if (offset from the cell's centre to the face centre),
+//   A, n (L -> R), vcap_L, vcap_R of the face;
+// zeros for padding entries.  One coalesced load per component and slot.
+enum SideComp { kSW0 = 0, kSW1, kSW2, kSR0, kSR1, kSR2, kSA, kSN0, kSN1, kSN2, kSVL, kSVR, kSideComps };
 template <typename T>
 struct GeomView {
     const T* face;
     const T* cell;
+    const T* side;
     int64_t nf;
+    int64_t ne;
+    __device__ T sv(int c, int64_t e) const { return side[(int64_t)c * ne + e]; }
 };
 
 // Face sides of each cell in sliced-ELL order: slice s (cells 64s..64s+63)
@@ -50,6 +59,7 @@ struct SellView {
     const int32_t* opp;
     const int32_t* ptr;
     const int32_t* deg;
+    int32_t uniform_deg;   // slots of every slice when all are equal and specialised (6, 14), else 0
 };
 
 // Tiles of the fused transport kernel: tile t is cells [256 t, 256 t + 256)
