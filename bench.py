@@ -248,23 +248,25 @@ def main() -> int:
             return errN, p999, frac, errC
 
         errN, p999, frac, errC = n_errors(fields_mixed["N"], f64["N"])
-        # The same FP64 run on the other transport path differs from the first
-        # only in the order of its roundings: the spread it shows is what the
-        # problem itself does to a relative change of 1e-16.
-        other64 = rt.RT_TRANSPORT_FUSED if not st64_fused else rt.RT_TRANSPORT_SPLIT
+        # Conditioning of the workload itself: the FP64 run again from n_H
+        # rounded to FP32 (a relative change of at most 6e-8, the size of one
+        # FP32 rounding).  How far that moves N is what any 1e-7-level change,
+        # such as FP32 storage, can be expected to do.
         try:
-            st_o, _, _ = timed_run(rt, mesh, cfg, rt.RT_FP64, args.steps, 0, torch, transport=other64)
-            f_o = st_o.fields()
-            st_o.close()
-            oN, op999, ofrac, oC = n_errors(f_o["N"], f64["N"])
-            out["fp64_reordered_vs_fp64"] = {
-                "N_rel_max(N>1e-10 max)": oN, "N_rel_p99.9(N>1e-10 max)": op999, "N_frac_cells_rel>1e-3": ofrac,
-                "N_rel_max(stencil floor 1e-4)": oC,
-                "x_HII_abs_max": float(np.abs(f_o["species"][1] - f64["species"][1]).max()),
+            nH32 = cfg["state"]["n_H"].astype(np.float32).astype(np.float64)
+            st_p = rt.State.from_config(mesh, cfg, precision=rt.RT_FP64, n_H=nH32)
+            st_p.subcycle(args.steps, stream=torch.cuda.current_stream())
+            f_p = st_p.fields()
+            st_p.close()
+            pN, pp999, pfrac, pC = n_errors(f_p["N"], f64["N"])
+            out["fp64_nH_rounded_to_fp32_vs_fp64"] = {
+                "N_rel_max(N>1e-10 max)": pN, "N_rel_p99.9(N>1e-10 max)": pp999, "N_frac_cells_rel>1e-3": pfrac,
+                "N_rel_max(stencil floor 1e-4)": pC,
+                "x_HII_abs_max": float(np.abs(f_p["species"][1] - f64["species"][1]).max()),
             }
-            del f_o
+            del f_p
         except rt.RtError as e:
-            out["fp64_reordered_vs_fp64"] = f"unavailable: {e}"
+            out["fp64_nH_rounded_to_fp32_vs_fp64"] = f"unavailable: {e}"
         out["fp64_value"] = v64
         out["fp64_ms_per_step"] = t64 / args.steps * 1e3
         out["mixed_speedup_vs_fp64"] = value / v64

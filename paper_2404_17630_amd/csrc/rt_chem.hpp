@@ -190,13 +190,13 @@ __device__ inline int chem_attempt(const ChemParams& P, double Dt, const R& nH, 
     const R nHeI = yhe * nH * x[2];
     const R nHeII = yhe * nH * x[3];
 
-    R fac[NB], Nn[NB];
+    R ifac[NB], Nn[NB];
     R G0 = 0.0, G1 = 0.0, G2 = 0.0, heat = 0.0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const R kap = P.sigma[b][0] * nHI + P.sigma[b][1] * nHeI + P.sigma[b][2] * nHeII;
-        fac[b] = 1.0 + ct * d * kap;
-        Nn[b] = s.N[b] / fac[b];
+        ifac[b] = 1.0 / (1.0 + ct * d * kap);
+        Nn[b] = s.N[b] * ifac[b];
         G0 += ct * P.sigma[b][0] * Nn[b];
         G1 += ct * P.sigma[b][1] * Nn[b];
         G2 += ct * P.sigma[b][2] * Nn[b];
@@ -205,9 +205,9 @@ __device__ inline int chem_attempt(const ChemParams& P, double Dt, const R& nH, 
     }
 
     R xn[5];
-    const R den = 1.0 + (G0 + r.col_HI * ne + r.rec_HII * ne) * d;
-    xn[0] = (x[0] + r.rec_HII * ne * d) / den;
-    xn[1] = (x[1] + (G0 + r.col_HI * ne) * d) / den;
+    const R iden = 1.0 / (1.0 + (G0 + r.col_HI * ne + r.rec_HII * ne) * d);
+    xn[0] = (x[0] + r.rec_HII * ne * d) * iden;
+    xn[1] = (x[1] + (G0 + r.col_HI * ne) * d) * iden;
     if (hhe) {
         xn[2] = (x[2] + r.rec_HeII * ne * x[3] * d) / (1.0 + (G1 + r.col_HeI * ne) * d);
         xn[4] = (x[4] + (G2 + r.col_HeII * ne) * x[3] * d) / (1.0 + r.rec_HeIII * ne * d);
@@ -222,15 +222,23 @@ __device__ inline int chem_attempt(const ChemParams& P, double Dt, const R& nH, 
         xn[2] = x[2]; xn[3] = x[3]; xn[4] = x[4];
     }
 
+    // Largest relative change: each candidate is a fraction |change| / scale,
+    // compared without dividing; one division gives f.
     R un = s.u;
-    R f = 0.0;
+    R fnum = 0.0, fden = 1.0;
     if (!P.isothermal) {
         const R rho = kProtonMass * nH * (1.0 + 4.0 * yhe);
         un = s.u + d * (heat - cooling_rate(P, nH, x, r)) / rho;
-        f = m_abs(un - s.u) / s.u;
+        fnum = m_abs(un - s.u);
+        fden = s.u;
     }
     const int ns = hhe ? 5 : 2;
-    for (int q = 0; q < ns; ++q) f = m_max(f, m_abs(xn[q] - x[q]) / m_max(x[q], R(P.xfloor)));
+    for (int q = 0; q < ns; ++q) {
+        const R num = m_abs(xn[q] - x[q]);
+        const R den = m_max(x[q], R(P.xfloor));
+        if (val(num) * val(fden) > val(fnum) * val(den)) { fnum = num; fden = den; }
+    }
+    const R f = fnum / fden;
 
     if (val(f) > P.fmax) {
         s.d = d * (P.fs / f);
@@ -239,9 +247,9 @@ __device__ inline int chem_attempt(const ChemParams& P, double Dt, const R& nH, 
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         s.N[b] = Nn[b];
-        s.Fh[b][0] = s.Fh[b][0] / fac[b];
-        s.Fh[b][1] = s.Fh[b][1] / fac[b];
-        s.Fh[b][2] = s.Fh[b][2] / fac[b];
+        s.Fh[b][0] = s.Fh[b][0] * ifac[b];
+        s.Fh[b][1] = s.Fh[b][1] * ifac[b];
+        s.Fh[b][2] = s.Fh[b][2] * ifac[b];
     }
     for (int q = 0; q < 5; ++q) x[q] = xn[q];
     s.u = un;

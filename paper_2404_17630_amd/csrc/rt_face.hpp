@@ -20,7 +20,8 @@
 namespace rtk {
 
 // Relative size below which the flux of N through a face counts as
-// rounding noise of its two terms (see face_flux).
+// rounding noise of its terms and of the two cells' contents (see
+// face_flux).
 constexpr double kCapNoise = 1.0e-12;
 
 template <typename R, typename G>
@@ -43,7 +44,11 @@ template <typename R, typename G>
 __device__ inline void radiation_pressure_n(const R* U, G n0, G n1, G n2, R* P) {
     const R N = U[0];
     const R F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
-    if (val(N) <= 0 || val(F2) <= 0) {
+    // Isotropic when f = |Fh|/N <= 1e-8: the anisotropic part of D is
+    // (3 chi - 1)/2 = O(f^2) <= 1e-16, below the rounding of either
+    // precision, and the direction of a vanishing Fh (whose derivative is
+    // 1/|Fh|) does not enter.
+    if (val(N) <= 0 || val(F2) <= G(1e-16) * val(N) * val(N)) {
         const R third = N * G(1.0 / 3.0);
         P[0] = third * n0; P[1] = third * n1; P[2] = third * n2;
         return;
@@ -92,12 +97,16 @@ __device__ inline bool face_flux(R* sL, R* sR, const R& NL, const R& NR, G vcL, 
         const G vc = upL ? vcL : vcR;
         const R q = m_abs(Phi[0]) * cdt * A;
         if (val(Nup) * vc < val(q)) {
-            // The flux of N is a difference of terms of size N_L + N_R; when it
-            // is at their rounding level (free streaming along n into an empty
-            // cell) its sign and size are noise, and so is the dependence of
-            // theta on the face states: theta is then held constant for the
+            // The flux of N is a difference of terms of size N_L* + N_R*; when
+            // it is at their rounding level, or at that of the two cells'
+            // contents (free streaming along n into an empty cell, a face
+            // state that is the rounding residue of a limited extrapolation),
+            // its sign and size are noise, and so is the dependence of theta
+            // on the face states: theta is then held constant for the
             // derivative.  The value is the same either way.
-            const bool noise = (double)val(m_abs(Phi[0])) <= kCapNoise * (double)(val(sL[0]) + val(sR[0]));
+            const bool noise = (double)val(m_abs(Phi[0])) <=
+                               kCapNoise * ((double)val(sL[0]) + (double)val(sR[0]) + (double)val(NL) +
+                                            (double)val(NR));
             if (noise) {
                 const auto th = val(Nup) * vc / val(q);
 #pragma unroll
