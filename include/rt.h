@@ -169,12 +169,14 @@ int rt_mesh_destroy(rt_mesh* mesh);
  * sptr[i/64] + 64 k + i%64, with nbr (neighbour, -1 for padding), fsf (face
  * index f, or ~f when the cell is the face's R cell) and opp (the entry of
  * the same face in the neighbour's slots).  Tiles of the fused transport
- * kernel (cells 256 t .. 256 t + 255, face states in LDS): lds_opp (LDS slot
- * of the opposite state of each entry; the tile's own entries occupy slots
- * 0 .. ptr[4t+4] - ptr[4t] - 1 in entry order, its halo sides follow),
+ * kernel (cells T t .. T t + T - 1 with T = RT_TILE_CELLS, face states in
+ * LDS): lds_opp (LDS slot of the opposite state of each entry; the tile's
+ * own entries occupy slots 0 .. ptr[(t+1) T/64] - ptr[t T/64] - 1 in entry
+ * order, its halo sides follow),
  * halo_ptr [n_tiles + 1] into halo_cell (cells outside the tile that share
  * a face with it), hside_ptr [n_halo + 1] into hside_entry (the entries of
  * each halo cell that face the tile, in the order of their LDS slots). */
+#define RT_TILE_CELLS        256   /* cells per tile of the fused transport kernel */
 #define RT_TABLE_NBR         0
 #define RT_TABLE_FSF         1
 #define RT_TABLE_OPP         2

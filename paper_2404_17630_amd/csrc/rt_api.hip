@@ -176,12 +176,16 @@ int rt_mesh::build_float_geometry() {
     return RT_OK;
 }
 
-// Tiles of 256 cells for the fused transport kernel: the LDS slot of every
+// Tiles of kTileCells cells for the fused transport kernel: the LDS slot of every
 // face side's opposite state, and the halo cells with the sides they
 // contribute, grouped per tile in (cell, entry) order.
+static_assert(kTileCells == RT_TILE_CELLS, "tile size of the header and the kernels");
+static_assert(kTileCells % kBlock == 0 && kTileCells % kSlice == 0, "tiles are whole blocks and slices");
+static_assert(kTileThreads == kTileCells, "one thread per tile cell in the flux phase");
+
 void rt_mesh::build_tiles() {
     const int64_t ns = (int64_t)sdeg.size();
-    const int64_t ntiles = (nc + kBlock - 1) / kBlock;
+    const int64_t ntiles = (nc + kTileCells - 1) / kTileCells;
     lds_opp.assign(n_entries, -1);
     halo_ptr.assign(ntiles + 1, 0);
     halo_cell.clear();
@@ -194,7 +198,7 @@ void rt_mesh::build_tiles() {
     };
     std::vector<Ext> ext;
     for (int64_t t = 0; t < ntiles; ++t) {
-        const int64_t c0 = t * kBlock, c1 = std::min<int64_t>(nc, c0 + kBlock);
+        const int64_t c0 = t * kTileCells, c1 = std::min<int64_t>(nc, c0 + kTileCells);
         const int64_t e0 = sptr[t * kTileSlices];
         const int64_t tile_sides = (int64_t)sptr[std::min<int64_t>(ns, (t + 1) * kTileSlices)] - e0;
         ext.clear();
@@ -227,50 +231,57 @@ void rt_mesh::build_tiles() {
 }
 
 // Per face side records in the transport precision (rtk::SideComp), one
-// component at a time.
+// group at a time.
 int rt_mesh::build_side_geometry(size_t tbytes) {
     DevMem& d = tbytes == 4 ? d_side32 : d_side64;
     if (d.ptr) return RT_OK;
     const int64_t ne = n_entries;
     int rc;
-    if ((rc = d.alloc((size_t)kSideComps * ne * tbytes))) return rc;
-    std::vector<double> comp(ne);
-    std::vector<float> comp32(tbytes == 4 ? ne : 0);
-    for (int c = 0; c < kSideComps; ++c) {
+    if ((rc = d.alloc((size_t)kSideGroups * 4 * ne * tbytes))) return rc;
+    std::vector<double> grp((size_t)4 * ne);
+    std::vector<float> grp32(tbytes == 4 ? 4 * ne : 0);
+    for (int g = 0; g < kSideGroups; ++g) {
         for (int64_t e = 0; e < ne; ++e) {
-            double v = 0.0;
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
             if (nbr[e] >= 0) {
                 const bool isL = fsf[e] >= 0;
                 const double* rec = &face[(size_t)(isL ? fsf[e] : ~fsf[e]) * kFaceRec];
                 const double* ro = isL ? rec + 4 : rec + 7;     // own offset
                 const double* rn = isL ? rec + 7 : rec + 4;     // neighbour's offset
-                if (c <= kSW2) {
-                    const double d0 = ro[0] - rn[0], d1 = ro[1] - rn[1], d2 = ro[2] - rn[2];
-                    const double sc = rec[0] / (d0 * d0 + d1 * d1 + d2 * d2);
-                    v = (c == kSW0 ? d0 : c == kSW1 ? d1 : d2) * sc;
-                } else if (c <= kSR2) {
-                    v = ro[c - kSR0];
-                } else if (c == kSA) {
-                    v = rec[0];
-                } else if (c <= kSN2) {
-                    v = rec[1 + (c - kSN0)];
-                } else {
-                    v = rec[c == kSVL ? 10 : 11];
-                }
+                double all[kSideComps];
+                const double d0 = ro[0] - rn[0], d1 = ro[1] - rn[1], d2 = ro[2] - rn[2];
+                const double sc = rec[0] / (d0 * d0 + d1 * d1 + d2 * d2);
+                all[kSW0] = d0 * sc; all[kSW1] = d1 * sc; all[kSW2] = d2 * sc;
+                all[kSR0] = ro[0]; all[kSR1] = ro[1]; all[kSR2] = ro[2];
+                all[kSA] = rec[0];
+                all[kSN0] = rec[1]; all[kSN1] = rec[2]; all[kSN2] = rec[3];
+                all[kSVL] = rec[10]; all[kSVR] = rec[11];
+                for (int q = 0; q < 4; ++q) v[q] = all[4 * g + q];
             }
-            comp[e] = v;
+            for (int q = 0; q < 4; ++q) grp[(size_t)4 * e + q] = v[q];
         }
-        void* dst = (char*)d.ptr + (size_t)c * ne * tbytes;
+        void* dst = (char*)d.ptr + (size_t)g * 4 * ne * tbytes;
         hipError_t err;
         if (tbytes == 4) {
-            for (int64_t e = 0; e < ne; ++e) comp32[e] = (float)comp[e];
-            err = hipMemcpy(dst, comp32.data(), ne * 4, hipMemcpyHostToDevice);
+            for (size_t q = 0; q < grp.size(); ++q) grp32[q] = (float)grp[q];
+            err = hipMemcpy(dst, grp32.data(), (size_t)4 * ne * 4, hipMemcpyHostToDevice);
         } else {
-            err = hipMemcpy(dst, comp.data(), ne * 8, hipMemcpyHostToDevice);
+            err = hipMemcpy(dst, grp.data(), (size_t)4 * ne * 8, hipMemcpyHostToDevice);
         }
         if (err != hipSuccess) return rt_fail(RT_EDEVICE, "side geometry upload: %s", hipGetErrorString(err));
     }
     return RT_OK;
+}
+
+// (nbr, fsf, opp, 0) of every sliced-ELL entry as one 16-byte record.
+static int upload_packed_index(rt_mesh* m) {
+    std::vector<int32_t> p((size_t)4 * m->n_entries, 0);
+    for (int64_t e = 0; e < m->n_entries; ++e) {
+        p[4 * e] = m->nbr[e];
+        p[4 * e + 1] = m->fsf[e];
+        p[4 * e + 2] = m->opp[e];
+    }
+    return m->d_idx.upload(p.data(), p.size() * 4);
 }
 
 extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const double* centre, int64_t n_faces,
@@ -479,7 +490,7 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
         (rc = m->d_fsf.upload(m->fsf.data(), m->fsf.size() * 4)) ||
         (rc = m->d_opp.upload(m->opp.data(), m->opp.size() * 4)) ||
         (rc = m->d_sptr.upload(m->sptr.data(), m->sptr.size() * 4)) ||
-        (rc = m->d_sdeg.upload(m->sdeg.data(), m->sdeg.size() * 4)) ||
+        (rc = m->d_sdeg.upload(m->sdeg.data(), m->sdeg.size() * 4)) || (rc = upload_packed_index(m)) ||
         (rc = m->d_lds_opp.upload(m->lds_opp.data(), m->lds_opp.size() * 4)) ||
         (rc = m->d_halo_ptr.upload(m->halo_ptr.data(), m->halo_ptr.size() * 4)) ||
         (rc = m->d_halo_cell.upload(m->halo_cell.data(), m->halo_cell.size() * 4)) ||
@@ -905,7 +916,8 @@ GeomView<double> rt_geo64(const rt_mesh* m) { return geom_view<double>(m); }
 
 SellView rt_sell(const rt_mesh* m) {
     return SellView{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_opp.ptr,
-                    (const int32_t*)m->d_sptr.ptr, (const int32_t*)m->d_sdeg.ptr, m->uniform_deg};
+                    (const int32_t*)m->d_sptr.ptr, (const int32_t*)m->d_sdeg.ptr, (const int4*)m->d_idx.ptr,
+                    m->uniform_deg};
 }
 
 // One piece of a subcycle on explicit buffers (U, G in the state's precision).

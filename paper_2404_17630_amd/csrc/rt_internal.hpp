@@ -48,7 +48,7 @@ struct rt_mesh {
     bool geo32_ready = false;
     DevMem d_side32, d_side64;   // per face side records (rtk::SideComp), built on first use
     int32_t uniform_deg = 0;     // rtk::SellView::uniform_deg
-    DevMem d_nbr, d_fsf, d_opp, d_sptr, d_sdeg;
+    DevMem d_nbr, d_fsf, d_opp, d_sptr, d_sdeg, d_idx;
     // Tiles of the fused transport kernel (rtk::TileView).
     std::vector<int32_t> lds_opp, halo_ptr, halo_cell, hside_ptr, hside_entry;
     int64_t tile_max_sides = 0;  // largest tile + halo side count

@@ -61,7 +61,7 @@ __device__ inline int wave_or(int v) {
 }
 
 // Sum over the block; the result is valid in thread 0.
-template <typename V>
+template <typename V, int NT = kBlock>
 __device__ inline V block_sum(V v, V* lds) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6;
@@ -70,7 +70,7 @@ __device__ inline V block_sum(V v, V* lds) {
     __syncthreads();
     V s = 0;
     if (threadIdx.x == 0)
-        for (int k = 0; k < kBlock / 64; ++k) s += lds[k];
+        for (int k = 0; k < NT / 64; ++k) s += lds[k];
     return s;
 }
 template <typename V>
@@ -85,6 +85,7 @@ __device__ inline V block_max(V v, V* lds) {
         for (int k = 1; k < kBlock / 64; ++k) s = lds[k] > s ? lds[k] : s;
     return s;
 }
+template <int NT = kBlock>
 __device__ inline int block_or(int v, int* lds) {
     v = wave_or(v);
     const int w = threadIdx.x >> 6;
@@ -93,7 +94,7 @@ __device__ inline int block_or(int v, int* lds) {
     __syncthreads();
     int s = 0;
     if (threadIdx.x == 0)
-        for (int k = 0; k < kBlock / 64; ++k) s |= lds[k];
+        for (int k = 0; k < NT / 64; ++k) s |= lds[k];
     return s;
 }
 
@@ -260,8 +261,9 @@ __global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T
                                                       int use_limiter) {
     const int64_t blk = xcd_logical_block();
     if constexpr (DEG > 0) {
-        // One lane per cell for all bins: the side records are loaded once.
-        const int64_t i = blk * kBlock + threadIdx.x;
+        // One lane per (cell, bin) with the cell's side records in registers.
+        const int b = (int)(blk % nb);
+        const int64_t i = (blk / nb) * kBlock + threadIdx.x;
         if (i >= nc) return;
         CellSides<T, DEG> cs;
         load_cell_sides<T, DEG>(i, geo, sell, cs);
@@ -269,17 +271,15 @@ __global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T
         load4(geo.cell + i * kCellRec, cell);
         load4(geo.cell + i * kCellRec + 4, cell + 4);
         const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
-        for (int b = 0; b < nb; ++b) {
-            double ui[4], g[4][3];
-            limited_gradient_c<T, DEG>(i, b, nc, U, cell, cs, use_limiter, ui, g);
-            T* FVb = FV + (int64_t)b * n_entries * 4;
+        double ui[4], g[4][3];
+        limited_gradient_c<T, DEG>(i, b, nc, U, cell, cs, use_limiter, ui, g);
+        T* FVb = FV + (int64_t)b * n_entries * 4;
 #pragma unroll
-            for (int k = 0; k < DEG; ++k) {
-                if (cs.nbr[k] < 0) continue;
-                T st[4];
-                face_state<T>(ui, g, cs.r[k][0], cs.r[k][1], cs.r[k][2], st);
-                store4(FVb + (base + (int64_t)k * kSlice) * 4, st);
-            }
+        for (int k = 0; k < DEG; ++k) {
+            if (cs.nbr[k] < 0) continue;
+            T st[4];
+            face_state<T>(ui, g, cs.r[k][0], cs.r[k][1], cs.r[k][2], st);
+            store4(FVb + (base + (int64_t)k * kSlice) * 4, st);
         }
     } else {
         const int b = (int)(blk % nb);
@@ -324,43 +324,44 @@ __global__ __launch_bounds__(kBlock) void k_gradient(const double* __restrict__ 
 // counters and status, accumulated across the subcycles of one call.
 // ---------------------------------------------------------------------------
 
-// Divergence update of cell i from its flux sum, post-update guards, the new
-// record, and the block's partials (sum N V of this bin, counters, status)
-// accumulated across the subcycles of one call.  Called by every thread of
-// the block (i >= nc contributes nothing).
+// Divergence update of cell i from its flux sum, post-update guards and the
+// new record; adds the cell's N V, guard counts and status to the thread's.
 template <typename T, typename TA>
-__device__ inline void finish_cell(int64_t i, int b, int64_t nc, const T* ui, const double* acc, TA cdt,
-                                   const GeomView<T>& geo, T* __restrict__ Unew, int cAdmN, int cAdmF, int cCap,
-                                   int64_t blk, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
-                                   int32_t* __restrict__ part_status, int64_t n_blocks) {
-    __shared__ double ldsd[kBlock / 64];
-    __shared__ int64_t ldsi[kBlock / 64];
-    __shared__ int ldss[kBlock / 64];
-    int cGN = 0, cGF = 0, status = 0;
-    double nv = 0.0;
-    if (i < nc) {
-        const double vol = (double)geo.cell[i * kCellRec + 6];
-        const double coef = (double)cdt / vol;
-        double un[4];
+__device__ inline void update_cell(int64_t i, int b, int64_t nc, const T* ui, const double* acc, TA cdt,
+                                   const GeomView<T>& geo, T* __restrict__ Unew, double& nv, int& cGN, int& cGF,
+                                   int& status) {
+    const double vol = (double)geo.cell[i * kCellRec + 6];
+    const double coef = (double)cdt / vol;
+    double un[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) un[v] = (double)ui[v] - coef * acc[v];
-        update_guards<double>(un, cGN, cGF);
-        T o[4];
+    for (int v = 0; v < 4; ++v) un[v] = (double)ui[v] - coef * acc[v];
+    update_guards<double>(un, cGN, cGF);
+    T o[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            o[v] = (T)un[v];
-            if (!isfinite((double)o[v])) status = 1;
-        }
-        store4(Unew + urec(b, nc, i), o);
-        nv = (double)o[0] * vol;
+    for (int v = 0; v < 4; ++v) {
+        o[v] = (T)un[v];
+        if (!isfinite((double)o[v])) status = 1;
     }
-    const double snv = block_sum<double>(nv, ldsd);
-    const int64_t s0 = block_sum<int64_t>(cAdmN, ldsi);
-    const int64_t s1 = block_sum<int64_t>(cAdmF, ldsi);
-    const int64_t s2 = block_sum<int64_t>(cCap, ldsi);
-    const int64_t s3 = block_sum<int64_t>(cGN, ldsi);
-    const int64_t s4 = block_sum<int64_t>(cGF, ldsi);
-    const int st = block_or(status, ldss);
+    store4(Unew + urec(b, nc, i), o);
+    nv += (double)o[0] * vol;
+}
+
+// The block's partials (sum N V of this bin, counters, status), accumulated
+// across the subcycles of one call.  Called by every thread of the block.
+template <int NT = kBlock>
+__device__ inline void block_partials(double nv, int cAdmN, int cAdmF, int cCap, int cGN, int cGF, int status,
+                                      int64_t blk, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
+                                      int32_t* __restrict__ part_status, int64_t n_blocks) {
+    __shared__ double ldsd[NT / 64];
+    __shared__ int64_t ldsi[NT / 64];
+    __shared__ int ldss[NT / 64];
+    const double snv = block_sum<double, NT>(nv, ldsd);
+    const int64_t s0 = block_sum<int64_t, NT>(cAdmN, ldsi);
+    const int64_t s1 = block_sum<int64_t, NT>(cAdmF, ldsi);
+    const int64_t s2 = block_sum<int64_t, NT>(cCap, ldsi);
+    const int64_t s3 = block_sum<int64_t, NT>(cGN, ldsi);
+    const int64_t s4 = block_sum<int64_t, NT>(cGF, ldsi);
+    const int st = block_or<NT>(status, ldss);
     if (threadIdx.x == 0) {
         part_nv[blk] = snv;
         part_cnt[0 * n_blocks + blk] += s0;
@@ -370,6 +371,17 @@ __device__ inline void finish_cell(int64_t i, int b, int64_t nc, const T* ui, co
         part_cnt[4 * n_blocks + blk] += s4;
         part_status[blk] |= st;
     }
+}
+
+template <typename T, typename TA>
+__device__ inline void finish_cell(int64_t i, int b, int64_t nc, const T* ui, const double* acc, TA cdt,
+                                   const GeomView<T>& geo, T* __restrict__ Unew, int cAdmN, int cAdmF, int cCap,
+                                   int64_t blk, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
+                                   int32_t* __restrict__ part_status, int64_t n_blocks) {
+    int cGN = 0, cGF = 0, status = 0;
+    double nv = 0.0;
+    if (i < nc) update_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, nv, cGN, cGF, status);
+    block_partials(nv, cAdmN, cAdmF, cCap, cGN, cGF, status, blk, part_nv, part_cnt, part_status, n_blocks);
 }
 
 template <typename T, typename TA, int DEG>
@@ -422,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
 // ---------------------------------------------------------------------------
 
 template <typename T, typename TA, int DEG>
-__global__ __launch_bounds__(kBlock) void k_transport(const T* __restrict__ U, T* __restrict__ Unew, int64_t nc,
+__global__ __launch_bounds__(kTileThreads) void k_transport(const T* __restrict__ U, T* __restrict__ Unew, int64_t nc,
                                                       int nb, GeomView<T> geo, SellView sell, TileView tile,
                                                       int use_limiter, TA cdt, double* __restrict__ part_nv,
                                                       int64_t* __restrict__ part_cnt,
@@ -432,17 +444,17 @@ __global__ __launch_bounds__(kBlock) void k_transport(const T* __restrict__ U, T
     const int64_t blk = xcd_logical_block();
     const int b = (int)(blk % nb);
     const int64_t t = blk / nb;
-    const int64_t c0 = t * kBlock;
+    const int64_t c0 = t * kTileCells;
     const int64_t e0 = sell.ptr[t * kTileSlices];
     const int64_t sl_end = (t + 1) * kTileSlices < tile.n_slices ? (t + 1) * kTileSlices : tile.n_slices;
     const int64_t tile_sides = (int64_t)sell.ptr[sl_end] - e0;
     const int32_t hq0 = tile.halo_ptr[t], hq1 = tile.halo_ptr[t + 1];
     const int32_t hs0 = tile.hside_ptr[hq0];
-    const int64_t n_items = kBlock + (hq1 - hq0);
+    const int64_t n_items = kTileCells + (hq1 - hq0);
 
-    for (int64_t item = threadIdx.x; item < n_items; item += kBlock) {
-        const bool own = item < kBlock;
-        const int64_t c = own ? c0 + item : (int64_t)tile.halo_cell[hq0 + (item - kBlock)];
+    for (int64_t item = threadIdx.x; item < n_items; item += kTileThreads) {
+        const bool own = item < kTileCells;
+        const int64_t c = own ? c0 + item : (int64_t)tile.halo_cell[hq0 + (item - kTileCells)];
         if (c >= nc) continue;
         double uc[4], g[4][3];
         T rr[SlotCount<DEG>::kMax][3];
@@ -465,8 +477,8 @@ __global__ __launch_bounds__(kBlock) void k_transport(const T* __restrict__ U, T
         if (own) {
             export_face_states<T, DEG>(c, uc, g, rr, ok, geo, sell, lds, e0);
         } else {
-            const int32_t sp = tile.hside_ptr[hq0 + (item - kBlock)];
-            const int32_t n_sides = tile.hside_ptr[hq0 + (item - kBlock) + 1] - sp;
+            const int32_t sp = tile.hside_ptr[hq0 + (item - kTileCells)];
+            const int32_t n_sides = tile.hside_ptr[hq0 + (item - kTileCells) + 1] - sp;
             for (int32_t q = 0; q < n_sides; ++q) {
                 const int64_t e = tile.hside_entry[sp + q];
                 T st[4];
@@ -477,13 +489,14 @@ __global__ __launch_bounds__(kBlock) void k_transport(const T* __restrict__ U, T
     }
     __syncthreads();
 
+    int cAdmN = 0, cAdmF = 0, cCap = 0, cGN = 0, cGF = 0, status = 0;
+    double nv = 0.0;
+    const TileFaceStates<T> fsv{lds, e0, tile.lds_opp};
     const int64_t i = c0 + threadIdx.x;
-    int cAdmN = 0, cAdmF = 0, cCap = 0;
-    T ui[4] = {0, 0, 0, 0};
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < nc) {
+        T ui[4];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
         load4(U + urec(b, nc, i), ui);
-        const TileFaceStates<T> fsv{lds, e0, tile.lds_opp};
         if constexpr (DEG > 0) {
             CellFaces<T, DEG> cf;
             load_cell_faces<T, DEG>(i, geo, sell, cf);
@@ -492,9 +505,12 @@ __global__ __launch_bounds__(kBlock) void k_transport(const T* __restrict__ U, T
         } else {
             cell_flux_sum_s<T, TA, DEG>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
         }
+        update_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, nv, cGN, cGF, status);
     }
-    finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt, part_status,
-                       n_blocks);
+    // Partials go to the slot of the tile's first 256-cell block, so that
+    // they are laid out as those of the split kernels.
+    block_partials<kTileThreads>(nv, cAdmN, cAdmF, cCap, cGN, cGF, status, (t * kTileBlocks) * nb + b, part_nv,
+                                 part_cnt, part_status, n_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -670,8 +686,8 @@ template <typename T>
 void launch_facestate(const T* U, T* FV, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
                       const SellView& sell, int use_limiter, hipStream_t s) {
 #define RT_CALL(D)                                                                                             \
-    hipLaunchKernelGGL((k_facestate<T, D>), dim3((unsigned)(D > 0 ? grid_for(nc, kBlock) : transport_blocks(nc, nb))), \
-                       dim3(kBlock), 0, s, U, FV, nc, nb, n_entries, geo, sell, use_limiter)
+    hipLaunchKernelGGL((k_facestate<T, D>), dim3((unsigned)transport_blocks(nc, nb)), dim3(kBlock), 0, s, U, FV,    \
+                       nc, nb, n_entries, geo, sell, use_limiter)
     RT_DEG_DISPATCH(sell.uniform_deg, RT_CALL)
 #undef RT_CALL
 }
@@ -698,11 +714,12 @@ template <typename T, int D>
 static void launch_transport_deg(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>& geo,
                                  const SellView& sell, const TileView& tile, size_t lds_bytes, int use_limiter,
                                  double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
-    const int64_t nblk = transport_blocks(nc, nb);
+    const int64_t nblk = transport_blocks(nc, nb);              // partial slots (256-cell blocks)
+    const int64_t ntile_blk = (int64_t)grid_for(nc, kTileCells) * nb;
     if (lds_bytes > 65536)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport<T, T, D>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    hipLaunchKernelGGL((k_transport<T, T, D>), dim3((unsigned)nblk), dim3(kBlock), lds_bytes, s, U, Unew, nc, nb,
+    hipLaunchKernelGGL((k_transport<T, T, D>), dim3((unsigned)ntile_blk), dim3(kTileThreads), lds_bytes, s, U, Unew, nc, nb,
                        geo, sell, tile, use_limiter, (T)cdt, part_nv, part_cnt, part_status, nblk);
 }
 

@@ -53,6 +53,8 @@ struct GlobalFaceStates {
     const int32_t* opp;
     __device__ const T* own(int64_t e) const { return FVb + e * 4; }
     __device__ const T* other(int64_t e) const { return FVb + (int64_t)opp[e] * 4; }
+    // with the entry's opposite entry already loaded
+    __device__ const T* other(int64_t e, int32_t eo) const { return FVb + (int64_t)eo * 4; }
 };
 template <typename T>
 struct TileFaceStates {
@@ -61,6 +63,7 @@ struct TileFaceStates {
     const int32_t* lds_opp;
     __device__ const T* own(int64_t e) const { return lds + (e - e0) * 4; }
     __device__ const T* other(int64_t e) const { return lds + (int64_t)lds_opp[e] * 4; }
+    __device__ const T* other(int64_t e, int32_t) const { return lds + (int64_t)lds_opp[e] * 4; }
 };
 
 // The limited state of a cell at one of its faces, U_i + g . r_if, rounded
@@ -113,14 +116,17 @@ __device__ inline void load_cell_sides(int64_t i, const GeomView<T>& geo, const 
 #pragma unroll
     for (int k = 0; k < DEG; ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
-        cs.nbr[k] = sell.nbr[e];
-        cs.w[k][0] = geo.sv(kSW0, e); cs.w[k][1] = geo.sv(kSW1, e); cs.w[k][2] = geo.sv(kSW2, e);
-        cs.r[k][0] = geo.sv(kSR0, e); cs.r[k][1] = geo.sv(kSR1, e); cs.r[k][2] = geo.sv(kSR2, e);
+        cs.nbr[k] = sell.idx[e].x;
+        T g0[4], g1[4];
+        load4(geo.sg(0, e), g0);
+        load4(geo.sg(1, e), g1);
+        cs.w[k][0] = g0[0]; cs.w[k][1] = g0[1]; cs.w[k][2] = g0[2];
+        cs.r[k][0] = g0[3]; cs.r[k][1] = g1[0]; cs.r[k][2] = g1[1];
     }
 }
 template <typename T, int DEG>
 struct CellFaces {
-    int32_t nbr[DEG];
+    int32_t nbr[DEG], opp[DEG];
     bool isL[DEG];
     T A[DEG], n[DEG][3], vL[DEG], vR[DEG];
 };
@@ -130,11 +136,15 @@ __device__ inline void load_cell_faces(int64_t i, const GeomView<T>& geo, const 
 #pragma unroll
     for (int k = 0; k < DEG; ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
-        cf.nbr[k] = sell.nbr[e];
-        cf.isL[k] = sell.fsf[e] >= 0;
-        cf.A[k] = geo.sv(kSA, e);
-        cf.n[k][0] = geo.sv(kSN0, e); cf.n[k][1] = geo.sv(kSN1, e); cf.n[k][2] = geo.sv(kSN2, e);
-        cf.vL[k] = geo.sv(kSVL, e); cf.vR[k] = geo.sv(kSVR, e);
+        const int4 id = sell.idx[e];
+        cf.nbr[k] = id.x;
+        cf.isL[k] = id.y >= 0;
+        cf.opp[k] = id.z;
+        T g1[4], g2[4];
+        load4(geo.sg(1, e), g1);
+        load4(geo.sg(2, e), g2);
+        cf.A[k] = g1[2]; cf.vL[k] = g1[3];
+        cf.n[k][0] = g2[0]; cf.n[k][1] = g2[1]; cf.n[k][2] = g2[2]; cf.vR[k] = g2[3];
     }
 }
 
@@ -210,7 +220,7 @@ __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __
         const TA A = (TA)cf.A[k];
         T so[4], sn[4];
         load4(fsv.own(e), so);
-        load4(fsv.other(e), sn);
+        load4(fsv.other(e, cf.opp[k]), sn);
         const TA Nj = (TA)U[urec(b, nc, j)];
         TA sL[4], sR[4];
 #pragma unroll

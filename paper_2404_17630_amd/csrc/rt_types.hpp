@@ -32,12 +32,15 @@ __host__ __device__ inline int64_t urec(int b, int64_t nc, int64_t i) { return (
 //   cell [nc][kCellRec]: inverse geometry matrix xx, yy, zz, xy, xz, yz; V; vcap
 constexpr int kFaceRec = 12;
 constexpr int kCellRec = 8;
-// Per face side (sliced-ELL entry e), structure of arrays side[c * ne + e]:
-//   w = A d / |d|^2 with d = s_j - s_i (least-squares weight vector),
-//   r = r_if (offset from the cell's centre to the face centre),
-//   A, n (L -> R), vcap_L, vcap_R of the face;
-// zeros for padding entries.  One coalesced load per component and slot.
-enum SideComp { kSW0 = 0, kSW1, kSW2, kSR0, kSR1, kSR2, kSA, kSN0, kSN1, kSN2, kSVL, kSVR, kSideComps };
+// Per face side (sliced-ELL entry e), three groups of four values, each
+// group a structure of arrays of 4-value records side[g][e][4]:
+//   g = 0: w_x, w_y, w_z, r_x      w = A d / |d|^2 with d = s_j - s_i
+//   g = 1: r_y, r_z, A, vcap_L     r = r_if, offset from the cell centre
+//   g = 2: n_x, n_y, n_z, vcap_R   n from L to R, vcap = V / n_faces
+// zeros for padding entries.  A wavefront reads a group of a slot as one
+// contiguous run of 16-byte (FP32) or 32-byte (FP64) records.
+enum SideComp { kSW0 = 0, kSW1, kSW2, kSR0, kSR1, kSR2, kSA, kSVL, kSN0, kSN1, kSN2, kSVR, kSideComps };
+constexpr int kSideGroups = 3;
 template <typename T>
 struct GeomView {
     const T* face;
@@ -45,7 +48,10 @@ struct GeomView {
     const T* side;
     int64_t nf;
     int64_t ne;
-    __device__ T sv(int c, int64_t e) const { return side[(int64_t)c * ne + e]; }
+    // component c (SideComp) of entry e
+    __device__ T sv(int c, int64_t e) const { return side[((int64_t)(c >> 2) * ne + e) * 4 + (c & 3)]; }
+    // group g of entry e (four values)
+    __device__ const T* sg(int g, int64_t e) const { return side + ((int64_t)g * ne + e) * 4; }
 };
 
 // Face sides of each cell in sliced-ELL order: slice s (cells 64s..64s+63)
@@ -59,12 +65,13 @@ struct SellView {
     const int32_t* opp;
     const int32_t* ptr;
     const int32_t* deg;
+    const int4* idx;       // (nbr, fsf, opp, 0) of each entry, one 16-byte load
     int32_t uniform_deg;   // slots of every slice when all are equal and specialised (6, 14), else 0
 };
 
-// Tiles of the fused transport kernel: tile t is cells [256 t, 256 t + 256)
-// (four slices, so its face sides are the contiguous entries
-// ptr[4t] .. ptr[4t+4]).  Face states live in LDS: first the tile's own
+// Tiles of the fused transport kernel: tile t is cells [T t, T t + T) with
+// T = kTileCells (whole slices, so its face sides are the contiguous entries
+// ptr[t T/64] .. ptr[(t+1) T/64]).  Face states live in LDS: first the tile's own
 // sides at (entry - ptr[4t]), then the halo sides: the sides of cells
 // outside the tile that face a tile cell, grouped by halo cell.
 //   lds_opp[e]     LDS slot of the state on the other side of entry e
@@ -74,7 +81,10 @@ struct SellView {
 //                  slot of halo side s of tile t is
 //                  (tile sides) + s - hside_ptr[halo_ptr[t]]
 //   hside_entry[s] sliced-ELL entry of the halo side
-constexpr int kTileSlices = kBlock / kSlice;
+constexpr int kTileCells = 256;                 // cells per tile (RT_TILE_CELLS)
+constexpr int kTileThreads = 256;               // threads per tile workgroup: one per tile cell
+constexpr int kTileSlices = kTileCells / kSlice;
+constexpr int kTileBlocks = kTileCells / kBlock;  // 256-cell blocks per tile (partials layout)
 struct TileView {
     const int32_t* lds_opp;
     const int32_t* halo_ptr;

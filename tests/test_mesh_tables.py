@@ -7,7 +7,8 @@ import pytest
 import rtgen
 from paper_2404_17630_amd import rt
 
-SLICE, TILE = 64, 256
+SLICE, TILE = 64, rt.RT_TILE_CELLS
+TILE_SLICES = TILE // SLICE
 
 
 def meshes():
@@ -81,8 +82,8 @@ def test_tile_tables_route_every_opposite_state(mesh):
             cell_of_entry[e] = i
     for tt in range(ntiles):
         c0, c1 = tt * TILE, min(nc, tt * TILE + TILE)
-        e0 = sptr[tt * 4]
-        n_own = sptr[min(ns, tt * 4 + 4)] - e0
+        e0 = sptr[tt * TILE_SLICES]
+        n_own = sptr[min(ns, (tt + 1) * TILE_SLICES)] - e0
         q0, q1 = t["halo_ptr"][tt], t["halo_ptr"][tt + 1]
         hs0, hs1 = t["hside_ptr"][q0], t["hside_ptr"][q1]
         writes = np.zeros(n_own + (hs1 - hs0), int)
