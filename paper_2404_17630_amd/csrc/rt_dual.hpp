@@ -8,6 +8,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "rt_math.hpp"
+
 namespace rtk {
 
 template <int K>
@@ -90,21 +92,22 @@ template <int K> __device__ inline Dual<K> m_sqrt(const Dual<K>& a) {
     const double s = sqrt(a.v);
     return chain(a, s, 0.5 / s);
 }
-__device__ inline double m_exp(double x) { return exp(x); }
+// exp, log and powers of positive bases through rt_exp / rt_log.
+__device__ inline double m_exp(double x) { return rt_exp(x); }
 template <int K> __device__ inline Dual<K> m_exp(const Dual<K>& a) {
-    const double e = exp(a.v);
+    const double e = rt_exp(a.v);
     return chain(a, e, e);
 }
-__device__ inline double m_pow(double x, double p) { return pow(x, p); }
+__device__ inline double m_pow(double x, double p) { return rt_exp(p * rt_log(x)); }
 template <int K> __device__ inline Dual<K> m_pow(const Dual<K>& a, double p) {
-    const double r = pow(a.v, p);
-    return chain(a, r, p * pow(a.v, p - 1.0));
+    const double r = rt_exp(p * rt_log(a.v));
+    return chain(a, r, p * r / a.v);
 }
-__device__ inline double m_log(double x) { return log(x); }
-template <int K> __device__ inline Dual<K> m_log(const Dual<K>& a) { return chain(a, log(a.v), 1.0 / a.v); }
-__device__ inline double m_log10(double x) { return log10(x); }
+__device__ inline double m_log(double x) { return rt_log(x); }
+template <int K> __device__ inline Dual<K> m_log(const Dual<K>& a) { return chain(a, rt_log(a.v), 1.0 / a.v); }
+__device__ inline double m_log10(double x) { return 0.43429448190325182765 * rt_log(x); }
 template <int K> __device__ inline Dual<K> m_log10(const Dual<K>& a) {
-    return chain(a, log10(a.v), 0.43429448190325182765 / a.v);
+    return chain(a, 0.43429448190325182765 * rt_log(a.v), 0.43429448190325182765 / a.v);
 }
 template <typename R> __device__ inline R m_abs(const R& a) { return val(a) < 0 ? -a : a; }
 template <typename R> __device__ inline R m_max(const R& a, const R& b) { return val(a) >= val(b) ? a : b; }
