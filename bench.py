@@ -65,6 +65,17 @@ def algorithmic_bytes(kernel: str, nc: int, nb: int, nf: int, n_sides: int, n_sr
     return 0.0
 
 
+def subcycle_bytes_per_cell(nb: int, p: int, g: int) -> dict:
+    """Whole-subcycle HBM bytes per cell on a six-face mesh, two accountings.
+    Two-pass: the gradient pass stores 3 gradient rows per field (and the
+    flux pass reads them), so fields move 36 nb p bytes; the geometry (cell:
+    M^-1, V, s = 10 values; per face side 8 index bytes; per face A, n, x_f
+    = 7 values read by each side) is read twice; the chemistry moves 13 FP64
+    values.  Compulsory: fields read and written once, geometry once."""
+    geo = 52 * g + 48
+    return {"two_pass": 36 * nb * p + 2 * geo + 104, "compulsory": 8 * nb * p + geo + 104}
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     for f in sorted((ROOT / "paper_2404_17630_amd" / "csrc").glob("*")):
@@ -203,6 +214,10 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic},
         "kernels_mixed": kt_mixed,
+        "subcycle_effective": {
+            name: {"bytes_per_cell": b, "GB/s": b * nc / (t_mixed / args.steps) / 1e9,
+                   "frac": b * nc / (t_mixed / args.steps) / 1e9 / HBM_PEAK_GBS}
+            for name, b in subcycle_bytes_per_cell(nb, 4, 4).items()},
         "chem_attempts_per_cell_subcycle": diag["substeps"] / (nc * args.steps),
     }
 
@@ -280,6 +295,10 @@ def main() -> int:
             "T_rel_max": float((np.abs(fields_mixed["T"] - f64["T"]) / f64["T"]).max()),
         }
         out["kernels_fp64"] = kernel_table(prof64, 8, 8)
+        out["fp64_subcycle_effective"] = {
+            name: {"bytes_per_cell": b, "GB/s": b * nc / (t64 / args.steps) / 1e9,
+                   "frac": b * nc / (t64 / args.steps) / 1e9 / HBM_PEAK_GBS}
+            for name, b in subcycle_bytes_per_cell(nb, 8, 8).items()}
         out["fp64_transport"] = "fused" if st64_fused else "split"
         del fields_mixed, f64
         mesh.close()
