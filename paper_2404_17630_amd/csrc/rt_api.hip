@@ -640,7 +640,8 @@ int rt_state::alloc_buffers() {
     n_cblk = chem_blocks(nc);
     if ((rc = part_nv.alloc(n_fblk * 8)) || (rc = part_cnt.alloc(5 * n_fblk * 8)) ||
         (rc = part_fst.alloc(n_fblk * 4)) || (rc = chem_sum.alloc(n_cblk * 8)) || (rc = chem_max.alloc(n_cblk * 8)) ||
-        (rc = chem_st.alloc(n_cblk * 4)) || (rc = d_diag.alloc(sizeof(DiagDev))))
+        (rc = chem_st.alloc(n_cblk * 4)) || (rc = d_diag.alloc(sizeof(DiagDev))) ||
+        (rc = d_red.alloc(kReduceBlocks * sizeof(DiagDev))))
         return rc;
     RT_HIP(hipHostMalloc((void**)&h_diag, sizeof(DiagDev), hipHostMallocDefault));
     return RT_OK;
@@ -1056,7 +1057,8 @@ void rt_reset_partials(rt_state* s, hipStream_t st) {
 int rt_read_status(rt_state* s, hipStream_t st, int* status) {
     launch_reduce((const double*)s->part_nv.ptr, (const int64_t*)s->part_cnt.ptr, (const int32_t*)s->part_fst.ptr,
                   s->n_fblk, s->nb, (const int64_t*)s->chem_sum.ptr, (const int64_t*)s->chem_max.ptr,
-                  (const int32_t*)s->chem_st.ptr, s->n_cblk, (const double*)s->d_nv_scale.ptr, (DiagDev*)s->d_diag.ptr,
+                  (const int32_t*)s->chem_st.ptr, s->n_cblk, (const double*)s->d_nv_scale.ptr, (DiagDev*)s->d_red.ptr,
+                  (DiagDev*)s->d_diag.ptr,
                   st);
     RT_HIP(hipGetLastError());
     RT_HIP(hipMemcpyAsync(s->h_diag, s->d_diag.ptr, sizeof(DiagDev), hipMemcpyDeviceToHost, st));
@@ -1090,7 +1092,8 @@ extern "C" int rt_subcycle(rt_state* s, int n, double dt, void* hip_stream) {
     s->prof_begin(RT_KERNEL_REDUCE, st);
     launch_reduce((const double*)s->part_nv.ptr, (const int64_t*)s->part_cnt.ptr, (const int32_t*)s->part_fst.ptr,
                   s->n_fblk, s->nb, (const int64_t*)s->chem_sum.ptr, (const int64_t*)s->chem_max.ptr,
-                  (const int32_t*)s->chem_st.ptr, s->n_cblk, (const double*)s->d_nv_scale.ptr, (DiagDev*)s->d_diag.ptr,
+                  (const int32_t*)s->chem_st.ptr, s->n_cblk, (const double*)s->d_nv_scale.ptr, (DiagDev*)s->d_red.ptr,
+                  (DiagDev*)s->d_diag.ptr,
                   st);
     s->prof_end(st);
     RT_HIP(hipGetLastError());

@@ -51,30 +51,35 @@ struct Rates {
     R cr_HII, cr_HeII, cr_HeIII, cd_HeII, ce_HI, ce_HeII, cff;
 };
 
-// x^p from ln x.
+// Every fit below is a product of powers and exponentials, so it is
+// evaluated as one exponential of the summed exponent: x^p y^q e^z =
+// exp(p ln x + q ln y + z).  A fit then costs one exp, plus one exp and one
+// log for its (1 + (lambda/l0)^b)^-c factor.
 template <typename R>
-__device__ inline R pow_ln(const R& lnx, double p) {
-    return m_exp(p * lnx);
+__device__ inline R log1p_pow(const R& ln_lam, double ln_l0, double b) {   // ln(1 + (lambda/l0)^b)
+    return m_log(1.0 + m_exp(b * (ln_lam - ln_l0)));
 }
 
 // Case-B hydrogenic recombination of Hui & Gnedin in terms of
-// lambda = 2 T_ion / T (ln lambda given).
+// lambda = 2 T_ion / T (ln lambda given):
+// 2.753e-14 lambda^1.5 / (1 + (lambda/2.740)^0.407)^2.242.
 template <typename R>
 __device__ inline R hg_rec_caseB(const R& ln_lam) {
-    return 2.753e-14 * pow_ln(ln_lam, 1.5) / m_pow(1.0 + pow_ln(ln_lam - 1.007957920399979 /* ln 2.740 */, 0.407), 2.242);
+    return 2.753e-14 * m_exp(1.5 * ln_lam - 2.242 * log1p_pow(ln_lam, 1.007957920399979 /* ln 2.740 */, 0.407));
 }
-// Matching case-B recombination cooling coefficient (erg cm^3/s).
+// Matching case-B recombination cooling coefficient (erg cm^3/s):
+// 3.435e-30 T lambda^1.970 / (1 + (lambda/2.250)^0.376)^3.720.
 template <typename R>
 __device__ inline R hg_rec_cool_caseB(const R& T, const R& ln_lam) {
-    return 3.435e-30 * T * pow_ln(ln_lam, 1.970) /
-           m_pow(1.0 + pow_ln(ln_lam - 0.8109302162163288 /* ln 2.250 */, 0.376), 3.720);
+    return 3.435e-30 * T *
+           m_exp(1.970 * ln_lam - 3.720 * log1p_pow(ln_lam, 0.8109302162163288 /* ln 2.250 */, 0.376));
 }
 // Hui & Gnedin collisional ionisation, A T^-3/2 e^(-lambda/2) lambda^-a /
 // (1 + (lambda/l0)^b)^c.
 template <typename R>
-__device__ inline R hg_col(double A, const R& t32, const R& lam, const R& ln_lam, double a, double ln_l0, double b,
+__device__ inline R hg_col(double A, const R& lnT, const R& lam, const R& ln_lam, double a, double ln_l0, double b,
                            double c) {
-    return A * t32 * m_exp(-0.5 * lam) * pow_ln(ln_lam, -a) / m_pow(1.0 + pow_ln(ln_lam - ln_l0, b), c);
+    return A * m_exp(-1.5 * lnT - 0.5 * lam - a * ln_lam - c * log1p_pow(ln_lam, ln_l0, b));
 }
 
 template <typename R>
@@ -95,25 +100,26 @@ __device__ inline Rates<R> network_rates(const ChemParams& P, R T) {
     const R ln_lH = 12.662275226919286 /* ln(2 T_HI) */ - lnT;
     const R ln_lHe1 = 13.254566388120152 /* ln(2 T_HeI) */ - lnT;
     const R ln_lHe2 = 14.049024154019651 /* ln(2 T_HeII) */ - lnT;
-    const R t32 = pow_ln(lnT, -1.5);
     const R sqT = m_sqrt(T);
-    // Cen (1992) dielectronic recombination shape T^-3/2 e^(-470000/T) (1 + 0.3 e^(-94000/T))
-    const R diel = t32 * m_exp(-470000.0 * iT) * (1.0 + 0.3 * m_exp(-94000.0 * iT));
-    const R rHe1 = 1.26e-14 * pow_ln(ln_lHe1, 0.75);
+    // Cen (1992) dielectronic recombination shape T^-3/2 e^(-470000/T) (1 + 0.3 e^(-94000/T)),
+    // with e^(-470000/T) = (e^(-94000/T))^5
+    const R e94 = m_exp(-94000.0 * iT);
+    const R e94_2 = e94 * e94;
+    const R diel = (iT / sqT) * (e94_2 * e94_2 * e94) * (1.0 + 0.3 * e94);
+    const R rHe1 = 1.26e-14 * m_exp(0.75 * ln_lHe1);
     r.rec_HII = hg_rec_caseB(ln_lH);
     r.rec_HeII = rHe1 + 1.9e-3 * diel;
     r.rec_HeIII = 2.0 * hg_rec_caseB(ln_lHe2);
-    r.col_HI = hg_col(21.11, t32, lH, ln_lH, 1.089, -1.0384583658483626 /* ln 0.354 */, 0.874, 1.101);
-    r.col_HeI = hg_col(32.38, t32, lHe1, ln_lHe1, 1.146, -0.8770700187208739 /* ln 0.416 */, 0.987, 1.056);
-    r.col_HeII = hg_col(19.95, t32, lHe2, ln_lHe2, 1.089, -0.5923972774598022 /* ln 0.553 */, 0.735, 1.275);
-    const R sq = 1.0 + 0.0031622776601683794 * sqT;   // 1 + (T / 1e5)^1/2
-    const R isq = 1.0 / sq;
+    r.col_HI = hg_col(21.11, lnT, lH, ln_lH, 1.089, -1.0384583658483626 /* ln 0.354 */, 0.874, 1.101);
+    r.col_HeI = hg_col(32.38, lnT, lHe1, ln_lHe1, 1.146, -0.8770700187208739 /* ln 0.416 */, 0.987, 1.056);
+    r.col_HeII = hg_col(19.95, lnT, lHe2, ln_lHe2, 1.089, -0.5923972774598022 /* ln 0.553 */, 0.735, 1.275);
+    const R isq = 1.0 / (1.0 + 0.0031622776601683794 * sqT);   // 1 / (1 + (T / 1e5)^1/2)
     r.cr_HII = hg_rec_cool_caseB(T, ln_lH);
     r.cr_HeII = kBoltz * T * rHe1;
     r.cr_HeIII = 8.0 * hg_rec_cool_caseB(T, ln_lHe2);
     r.cd_HeII = 1.24e-13 * diel;
     r.ce_HI = 7.5e-19 * m_exp(-118348.0 * iT) * isq;
-    r.ce_HeII = 5.54e-17 * pow_ln(lnT, -0.397) * m_exp(-473638.0 * iT) * isq;
+    r.ce_HeII = 5.54e-17 * m_exp(-0.397 * lnT - 473638.0 * iT) * isq;
     const R lg = 0.43429448190325182765 * lnT - 5.5;    // log10 T - 5.5
     r.cff = 1.42e-27 * (1.1 + 0.34 * m_exp(-lg * lg * (1.0 / 3.0))) * sqT;
     return r;
@@ -233,7 +239,9 @@ __device__ inline int chem_attempt(const ChemParams& P, double Dt, const R& nH, 
         fden = s.u;
     }
     const int ns = hhe ? 5 : 2;
-    for (int q = 0; q < ns; ++q) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        if (q >= ns) break;
         const R num = m_abs(xn[q] - x[q]);
         const R den = m_max(x[q], R(P.xfloor));
         if (val(num) * val(fden) > val(fnum) * val(den)) { fnum = num; fden = den; }
@@ -251,6 +259,7 @@ __device__ inline int chem_attempt(const ChemParams& P, double Dt, const R& nH, 
         s.Fh[b][1] = s.Fh[b][1] * ifac[b];
         s.Fh[b][2] = s.Fh[b][2] * ifac[b];
     }
+#pragma unroll
     for (int q = 0; q < 5; ++q) x[q] = xn[q];
     s.u = un;
     if (last) return 1;

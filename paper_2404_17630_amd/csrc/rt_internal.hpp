@@ -94,6 +94,7 @@ struct rt_state {
     // Per-block partials and the diagnostics record.
     int64_t n_fblk = 0, n_cblk = 0;
     DevMem part_nv, part_cnt, part_fst, chem_sum, chem_max, chem_st, d_diag;
+    DevMem d_red;                // first-stage records of the reduction [kReduceBlocks]
     rtk::DiagDev* h_diag = nullptr;
     rt_diag diag{};
 

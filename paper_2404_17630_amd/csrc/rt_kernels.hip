@@ -141,20 +141,36 @@ __global__ void k_sources(T* __restrict__ U, int64_t nc, int nb, int32_t n_cells
 // bit for bit as a one-cell-per-lane launch.
 // ---------------------------------------------------------------------------
 
+// Inputs of one cell, as stored.
 template <int NB, typename T>
-__device__ inline void chem_load(const T* __restrict__ U, const double* __restrict__ X, const double* __restrict__ Ue,
-                                 int64_t nc, int64_t i, const double* __restrict__ scale, ChemState<NB, double>& s) {
+struct ChemInput {
+    T U[NB][4];
+    double x[5], u, nh;
+};
+
+template <int NB, typename T>
+__device__ inline void chem_fetch(const T* __restrict__ U, const double* __restrict__ X, const double* __restrict__ Ue,
+                                  const double* __restrict__ nH, int64_t nc, int64_t i, ChemInput<NB, T>& in) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) load4(U + urec(b, nc, i), in.U[b]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) in.x[q] = X[(int64_t)q * nc + i];
+    in.u = Ue[i];
+    in.nh = nH[i];
+}
+
+template <int NB, typename T>
+__device__ inline void chem_unpack(const ChemInput<NB, T>& in, const double* __restrict__ scale,
+                                   ChemState<NB, double>& s) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        T r[4];
-        load4(U + urec(b, nc, i), r);
-        s.N[b] = (double)r[0] * scale[b];
+        s.N[b] = (double)in.U[b][0] * scale[b];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) s.Fh[b][k] = (double)r[1 + k] * scale[b];
+        for (int k = 0; k < 3; ++k) s.Fh[b][k] = (double)in.U[b][1 + k] * scale[b];
     }
 #pragma unroll
-    for (int q = 0; q < 5; ++q) s.x[q] = X[(int64_t)q * nc + i];
-    s.u = Ue[i];
+    for (int q = 0; q < 5; ++q) s.x[q] = in.x[q];
+    s.u = in.u;
 }
 
 template <int NB, typename T>
@@ -174,14 +190,21 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
     __syncthreads();
     int64_t sum_att = 0, max_att = 0;
     int status = 0;
+    // The lane's current cell i and the next one it will take, whose inputs
+    // are fetched while i is integrated.
     int64_t i = c0 + threadIdx.x;
     bool active = i < c1;
     ChemState<NB, double> s;
+    ChemInput<NB, T> pf;
     double nh = 0.0;
+    int64_t inext = c1;
     if (active) {
-        chem_load<NB, T>(U, X, Ue, nc, i, scale, s);
-        nh = nH[i];
+        chem_fetch<NB, T>(U, X, Ue, nH, nc, i, pf);
+        chem_unpack<NB, T>(pf, scale, s);
+        nh = pf.nh;
         chem_begin<NB, double>(dt, s);
+        inext = c0 + atomicAdd(&next, 1);
+        if (inext < c1) chem_fetch<NB, T>(U, X, Ue, nH, nc, inext, pf);
     }
     while (active) {
         const int r = chem_attempt<NB, double>(P, dt, nh, s);
@@ -202,12 +225,14 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
             Ue[i] = s.u;
             if (!isfinite(s.u)) status |= 1;
         }
-        i = c0 + atomicAdd(&next, 1);
+        i = inext;
         active = i < c1;
         if (active) {
-            chem_load<NB, T>(U, X, Ue, nc, i, scale, s);
-            nh = nH[i];
+            chem_unpack<NB, T>(pf, scale, s);
+            nh = pf.nh;
             chem_begin<NB, double>(dt, s);
+            inext = c0 + atomicAdd(&next, 1);
+            if (inext < c1) chem_fetch<NB, T>(U, X, Ue, nH, nc, inext, pf);
         }
     }
     const int64_t sm = block_sum<int64_t>(sum_att, lds64);
@@ -514,42 +539,81 @@ __global__ __launch_bounds__(kTileThreads) void k_transport(const T* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// k_reduce: one block folds the per-block partials in a fixed order into the
+// k_reduce: the per-block partials folded in a fixed order into the
 // diagnostics record (deterministic).
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_reduce(const double* __restrict__ part_nv, const int64_t* __restrict__ part_cnt,
-                                                   const int32_t* __restrict__ part_fstatus, int64_t n_fblocks, int nb,
-                                                   const int64_t* __restrict__ chem_sum, const int64_t* __restrict__ chem_max,
-                                                   const int32_t* __restrict__ chem_status, int64_t n_cblocks,
-                                                   const double* __restrict__ nv_scale /*[nb] scale*h^3*/,
-                                                   DiagDev* __restrict__ out) {
+// Two stages: kReduceBlocks workgroups fold fixed, contiguous ranges of the
+// partials into one record each, then one workgroup folds those records.
+// The partition and the order of every sum are fixed, so the diagnostics
+// are reproducible bit for bit.
+__global__ __launch_bounds__(kBlock) void k_reduce_part(const double* __restrict__ part_nv,
+                                                        const int64_t* __restrict__ part_cnt,
+                                                        const int32_t* __restrict__ part_fstatus, int64_t n_fblocks,
+                                                        int nb, const int64_t* __restrict__ chem_sum,
+                                                        const int64_t* __restrict__ chem_max,
+                                                        const int32_t* __restrict__ chem_status, int64_t n_cblocks,
+                                                        DiagDev* __restrict__ parts) {
     __shared__ double ldsd[kBlock / 64];
     __shared__ int64_t ldsi[kBlock / 64];
     __shared__ int ldss[kBlock / 64];
+    const int64_t g = blockIdx.x;
+    const int64_t rows = n_fblocks / nb;                  // 256-cell blocks
+    const int64_t rper = (rows + kReduceBlocks - 1) / kReduceBlocks;
+    const int64_t r0 = g * rper < rows ? g * rper : rows, r1 = r0 + rper < rows ? r0 + rper : rows;
+    const int64_t cper = (n_cblocks + kReduceBlocks - 1) / kReduceBlocks;
+    const int64_t q0 = g * cper < n_cblocks ? g * cper : n_cblocks;
+    const int64_t q1 = q0 + cper < n_cblocks ? q0 + cper : n_cblocks;
+    DiagDev& o = parts[g];
     for (int b = 0; b < nb; ++b) {
-        double s = 0.0;
-        for (int64_t k = threadIdx.x; k * nb + b < n_fblocks; k += kBlock) s += part_nv[k * nb + b];
-        s = block_sum<double>(s, ldsd);
-        if (threadIdx.x == 0) out->photon_sum[b] = s * nv_scale[b];
+        double sm = 0.0;
+        for (int64_t k = r0 + threadIdx.x; k < r1; k += kBlock) sm += part_nv[k * nb + b];
+        sm = block_sum<double>(sm, ldsd);
+        if (threadIdx.x == 0) o.photon_sum[b] = sm;
     }
     for (int c = 0; c < 5; ++c) {
-        int64_t s = 0;
-        for (int64_t k = threadIdx.x; k < n_fblocks; k += kBlock) s += part_cnt[c * n_fblocks + k];
-        s = block_sum<int64_t>(s, ldsi);
-        if (threadIdx.x == 0) out->counters[c] = s;
+        int64_t sm = 0;
+        for (int64_t k = r0 * nb + threadIdx.x; k < r1 * nb; k += kBlock) sm += part_cnt[c * n_fblocks + k];
+        sm = block_sum<int64_t>(sm, ldsi);
+        if (threadIdx.x == 0) o.counters[c] = sm;
     }
     int st = 0;
-    for (int64_t k = threadIdx.x; k < n_fblocks; k += kBlock) st |= part_fstatus[k];
-    for (int64_t k = threadIdx.x; k < n_cblocks; k += kBlock) st |= chem_status[k];
+    for (int64_t k = r0 * nb + threadIdx.x; k < r1 * nb; k += kBlock) st |= part_fstatus[k];
+    for (int64_t k = q0 + threadIdx.x; k < q1; k += kBlock) st |= chem_status[k];
     st = block_or(st, ldss);
     int64_t cs = 0, cm = 0;
-    for (int64_t k = threadIdx.x; k < n_cblocks; k += kBlock) {
+    for (int64_t k = q0 + threadIdx.x; k < q1; k += kBlock) {
         cs += chem_sum[k];
         cm = chem_max[k] > cm ? chem_max[k] : cm;
     }
     cs = block_sum<int64_t>(cs, ldsi);
     cm = block_max<int64_t>(cm, ldsi);
+    if (threadIdx.x == 0) {
+        o.status = st;
+        o.substeps = cs;
+        o.max_substeps = cm;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const DiagDev* __restrict__ parts, int nb,
+                                                   const double* __restrict__ nv_scale /*[nb] scale*h^3*/,
+                                                   DiagDev* __restrict__ out) {
+    __shared__ double ldsd[kBlock / 64];
+    __shared__ int64_t ldsi[kBlock / 64];
+    __shared__ int ldss[kBlock / 64];
+    const int k = threadIdx.x;
+    const bool in = k < kReduceBlocks;
+    for (int b = 0; b < nb; ++b) {
+        const double sm = block_sum<double>(in ? parts[k].photon_sum[b] : 0.0, ldsd);
+        if (threadIdx.x == 0) out->photon_sum[b] = sm * nv_scale[b];
+    }
+    for (int c = 0; c < 5; ++c) {
+        const int64_t sm = block_sum<int64_t>(in ? parts[k].counters[c] : 0, ldsi);
+        if (threadIdx.x == 0) out->counters[c] = sm;
+    }
+    const int st = block_or(in ? parts[k].status : 0, ldss);
+    const int64_t cs = block_sum<int64_t>(in ? parts[k].substeps : 0, ldsi);
+    const int64_t cm = block_max<int64_t>(in ? parts[k].max_substeps : 0, ldsi);
     if (threadIdx.x == 0) {
         out->status = st;
         out->substeps = cs;
@@ -736,9 +800,10 @@ void launch_transport(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>
 
 void launch_reduce(const double* part_nv, const int64_t* part_cnt, const int32_t* part_fstatus, int64_t n_fblocks,
                    int nb, const int64_t* chem_sum, const int64_t* chem_max, const int32_t* chem_status,
-                   int64_t n_cblocks, const double* nv_scale, DiagDev* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, part_nv, part_cnt, part_fstatus, n_fblocks, nb,
-                       chem_sum, chem_max, chem_status, n_cblocks, nv_scale, out);
+                   int64_t n_cblocks, const double* nv_scale, DiagDev* parts, DiagDev* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_part, dim3(kReduceBlocks), dim3(kBlock), 0, s, part_nv, part_cnt, part_fstatus,
+                       n_fblocks, nb, chem_sum, chem_max, chem_status, n_cblocks, parts);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, s, parts, nb, nv_scale, out);
 }
 
 int64_t cfl_partials(int64_t nc) {

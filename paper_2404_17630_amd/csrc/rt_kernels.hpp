@@ -18,6 +18,11 @@ struct DiagDev {
     int32_t pad_;
 };
 
+// Workgroups of the first stage of the diagnostics reduction (one DiagDev
+// record each; no more than the threads of one workgroup).
+constexpr int kReduceBlocks = 256;
+static_assert(kReduceBlocks <= kBlock, "the second stage folds one record per thread");
+
 void fill_words(void* p, int64_t n_words, uint32_t v, hipStream_t s);
 
 int chem_chunk(int64_t nc);
@@ -54,7 +59,7 @@ void launch_transport(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>
 
 void launch_reduce(const double* part_nv, const int64_t* part_cnt, const int32_t* part_fstatus, int64_t n_fblocks,
                    int nb, const int64_t* chem_sum, const int64_t* chem_max, const int32_t* chem_status,
-                   int64_t n_cblocks, const double* nv_scale, DiagDev* out, hipStream_t s);
+                   int64_t n_cblocks, const double* nv_scale, DiagDev* parts, DiagDev* out, hipStream_t s);
 
 void launch_min_cfl_length(const double* vphys, int64_t nc, double* part, hipStream_t s);
 

@@ -26,7 +26,11 @@ def test_fused_and_split_agree(precision):
     errs = field_errors(a, b, cfg["params"]["c_reduced"], cfg["mesh"]["face_cells"])
     worst = max(errs, key=errs.get)
     say("fused vs split", "fp64" if precision == rt.RT_FP64 else "mixed", worst, f"{errs[worst]:.3e}")
-    assert max(errs.values()) <= (1e-12 if precision == rt.RT_FP64 else 1e-5), errs
+    # Both paths run the same per-cell arithmetic in the same order (the
+    # fused kernel only keeps the face states in LDS), so they agree bit for
+    # bit after any number of subcycles.
+    for key in ("N", "F", "species", "T"):
+        assert np.array_equal(a[key], b[key]), (key, errs)
     ref = oracle.run(cfg)
     e_ref = field_errors(a, ref, cfg["params"]["c_reduced"], cfg["mesh"]["face_cells"])
     if precision == rt.RT_FP64:
