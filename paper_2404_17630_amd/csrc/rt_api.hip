@@ -627,7 +627,8 @@ size_t rt_state::tbytes() const { return precision == RT_MIXED ? 4 : 8; }
 // The face-state array of the split path, allocated on first use.
 int rt_state::ensure_face_states() {
     if (FV.ptr) return RT_OK;
-    return FV.alloc((size_t)nb * 4 * mesh->n_entries * tbytes());
+    // face states [nb][n_entries][4], then the cells' N [nb][nc]
+    return FV.alloc(((size_t)nb * 4 * mesh->n_entries + (size_t)nb * nc) * tbytes());
 }
 
 int rt_state::alloc_buffers() {
@@ -953,11 +954,12 @@ void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStr
 
 void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st) {
     s->prof_begin(RT_KERNEL_GRADIENT, st);
+    const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;   // the cells' N follow the face states
     if (s->precision == RT_MIXED)
-        launch_facestate<float>((const float*)U, (float*)FV, s->nc, s->nb, s->mesh->n_entries,
+        launch_facestate<float>((const float*)U, (float*)FV, (float*)FV + nfv, s->nc, s->nb, s->mesh->n_entries,
                                 geom_view<float>(s->mesh), rt_sell(s->mesh), s->params.use_limiter, st);
     else
-        launch_facestate<double>((const double*)U, (double*)FV, s->nc, s->nb, s->mesh->n_entries,
+        launch_facestate<double>((const double*)U, (double*)FV, (double*)FV + nfv, s->nc, s->nb, s->mesh->n_entries,
                                  geom_view<double>(s->mesh), rt_sell(s->mesh), s->params.use_limiter, st);
     s->prof_end(st);
 }
@@ -965,12 +967,15 @@ void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st) {
 void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st) {
     const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
     s->prof_begin(RT_KERNEL_FLUX, st);
+    const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;
     if (s->precision == RT_MIXED)
-        launch_flux<float>((const float*)U, (const float*)FV, (float*)Un, s->nc, s->nb, s->mesh->n_entries,
+        launch_flux<float>((const float*)U, (const float*)FV, (const float*)FV + nfv, (float*)Un, s->nc, s->nb,
+                           s->mesh->n_entries,
                            geom_view<float>(s->mesh), rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr,
                            (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
     else
-        launch_flux<double>((const double*)U, (const double*)FV, (double*)Un, s->nc, s->nb, s->mesh->n_entries,
+        launch_flux<double>((const double*)U, (const double*)FV, (const double*)FV + nfv, (double*)Un, s->nc,
+                            s->nb, s->mesh->n_entries,
                             geom_view<double>(s->mesh), rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr,
                             (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
     s->prof_end(st);

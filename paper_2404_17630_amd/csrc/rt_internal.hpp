@@ -75,8 +75,9 @@ struct rt_state {
     double dt_cfl = 0.0;
 
     // Fields: U[b][nc][4] = (N, Fh_x, Fh_y, Fh_z) / scale_b in the transport
-    // precision, double-buffered; face states FV[b][entry][4] (split path
-    // only, allocated on first use); chemistry FP64.
+    // precision, double-buffered; face states FV[b][entry][4] followed by a
+    // copy of the cells' N [b][nc] (split path only, allocated on first
+    // use); chemistry FP64.
     DevMem U[2];
     int cur = 0;
     DevMem FV;

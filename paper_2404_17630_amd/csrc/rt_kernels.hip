@@ -281,9 +281,9 @@ __device__ inline void export_face_states(int64_t i, const double* ui, const dou
 }
 
 template <typename T, int DEG>
-__global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T* __restrict__ FV, int64_t nc, int nb,
-                                                      int64_t n_entries, GeomView<T> geo, SellView sell,
-                                                      int use_limiter) {
+__global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T* __restrict__ FV, T* __restrict__ NC,
+                                                      int64_t nc, int nb, int64_t n_entries, GeomView<T> geo,
+                                                      SellView sell, int use_limiter) {
     const int64_t blk = xcd_logical_block();
     if constexpr (DEG > 0) {
         // One lane per (cell, bin) with the cell's side records in registers.
@@ -298,13 +298,14 @@ __global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T
         const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
         double ui[4], g[4][3];
         limited_gradient_c<T, DEG>(i, b, nc, U, cell, cs, use_limiter, ui, g);
+        NC[(int64_t)b * nc + i] = (T)ui[0];
         T* FVb = FV + (int64_t)b * n_entries * 4;
 #pragma unroll
         for (int k = 0; k < DEG; ++k) {
             if (cs.nbr[k] < 0) continue;
             T st[4];
             face_state<T>(ui, g, cs.r[k][0], cs.r[k][1], cs.r[k][2], st);
-            store4(FVb + (base + (int64_t)k * kSlice) * 4, st);
+            store4_stream(FVb + (base + (int64_t)k * kSlice) * 4, st);
         }
     } else {
         const int b = (int)(blk % nb);
@@ -314,6 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T
         T rr[SlotCount<DEG>::kMax][3];
         bool ok[SlotCount<DEG>::kMax];
         limited_gradient_s<T, DEG>(i, b, nc, U, geo, sell, use_limiter, ui, g, rr, ok);
+        NC[(int64_t)b * nc + i] = (T)ui[0];
         export_face_states<T, DEG>(i, ui, g, rr, ok, geo, sell, FV + (int64_t)b * n_entries * 4, 0);
     }
 }
@@ -410,7 +412,8 @@ __device__ inline void finish_cell(int64_t i, int b, int64_t nc, const T* ui, co
 }
 
 template <typename T, typename TA, int DEG>
-__global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ FV, T* __restrict__ Unew,
+__global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ FV,
+                                                 const T* __restrict__ NC, T* __restrict__ Unew,
                                                  int64_t nc, int nb, int64_t n_entries, GeomView<T> geo, SellView sell,
                                                  TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
                                                  int32_t* __restrict__ part_status, int64_t n_blocks) {
@@ -427,7 +430,7 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
             CellFaces<T, DEG> cf;
             load_cell_faces<T, DEG>(i, geo, sell, cf);
             load4(U + urec(b, nc, i), ui);
-            const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp};
+            const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp, NC + (int64_t)b * nc};
             cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, (int64_t)sell.ptr[i / kSlice] + (i % kSlice), cf, cdt,
                                         (TA)ui[0], acc, cAdmN, cAdmF, cCap);
         }
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         if (i < nc) {
             load4(U + urec(b, nc, i), ui);
-            const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp};
+            const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp, NC + (int64_t)b * nc};
             cell_flux_sum_s<T, TA, DEG>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
         }
         finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(kTileThreads) void k_transport(const T* __restrict_
 
     int cAdmN = 0, cAdmF = 0, cCap = 0, cGN = 0, cGF = 0, status = 0;
     double nv = 0.0;
-    const TileFaceStates<T> fsv{lds, e0, tile.lds_opp};
+    const TileFaceStates<T> fsv{lds, e0, tile.lds_opp, U + (int64_t)b * nc * 4};
     const int64_t i = c0 + threadIdx.x;
     if (i < nc) {
         T ui[4];
@@ -747,11 +750,11 @@ int64_t transport_blocks(int64_t nc, int nb) { return (int64_t)grid_for(nc, kBlo
     }
 
 template <typename T>
-void launch_facestate(const T* U, T* FV, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
+void launch_facestate(const T* U, T* FV, T* NC, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
                       const SellView& sell, int use_limiter, hipStream_t s) {
 #define RT_CALL(D)                                                                                             \
     hipLaunchKernelGGL((k_facestate<T, D>), dim3((unsigned)transport_blocks(nc, nb)), dim3(kBlock), 0, s, U, FV,    \
-                       nc, nb, n_entries, geo, sell, use_limiter)
+                       NC, nc, nb, n_entries, geo, sell, use_limiter)
     RT_DEG_DISPATCH(sell.uniform_deg, RT_CALL)
 #undef RT_CALL
 }
@@ -763,12 +766,13 @@ void launch_gradient(const double* U, double* G, int64_t nc, int nb, const GeomV
 }
 
 template <typename T>
-void launch_flux(const T* U, const T* FV, T* Unew, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
+void launch_flux(const T* U, const T* FV, const T* NC, T* Unew, int64_t nc, int nb, int64_t n_entries,
+                 const GeomView<T>& geo,
                  const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
                  hipStream_t s) {
     const int64_t nblk = transport_blocks(nc, nb);
 #define RT_CALL(D)                                                                                               \
-    hipLaunchKernelGGL((k_flux<T, T, D>), dim3((unsigned)nblk), dim3(kBlock), 0, s, U, FV, Unew, nc, nb, n_entries, \
+    hipLaunchKernelGGL((k_flux<T, T, D>), dim3((unsigned)nblk), dim3(kBlock), 0, s, U, FV, NC, Unew, nc, nb, n_entries, \
                        geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk)
     RT_DEG_DISPATCH(sell.uniform_deg, RT_CALL)
 #undef RT_CALL
@@ -834,9 +838,9 @@ void launch_set_fields(T* U, const double* X, double* Ue, int64_t nc, int nb, in
                                     int64_t, const double*, const double*, const double*, double, hipStream_t);    \
     template void launch_chem<T>(T*, double*, double*, const double*, int64_t, const ChemParams&, double,           \
                                  const double*, const double*, int64_t*, int64_t*, int32_t*, hipStream_t);          \
-    template void launch_facestate<T>(const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, int, \
+    template void launch_facestate<T>(const T*, T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, int, \
                                       hipStream_t);                                                                \
-    template void launch_flux<T>(const T*, const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, \
+    template void launch_flux<T>(const T*, const T*, const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, \
                                  double, double*, int64_t*, int32_t*, hipStream_t);                                 \
     template void launch_transport<T>(const T*, T*, int64_t, int, const GeomView<T>&, const SellView&,             \
                                       const TileView&, size_t, int, double, double*, int64_t*, int32_t*,           \

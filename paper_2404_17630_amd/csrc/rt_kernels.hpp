@@ -40,15 +40,19 @@ void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, cons
                  const double* scale, const double* inv_scale, int64_t* part_sum, int64_t* part_max,
                  int32_t* part_status, hipStream_t s);
 
+// FV[b][e][4]: face states; NC[b][nc]: a copy of each cell's N, which
+// launch_flux gathers for the outflow cap (4 bytes a cell instead of a
+// 16-byte field record).
 template <typename T>
-void launch_facestate(const T* U, T* FV, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
+void launch_facestate(const T* U, T* FV, T* NC, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
                       const SellView& sell, int use_limiter, hipStream_t s);
 
 void launch_gradient(const double* U, double* G, int64_t nc, int nb, const GeomView<double>& geo, const SellView& sell,
                      int use_limiter, hipStream_t s);
 
 template <typename T>
-void launch_flux(const T* U, const T* FV, T* Unew, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
+void launch_flux(const T* U, const T* FV, const T* NC, T* Unew, int64_t nc, int nb, int64_t n_entries,
+                 const GeomView<T>& geo,
                  const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
                  hipStream_t s);
 

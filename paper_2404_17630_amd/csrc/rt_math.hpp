@@ -1,6 +1,6 @@
 // FP64 exponential and logarithm for the chemistry's rate fits.
 //
-// The network coefficients take ~40 exponentials and logarithms per
+// The network coefficients take 27 exponentials and logarithms per
 // substep; the general library routines handle every special case of the
 // IEEE formats at several times the cost of the finite, positive arguments
 // that occur here.  These follow the classical reduction methods (Cody &

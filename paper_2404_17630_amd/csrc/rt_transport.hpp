@@ -28,6 +28,14 @@ __device__ inline void store4(double* __restrict__ p, const double* v) {
     *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
     *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
 }
+// Store that bypasses the caches' retention (a record no kernel reads again
+// soon enough to find it there); the FP64 form is a plain store.
+__device__ inline void store4_stream(float* __restrict__ p, const float* v) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f x = {v[0], v[1], v[2], v[3]};
+    __builtin_nontemporal_store(x, reinterpret_cast<v4f*>(p));
+}
+__device__ inline void store4_stream(double* __restrict__ p, const double* v) { store4(p, v); }
 
 // The face record: A, n, rL, rR, vcap_L, vcap_R.
 template <typename T>
@@ -47,23 +55,28 @@ __device__ inline FaceRec<T> load_face(const T* __restrict__ face, int64_t f) {
 // Where the limited face states of a cell's sides are read from: the
 // face-state array FV[b][e][4] of the split path, or the LDS tile of the
 // fused kernel.
+// Both also give a neighbour's cell value of N (for the outflow cap).
 template <typename T>
 struct GlobalFaceStates {
     const T* FVb;          // FV of bin b
     const int32_t* opp;
+    const T* Nb;           // N of every cell of bin b, copied by k_facestate (4 bytes a cell)
     __device__ const T* own(int64_t e) const { return FVb + e * 4; }
     __device__ const T* other(int64_t e) const { return FVb + (int64_t)opp[e] * 4; }
     // with the entry's opposite entry already loaded
     __device__ const T* other(int64_t e, int32_t eo) const { return FVb + (int64_t)eo * 4; }
+    __device__ T cellN(int32_t j) const { return Nb[j]; }
 };
 template <typename T>
 struct TileFaceStates {
     const T* lds;
     int64_t e0;            // first entry of the tile
     const int32_t* lds_opp;
+    const T* Ub;           // fields of bin b
     __device__ const T* own(int64_t e) const { return lds + (e - e0) * 4; }
     __device__ const T* other(int64_t e) const { return lds + (int64_t)lds_opp[e] * 4; }
     __device__ const T* other(int64_t e, int32_t) const { return lds + (int64_t)lds_opp[e] * 4; }
+    __device__ T cellN(int32_t j) const { return Ub[(int64_t)j * 4]; }
 };
 
 // The limited state of a cell at one of its faces, U_i + g . r_if, rounded
@@ -116,7 +129,7 @@ __device__ inline void load_cell_sides(int64_t i, const GeomView<T>& geo, const 
 #pragma unroll
     for (int k = 0; k < DEG; ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
-        cs.nbr[k] = sell.idx[e].x;
+        cs.nbr[k] = sell.nbr[e];
         T g0[4], g1[4];
         load4(geo.sg(0, e), g0);
         load4(geo.sg(1, e), g1);
@@ -221,7 +234,7 @@ __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __
         T so[4], sn[4];
         load4(fsv.own(e), so);
         load4(fsv.other(e, cf.opp[k]), sn);
-        const TA Nj = (TA)U[urec(b, nc, j)];
+        const TA Nj = (TA)fsv.cellN(j);
         TA sL[4], sR[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -341,7 +354,7 @@ __device__ inline void cell_flux_sum_s(int64_t i, int b, int64_t nc, const T* __
         T so[4], sn[4];
         load4(fsv.own(e), so);
         load4(fsv.other(e), sn);
-        const TA Nj = (TA)U[urec(b, nc, j)];
+        const TA Nj = (TA)fsv.cellN(j);
         TA sL[4], sR[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
