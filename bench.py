@@ -44,9 +44,10 @@ def algorithmic_bytes(kernel: str, nc: int, nb: int, nf: int, n_sides: int, n_sr
     p = bytes per transport value, g = bytes per geometry value; indices are
     4 bytes.  Face sides per cell: n_sides / nc."""
     if kernel == "k_facestate":
-        # fields (4) in, one 4-value face state per face side out;
-        # cell record (M^-1, V, V/n_f), face record (12 values), neighbour + face index
-        return nb * (4 * nc + 4 * n_sides) * p + nc * 8 * g + nf * 12 * g + n_sides * 8
+        # fields (4) in, one 4-value face state per face side out, the cell's
+        # N copied out; cell record (M^-1, V, V/n_f), face record (12 values),
+        # neighbour index
+        return nb * (5 * nc + 4 * n_sides) * p + nc * 8 * g + nf * 12 * g + n_sides * 4
     if kernel == "k_transport":
         # fused gradient + face states + fluxes: fields in and out; cell and
         # face records; neighbour, face and opposite-slot index per face side
@@ -54,9 +55,9 @@ def algorithmic_bytes(kernel: str, nc: int, nb: int, nf: int, n_sides: int, n_sr
         # the side count, are not counted)
         return nb * 8 * nc * p + nc * 8 * g + nf * 12 * g + n_sides * 12
     if kernel == "k_flux":
-        # fields in and out, face states of every face side in; cell volume,
-        # face record, neighbour + face + opposite-side index
-        return nb * (8 * nc + 4 * n_sides) * p + nc * g + nf * 12 * g + n_sides * 12
+        # fields in and out, the cells' N copy, face states of every face side
+        # in; cell volume, face record, neighbour + face + opposite-side index
+        return nb * (9 * nc + 4 * n_sides) * p + nc * g + nf * 12 * g + n_sides * 12
     if kernel == "k_chem":
         # fields of all bins in and out, 5 fractions and u in and out, n_H in
         return nc * (8 * nb * p + 2 * 5 * 8 + 2 * 8 + 8)

@@ -155,8 +155,8 @@ int rt_params_default(int32_t nb, rt_params* p);
  * matrices M_i = sum_j A_ij n_ji n_ji^T and their inverses (Sec. 2.3.2: the
  * matrix depends on geometry only and is reused between subcycles), the
  * per-cell face lists in face-index order (Sec. 4.1.4) and the CFL length
- * (3V/4pi)^(1/3) (eq. timestep).  Errors: RT_EINVAL, RT_EMESH, RT_EDEVICE,
- * RT_ENOMEM. */
+ * (3V/4pi)^(1/3) (eq. timestep).  Every cell must have between 4 and 4096
+ * faces.  Errors: RT_EINVAL, RT_EMESH, RT_EDEVICE, RT_ENOMEM. */
 int rt_mesh_create(int64_t n_cells, const double* volume, const double* centre,
                    int64_t n_faces, const int64_t* face_cells, const double* area,
                    const double* normal, const double* face_centre, const double box[3],

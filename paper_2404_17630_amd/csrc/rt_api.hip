@@ -324,8 +324,11 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
         ++deg[L];
         ++deg[R];
     }
-    for (int64_t i = 0; i < nc; ++i)
+    for (int64_t i = 0; i < nc; ++i) {
         if (deg[i] < 4) return rt_fail(RT_EMESH, "cell %lld has %d faces (< 4)", (long long)i, deg[i]);
+        if (deg[i] > kMaxCellFaces)
+            return rt_fail(RT_EMESH, "cell %lld has %d faces (> %d)", (long long)i, deg[i], kMaxCellFaces);
+    }
 
     rt_mesh* m = new (std::nothrow) rt_mesh();
     if (!m) return rt_fail(RT_ENOMEM, "mesh handle");

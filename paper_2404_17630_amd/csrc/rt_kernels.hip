@@ -375,28 +375,51 @@ __device__ inline void update_cell(int64_t i, int b, int64_t nc, const T* ui, co
 
 // The block's partials (sum N V of this bin, counters, status), accumulated
 // across the subcycles of one call.  Called by every thread of the block.
+// Each wave reduces N V and the three per-face counts (packed in 21-bit
+// fields of one 64-bit sum; a block's count stays below 2^21 for cells of
+// up to kMaxCellFaces faces) with shuffles, the 0/1 guard flags and status
+// with ballots; one barrier, then thread 0 adds the waves in order.
 template <int NT = kBlock>
 __device__ inline void block_partials(double nv, int cAdmN, int cAdmF, int cCap, int cGN, int cGF, int status,
                                       int64_t blk, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
                                       int32_t* __restrict__ part_status, int64_t n_blocks) {
+    static_assert((int64_t)NT * kMaxCellFaces < (1 << 21), "packed counters overflow");
     __shared__ double ldsd[NT / 64];
-    __shared__ int64_t ldsi[NT / 64];
-    __shared__ int ldss[NT / 64];
-    const double snv = block_sum<double, NT>(nv, ldsd);
-    const int64_t s0 = block_sum<int64_t, NT>(cAdmN, ldsi);
-    const int64_t s1 = block_sum<int64_t, NT>(cAdmF, ldsi);
-    const int64_t s2 = block_sum<int64_t, NT>(cCap, ldsi);
-    const int64_t s3 = block_sum<int64_t, NT>(cGN, ldsi);
-    const int64_t s4 = block_sum<int64_t, NT>(cGF, ldsi);
-    const int st = block_or<NT>(status, ldss);
+    __shared__ uint64_t ldsc[NT / 64];
+    __shared__ uint32_t ldsg[NT / 64][3];
+    const uint64_t packed = (uint64_t)cAdmN | ((uint64_t)cAdmF << 21) | ((uint64_t)cCap << 42);
+    const double snv = wave_sum(nv);
+    const uint64_t spk = wave_sum(packed);
+    const uint64_t bGN = __ballot(cGN != 0), bGF = __ballot(cGF != 0), bST = __ballot(status != 0);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        ldsd[w] = snv;
+        ldsc[w] = spk;
+        ldsg[w][0] = (uint32_t)__popcll(bGN);
+        ldsg[w][1] = (uint32_t)__popcll(bGF);
+        ldsg[w][2] = bST != 0 ? 1u : 0u;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        part_nv[blk] = snv;
-        part_cnt[0 * n_blocks + blk] += s0;
-        part_cnt[1 * n_blocks + blk] += s1;
-        part_cnt[2 * n_blocks + blk] += s2;
-        part_cnt[3 * n_blocks + blk] += s3;
-        part_cnt[4 * n_blocks + blk] += s4;
-        part_status[blk] |= st;
+        double sn = 0.0;
+        uint64_t sc = 0;
+        int64_t g0 = 0, g1 = 0;
+        uint32_t st = 0;
+        for (int k = 0; k < NT / 64; ++k) {
+            sn += ldsd[k];
+            sc += ldsc[k];
+            g0 += ldsg[k][0];
+            g1 += ldsg[k][1];
+            st |= ldsg[k][2];
+        }
+        constexpr uint64_t kField = (1ull << 21) - 1;
+        part_nv[blk] = sn;
+        part_cnt[0 * n_blocks + blk] += (int64_t)(sc & kField);
+        part_cnt[1 * n_blocks + blk] += (int64_t)((sc >> 21) & kField);
+        part_cnt[2 * n_blocks + blk] += (int64_t)((sc >> 42) & kField);
+        part_cnt[3 * n_blocks + blk] += g0;
+        part_cnt[4 * n_blocks + blk] += g1;
+        part_status[blk] |= (int32_t)st;
     }
 }
 

@@ -114,6 +114,12 @@ template <int DEG>
 struct SlotCount {
     static constexpr int kMax = DEG > 0 ? DEG : 1;
 };
+// Slots whose gathers are issued together: all of them up to 8, else half
+// (the records of 14 slots at once would cost too many registers).
+template <int DEG>
+struct SlotBatch {
+    static constexpr int kSize = DEG <= 8 ? DEG : (DEG + 1) / 2;
+};
 
 // Side records of one cell's DEG slots (DEG > 0), loaded once and reused
 // for every bin: the neighbours, the least-squares weights and face offsets
@@ -175,22 +181,34 @@ __device__ inline void limited_gradient_c(int64_t i, int b, int64_t nc, const T*
         bs[v][0] = bs[v][1] = bs[v][2] = 0.0;
         umax[v] = umin[v] = ui[v];
     }
+    // The neighbour records of a batch of slots are all requested before
+    // any is used, so the gathers overlap instead of each waiting for the
+    // previous one (a padding slot reads the cell's own record and is
+    // skipped below).
+    constexpr int P = SlotBatch<DEG>::kSize;
 #pragma unroll
-    for (int k = 0; k < DEG; ++k) {
-        const int32_t j = cs.nbr[k];
-        if (j < 0) continue;
-        const double w0 = (double)cs.w[k][0], w1 = (double)cs.w[k][1], w2 = (double)cs.w[k][2];
-        T uj[4];
-        load4(U + urec(b, nc, j), uj);
+    for (int k0 = 0; k0 < DEG; k0 += P) {
+        T uj[P][4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const double ujv = (double)uj[v];
-            const double dphi = ujv - ui[v];
-            bs[v][0] += w0 * dphi;
-            bs[v][1] += w1 * dphi;
-            bs[v][2] += w2 * dphi;
-            umax[v] = ujv > umax[v] ? ujv : umax[v];
-            umin[v] = ujv < umin[v] ? ujv : umin[v];
+        for (int q = 0; q < P; ++q) {
+            const int k = k0 + q;
+            if (k < DEG) load4(U + urec(b, nc, cs.nbr[k] >= 0 ? (int64_t)cs.nbr[k] : i), uj[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int k = k0 + q;
+            if (k >= DEG || cs.nbr[k] < 0) continue;
+            const double w0 = (double)cs.w[k][0], w1 = (double)cs.w[k][1], w2 = (double)cs.w[k][2];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double ujv = (double)uj[q][v];
+                const double dphi = ujv - ui[v];
+                bs[v][0] += w0 * dphi;
+                bs[v][1] += w1 * dphi;
+                bs[v][2] += w2 * dphi;
+                umax[v] = ujv > umax[v] ? ujv : umax[v];
+                umin[v] = ujv < umin[v] ? ujv : umin[v];
+            }
         }
     }
     const double mxx = cell[0], myy = cell[1], mzz = cell[2], mxy = cell[3], mxz = cell[4], myz = cell[5];
@@ -224,34 +242,51 @@ template <typename T, typename TA, int DEG, typename FS>
 __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __restrict__ U, const FS& fsv,
                                        int64_t base, const CellFaces<T, DEG>& cf, TA cdt, TA Ni, double* acc,
                                        int& cAdmN, int& cAdmF, int& cCap) {
+    // The two face states and the neighbour's N of a batch of slots are all
+    // requested before the first flux is computed, so the gathers overlap
+    // (a padding slot reads its own entry and the cell itself, and is
+    // skipped below).
+    constexpr int P = SlotBatch<DEG>::kSize;
 #pragma unroll
-    for (int k = 0; k < DEG; ++k) {
-        const int32_t j = cf.nbr[k];
-        if (j < 0) continue;
-        const int64_t e = base + (int64_t)k * kSlice;
-        const bool isL = cf.isL[k];
-        const TA A = (TA)cf.A[k];
-        T so[4], sn[4];
-        load4(fsv.own(e), so);
-        load4(fsv.other(e, cf.opp[k]), sn);
-        const TA Nj = (TA)fsv.cellN(j);
-        TA sL[4], sR[4];
+    for (int k0 = 0; k0 < DEG; k0 += P) {
+        T so[P][4], sn[P][4], nj[P];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            sL[v] = (TA)(isL ? so[v] : sn[v]);
-            sR[v] = (TA)(isL ? sn[v] : so[v]);
+        for (int q = 0; q < P; ++q) {
+            const int k = k0 + q;
+            if (k >= DEG) break;
+            const int64_t e = base + (int64_t)k * kSlice;
+            const bool pad = cf.nbr[k] < 0;
+            load4(fsv.own(e), so[q]);
+            load4(pad ? fsv.own(e) : fsv.other(e, cf.opp[k]), sn[q]);
+            nj[q] = fsv.cellN(pad ? (int32_t)i : cf.nbr[k]);
         }
-        const TA NL = isL ? Ni : Nj, NR = isL ? Nj : Ni;
-        int aN = 0, aF = 0;
-        TA Phi[4];
-        const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)cf.vL[k], (TA)cf.vR[k], (TA)cf.n[k][0],
-                                             (TA)cf.n[k][1], (TA)cf.n[k][2], A, cdt, Phi, aN, aF);
-        if (isL) {
-            cAdmN += aN; cAdmF += aF; cCap += capped ? 1 : 0;
-        }
-        const TA sA = isL ? A : -A;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] += (double)(sA * Phi[v]);
+        for (int q = 0; q < P; ++q) {
+            const int k = k0 + q;
+            if (k >= DEG) break;
+            const int32_t j = cf.nbr[k];
+            if (j < 0) continue;
+            const bool isL = cf.isL[k];
+            const TA A = (TA)cf.A[k];
+            const TA Nj = (TA)nj[q];
+            TA sL[4], sR[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                sL[v] = (TA)(isL ? so[q][v] : sn[q][v]);
+                sR[v] = (TA)(isL ? sn[q][v] : so[q][v]);
+            }
+            const TA NL = isL ? Ni : Nj, NR = isL ? Nj : Ni;
+            int aN = 0, aF = 0;
+            TA Phi[4];
+            const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)cf.vL[k], (TA)cf.vR[k], (TA)cf.n[k][0],
+                                                 (TA)cf.n[k][1], (TA)cf.n[k][2], A, cdt, Phi, aN, aF);
+            if (isL) {
+                cAdmN += aN; cAdmF += aF; cCap += capped ? 1 : 0;
+            }
+            const TA sA = isL ? A : -A;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += (double)(sA * Phi[v]);
+        }
     }
 }
 

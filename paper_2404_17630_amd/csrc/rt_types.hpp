@@ -10,6 +10,7 @@ namespace rtk {
 constexpr int kMaxBins = 8;
 constexpr int kBlock = 256;          // threads per workgroup (four wave64s)
 constexpr int kSlice = 64;           // cells per SELL slice = one wavefront
+constexpr int kMaxCellFaces = 4096;    // faces a cell may have (rt_mesh_create rejects more)
 constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, workgroups dispatched round-robin
 
 // Chemistry constants (from rt_params).
