@@ -237,49 +237,48 @@ int rt_mesh::build_side_geometry(size_t tbytes) {
     if (d.ptr) return RT_OK;
     const int64_t ne = n_entries;
     int rc;
-    if ((rc = d.alloc((size_t)kSideGroups * 4 * ne * tbytes))) return rc;
-    std::vector<double> grp((size_t)4 * ne);
-    std::vector<float> grp32(tbytes == 4 ? 4 * ne : 0);
-    for (int g = 0; g < kSideGroups; ++g) {
-        for (int64_t e = 0; e < ne; ++e) {
-            double v[4] = {0.0, 0.0, 0.0, 0.0};
-            if (nbr[e] >= 0) {
-                const bool isL = fsf[e] >= 0;
-                const double* rec = &face[(size_t)(isL ? fsf[e] : ~fsf[e]) * kFaceRec];
-                const double* ro = isL ? rec + 4 : rec + 7;     // own offset
-                const double* rn = isL ? rec + 7 : rec + 4;     // neighbour's offset
-                double all[kSideComps];
-                const double d0 = ro[0] - rn[0], d1 = ro[1] - rn[1], d2 = ro[2] - rn[2];
-                const double sc = rec[0] / (d0 * d0 + d1 * d1 + d2 * d2);
-                all[kSW0] = d0 * sc; all[kSW1] = d1 * sc; all[kSW2] = d2 * sc;
-                all[kSR0] = ro[0]; all[kSR1] = ro[1]; all[kSR2] = ro[2];
-                all[kSA] = rec[0];
-                all[kSN0] = rec[1]; all[kSN1] = rec[2]; all[kSN2] = rec[3];
-                all[kSVL] = rec[10]; all[kSVR] = rec[11];
-                for (int q = 0; q < 4; ++q) v[q] = all[4 * g + q];
-            }
-            for (int q = 0; q < 4; ++q) grp[(size_t)4 * e + q] = v[q];
-        }
-        void* dst = (char*)d.ptr + (size_t)g * 4 * ne * tbytes;
-        hipError_t err;
-        if (tbytes == 4) {
-            for (size_t q = 0; q < grp.size(); ++q) grp32[q] = (float)grp[q];
-            err = hipMemcpy(dst, grp32.data(), (size_t)4 * ne * 4, hipMemcpyHostToDevice);
-        } else {
-            err = hipMemcpy(dst, grp.data(), (size_t)4 * ne * 8, hipMemcpyHostToDevice);
-        }
-        if (err != hipSuccess) return rt_fail(RT_EDEVICE, "side geometry upload: %s", hipGetErrorString(err));
+    if ((rc = d.alloc((size_t)kSideComps * ne * tbytes))) return rc;
+    // all components of every entry, then each group as its own array
+    std::vector<double> all((size_t)kSideComps * ne, 0.0);
+    for (int64_t e = 0; e < ne; ++e) {
+        if (nbr[e] < 0) continue;
+        const bool isL = fsf[e] >= 0;
+        const double* rec = &face[(size_t)(isL ? fsf[e] : ~fsf[e]) * kFaceRec];
+        const double* ro = isL ? rec + 4 : rec + 7;     // own offset
+        const double* rn = isL ? rec + 7 : rec + 4;     // neighbour's offset
+        double* a = &all[(size_t)kSideComps * e];
+        const double d0 = ro[0] - rn[0], d1 = ro[1] - rn[1], d2 = ro[2] - rn[2];
+        const double sc = rec[0] / (d0 * d0 + d1 * d1 + d2 * d2);
+        a[kSW0] = d0 * sc; a[kSW1] = d1 * sc; a[kSW2] = d2 * sc;
+        a[kSR0] = ro[0]; a[kSR1] = ro[1]; a[kSR2] = ro[2];
+        a[kSA] = rec[0];
+        a[kSN0] = rec[1]; a[kSN1] = rec[2]; a[kSN2] = rec[3];
+        a[kSVL] = rec[10]; a[kSVR] = rec[11];
     }
+    std::vector<double> grp((size_t)kSideComps * ne);
+    for (int g = 0; g < kSideGroups; ++g) {
+        const int c0 = kSideGroupFirst[g], w = kSideGroupFirst[g + 1] - c0;
+        for (int64_t e = 0; e < ne; ++e)
+            for (int q = 0; q < w; ++q) grp[(size_t)c0 * ne + (size_t)e * w + q] = all[(size_t)kSideComps * e + c0 + q];
+    }
+    hipError_t err;
+    if (tbytes == 4) {
+        std::vector<float> g32(grp.begin(), grp.end());
+        err = hipMemcpy(d.ptr, g32.data(), g32.size() * 4, hipMemcpyHostToDevice);
+    } else {
+        err = hipMemcpy(d.ptr, grp.data(), grp.size() * 8, hipMemcpyHostToDevice);
+    }
+    if (err != hipSuccess) return rt_fail(RT_EDEVICE, "side geometry upload: %s", hipGetErrorString(err));
     return RT_OK;
 }
 
-// (nbr, fsf, opp, 0) of every sliced-ELL entry as one 16-byte record.
+// (nbr, opp for an L side or ~opp for an R side) of every sliced-ELL entry
+// as one 8-byte record.
 static int upload_packed_index(rt_mesh* m) {
-    std::vector<int32_t> p((size_t)4 * m->n_entries, 0);
+    std::vector<int32_t> p((size_t)2 * m->n_entries, 0);
     for (int64_t e = 0; e < m->n_entries; ++e) {
-        p[4 * e] = m->nbr[e];
-        p[4 * e + 1] = m->fsf[e];
-        p[4 * e + 2] = m->opp[e];
+        p[2 * e] = m->nbr[e];
+        p[2 * e + 1] = m->nbr[e] < 0 ? 0 : (m->fsf[e] >= 0 ? m->opp[e] : ~m->opp[e]);
     }
     return m->d_idx.upload(p.data(), p.size() * 4);
 }
@@ -921,7 +920,7 @@ GeomView<double> rt_geo64(const rt_mesh* m) { return geom_view<double>(m); }
 
 SellView rt_sell(const rt_mesh* m) {
     return SellView{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_opp.ptr,
-                    (const int32_t*)m->d_sptr.ptr, (const int32_t*)m->d_sdeg.ptr, (const int4*)m->d_idx.ptr,
+                    (const int32_t*)m->d_sptr.ptr, (const int32_t*)m->d_sdeg.ptr, (const int2*)m->d_idx.ptr,
                     m->uniform_deg};
 }
 

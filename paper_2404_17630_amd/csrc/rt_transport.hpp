@@ -21,6 +21,14 @@ __device__ inline void load4(const double* __restrict__ p, double* o) {
     const double2 b = *reinterpret_cast<const double2*>(p + 2);
     o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
+__device__ inline void load2(const float* __restrict__ p, float* o) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    o[0] = v.x; o[1] = v.y;
+}
+__device__ inline void load2(const double* __restrict__ p, double* o) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = v.x; o[1] = v.y;
+}
 __device__ inline void store4(float* __restrict__ p, const float* v) {
     *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
 }
@@ -136,9 +144,9 @@ __device__ inline void load_cell_sides(int64_t i, const GeomView<T>& geo, const 
     for (int k = 0; k < DEG; ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
         cs.nbr[k] = sell.nbr[e];
-        T g0[4], g1[4];
+        T g0[4], g1[2];
         load4(geo.sg(0, e), g0);
-        load4(geo.sg(1, e), g1);
+        load2(geo.sg(1, e), g1);
         cs.w[k][0] = g0[0]; cs.w[k][1] = g0[1]; cs.w[k][2] = g0[2];
         cs.r[k][0] = g0[3]; cs.r[k][1] = g1[0]; cs.r[k][2] = g1[1];
     }
@@ -155,15 +163,15 @@ __device__ inline void load_cell_faces(int64_t i, const GeomView<T>& geo, const 
 #pragma unroll
     for (int k = 0; k < DEG; ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
-        const int4 id = sell.idx[e];
+        const int2 id = sell.nop[e];
         cf.nbr[k] = id.x;
         cf.isL[k] = id.y >= 0;
-        cf.opp[k] = id.z;
-        T g1[4], g2[4];
-        load4(geo.sg(1, e), g1);
-        load4(geo.sg(2, e), g2);
-        cf.A[k] = g1[2]; cf.vL[k] = g1[3];
-        cf.n[k][0] = g2[0]; cf.n[k][1] = g2[1]; cf.n[k][2] = g2[2]; cf.vR[k] = g2[3];
+        cf.opp[k] = id.y >= 0 ? id.y : ~id.y;
+        T g2[2], g3[4];
+        load2(geo.sg(2, e), g2);
+        load4(geo.sg(3, e), g3);
+        cf.vL[k] = g2[0]; cf.vR[k] = g2[1];
+        cf.A[k] = g3[0]; cf.n[k][0] = g3[1]; cf.n[k][1] = g3[2]; cf.n[k][2] = g3[3];
     }
 }
 

@@ -33,15 +33,19 @@ __host__ __device__ inline int64_t urec(int b, int64_t nc, int64_t i) { return (
 //   cell [nc][kCellRec]: inverse geometry matrix xx, yy, zz, xy, xz, yz; V; vcap
 constexpr int kFaceRec = 12;
 constexpr int kCellRec = 8;
-// Per face side (sliced-ELL entry e), three groups of four values, each
-// group a structure of arrays of 4-value records side[g][e][4]:
-//   g = 0: w_x, w_y, w_z, r_x      w = A d / |d|^2 with d = s_j - s_i
-//   g = 1: r_y, r_z, A, vcap_L     r = r_if, offset from the cell centre
-//   g = 2: n_x, n_y, n_z, vcap_R   n from L to R, vcap = V / n_faces
-// zeros for padding entries.  A wavefront reads a group of a slot as one
-// contiguous run of 16-byte (FP32) or 32-byte (FP64) records.
-enum SideComp { kSW0 = 0, kSW1, kSW2, kSR0, kSR1, kSR2, kSA, kSVL, kSN0, kSN1, kSN2, kSVR, kSideComps };
-constexpr int kSideGroups = 3;
+// Per face side (sliced-ELL entry e), twelve values in four groups, each
+// group a structure of arrays of records side[g][e][w] of width w, so that
+// a kernel reads exactly the groups it uses:
+//   g = 0 (w 4): w_x, w_y, w_z, r_x   w = A d / |d|^2 with d = s_j - s_i
+//   g = 1 (w 2): r_y, r_z             r = r_if, offset from the cell centre
+//   g = 2 (w 2): vcap_L, vcap_R       vcap = V / n_faces of the L and R cells
+//   g = 3 (w 4): A, n_x, n_y, n_z     n from L to R
+// (the gradient reads groups 0 and 1, the flux groups 2 and 3); zeros for
+// padding entries.  A wavefront reads a group of a slot as one contiguous
+// run.
+enum SideComp { kSW0 = 0, kSW1, kSW2, kSR0, kSR1, kSR2, kSVL, kSVR, kSA, kSN0, kSN1, kSN2, kSideComps };
+constexpr int kSideGroups = 4;
+constexpr int kSideGroupFirst[kSideGroups + 1] = {0, 4, 6, 8, 12};   // first component of each group
 template <typename T>
 struct GeomView {
     const T* face;
@@ -49,10 +53,16 @@ struct GeomView {
     const T* side;
     int64_t nf;
     int64_t ne;
+    // group g of entry e (kSideGroupFirst[g+1] - kSideGroupFirst[g] values)
+    __host__ __device__ const T* sg(int g, int64_t e) const {
+        const int w = kSideGroupFirst[g + 1] - kSideGroupFirst[g];
+        return side + (int64_t)kSideGroupFirst[g] * ne + e * w;
+    }
     // component c (SideComp) of entry e
-    __device__ T sv(int c, int64_t e) const { return side[((int64_t)(c >> 2) * ne + e) * 4 + (c & 3)]; }
-    // group g of entry e (four values)
-    __device__ const T* sg(int g, int64_t e) const { return side + ((int64_t)g * ne + e) * 4; }
+    __host__ __device__ T sv(int c, int64_t e) const {
+        const int g = c < 4 ? 0 : c < 6 ? 1 : c < 8 ? 2 : 3;
+        return sg(g, e)[c - kSideGroupFirst[g]];
+    }
 };
 
 // Face sides of each cell in sliced-ELL order: slice s (cells 64s..64s+63)
@@ -66,7 +76,7 @@ struct SellView {
     const int32_t* opp;
     const int32_t* ptr;
     const int32_t* deg;
-    const int4* idx;       // (nbr, fsf, opp, 0) of each entry, one 16-byte load
+    const int2* nop;       // (nbr, opp for an L side or ~opp for an R side) of each entry, one 8-byte load
     int32_t uniform_deg;   // slots of every slice when all are equal and specialised (6, 14), else 0
 };
 
