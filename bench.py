@@ -78,8 +78,10 @@ def subcycle_bytes_per_cell(nb: int, p: int, g: int) -> dict:
 
 
 def kernel_source_digest() -> str:
+    """First 16 hex digits of SHA-256 over the kernel sources and the build
+    script (its compiler flags)."""
     h = hashlib.sha256()
-    for f in sorted((ROOT / "paper_2404_17630_amd" / "csrc").glob("*")):
+    for f in sorted((ROOT / "paper_2404_17630_amd" / "csrc").glob("*")) + [ROOT / "paper_2404_17630_amd" / "build.py"]:
         h.update(f.read_bytes())
     return h.hexdigest()[:16]
 
@@ -117,6 +119,40 @@ def cpu_baseline():
     return dict(value=nc * nb * 2 / secs, unit="cell*bin updates/s", cores=1, kind="oracle",
                 sample="throughput recipe at 64^3 (262,144 cells, sigma_ln=1.5, 64 sources, 3 bins, c~=0.1c), "
                        f"2 subcycles from the initial state, {secs:.2f} s single-threaded")
+
+
+def adjoint_timing(rt, torch):
+    """The adjoint workload (64^3 cells, 3 bins, 64 sources, 50 FP64
+    subcycles, checkpoints every 10): seconds of the forward run and of one
+    rt_subcycle_adjoint call (its own forward pass, the segment recomputes
+    and the reverse sweep), with seeded weights as dL/dx_HI."""
+    import rtgen
+    from paper_2404_17630_amd.autograd import Problem
+    log("adjoint workload 64^3, 50 FP64 subcycles")
+    cfg = rtgen.adjoint_262k()
+    pb = Problem(cfg, checkpoint_every=10)
+    s0 = pb.state(pb.log_lum0, np.log(cfg["state"]["n_H"]))
+    stream = torch.cuda.current_stream()
+    run = s0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.subcycle(pb.n_subcycles, stream=stream)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    run.close()
+    nc = cfg["mesh"]["n_cells"]
+    g = torch.from_numpy(np.random.default_rng(11).normal(size=nc)).to("cuda")
+    d_lum = torch.zeros(pb.log_lum0.size, dtype=torch.float64, device="cuda")
+    d_nH = torch.zeros(nc, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rt.rt_subcycle_adjoint(s0.h, pb.n_subcycles, pb.checkpoint_every, g, d_lum, d_nH, stream)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    s0.close()
+    pb.mesh.close()
+    return {"cells": nc, "subcycles": pb.n_subcycles, "checkpoint_every": pb.checkpoint_every,
+            "forward_s": t_fwd, "adjoint_call_s": t_adj, "adjoint_over_forward": t_adj / t_fwd}
 
 
 def main() -> int:
@@ -312,6 +348,8 @@ def main() -> int:
         mesh_r.close()
         out["random_order_value"] = nc * nb * args.steps / t_r
         out["kernels_mixed_random"] = kernel_table(prof_r, 4, 4)
+        del cfg_r
+        out["adjoint_262k"] = adjoint_timing(rt, torch)
     else:
         st_mixed.close()
         mesh.close()

@@ -20,8 +20,12 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-    # packed FP32 instructions stay off (see the design notes)
+    # no packed FP32 arithmetic instructions in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP32 division and square root by the hardware reciprocal and square
+    # root (2.5 and 1 ulp) rather than correctly rounded sequences; only the
+    # mixed form's face physics computes in FP32
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wall", "-Wno-unused-result", "-Wno-unused-function",
     f"-I{ROOT / 'include'}", f"-I{CSRC}",
 ]

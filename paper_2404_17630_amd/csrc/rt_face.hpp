@@ -62,7 +62,8 @@ __device__ inline void radiation_pressure_n(const R* U, G n0, G n1, G n2, R* P) 
     const R f2 = f * f;
     const R chi = (G(3) + G(4) * f2) / (G(5) + G(2) * m_sqrt(G(4) - G(3) * f2));
     const R iso = G(0.5) * (G(1) - chi);
-    const R u0 = U[1] / Fm, u1 = U[2] / Fm, u2 = U[3] / Fm;
+    const R iFm = G(1) / Fm;
+    const R u0 = U[1] * iFm, u1 = U[2] * iFm, u2 = U[3] * iFm;
     const R dir = G(0.5) * (G(3) * chi - G(1)) * (u0 * n0 + u1 * n1 + u2 * n2);
     P[0] = N * (iso * n0 + dir * u0);
     P[1] = N * (iso * n1 + dir * u1);
