@@ -182,6 +182,7 @@ int rt_mesh::build_float_geometry() {
 static_assert(kTileCells == RT_TILE_CELLS, "tile size of the header and the kernels");
 static_assert(kTileCells % kBlock == 0 && kTileCells % kSlice == 0, "tiles are whole blocks and slices");
 static_assert(kTileThreads == kTileCells, "one thread per tile cell in the flux phase");
+static_assert(kTileCells % kFluxBlock == 0 && kFluxBlock % 64 == 0, "tiles hold whole flux workgroups of whole waves");
 
 void rt_mesh::build_tiles() {
     const int64_t ns = (int64_t)sdeg.size();
@@ -639,7 +640,7 @@ int rt_state::alloc_buffers() {
     if ((rc = U[0].alloc((size_t)nb * 4 * nc * t)) || (rc = U[1].alloc((size_t)nb * 4 * nc * t)) ||
         (rc = X.alloc(5 * nc * 8)) || (rc = Ue.alloc(nc * 8)) || (rc = nH.alloc(nc * 8)))
         return rc;
-    n_fblk = transport_blocks(nc, nb);
+    n_fblk = partial_blocks(nc, nb);
     n_cblk = chem_blocks(nc);
     if ((rc = part_nv.alloc(n_fblk * 8)) || (rc = part_cnt.alloc(5 * n_fblk * 8)) ||
         (rc = part_fst.alloc(n_fblk * 4)) || (rc = chem_sum.alloc(n_cblk * 8)) || (rc = chem_max.alloc(n_cblk * 8)) ||

@@ -423,7 +423,7 @@ __device__ inline void block_partials(double nv, int cAdmN, int cAdmF, int cCap,
     }
 }
 
-template <typename T, typename TA>
+template <typename T, typename TA, int NT = kBlock>
 __device__ inline void finish_cell(int64_t i, int b, int64_t nc, const T* ui, const double* acc, TA cdt,
                                    const GeomView<T>& geo, T* __restrict__ Unew, int cAdmN, int cAdmF, int cCap,
                                    int64_t blk, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
@@ -431,11 +431,11 @@ __device__ inline void finish_cell(int64_t i, int b, int64_t nc, const T* ui, co
     int cGN = 0, cGF = 0, status = 0;
     double nv = 0.0;
     if (i < nc) update_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, nv, cGN, cGF, status);
-    block_partials(nv, cAdmN, cAdmF, cCap, cGN, cGF, status, blk, part_nv, part_cnt, part_status, n_blocks);
+    block_partials<NT>(nv, cAdmN, cAdmF, cCap, cGN, cGF, status, blk, part_nv, part_cnt, part_status, n_blocks);
 }
 
 template <typename T, typename TA, int DEG>
-__global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ FV,
+__global__ __launch_bounds__(kFluxBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ FV,
                                                  const T* __restrict__ NC, T* __restrict__ Unew,
                                                  int64_t nc, int nb, int64_t n_entries, GeomView<T> geo, SellView sell,
                                                  TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
         // One lane per (cell, bin); the geometry of the three or more bins of
         // a tile is read by neighbouring workgroups on the same XCD.
         const int b = (int)(blk % nb);
-        const int64_t i = (blk / nb) * kBlock + threadIdx.x;
+        const int64_t i = (blk / nb) * kFluxBlock + threadIdx.x;
         int cAdmN = 0, cAdmF = 0, cCap = 0;
         T ui[4] = {0, 0, 0, 0};
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -457,11 +457,11 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
             cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, (int64_t)sell.ptr[i / kSlice] + (i % kSlice), cf, cdt,
                                         (TA)ui[0], acc, cAdmN, cAdmF, cCap);
         }
-        finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
+        finish_cell<T, TA, kFluxBlock>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
                            part_status, n_blocks);
     } else {
         const int b = (int)(blk % nb);
-        const int64_t i = (blk / nb) * kBlock + threadIdx.x;
+        const int64_t i = (blk / nb) * kFluxBlock + threadIdx.x;
         int cAdmN = 0, cAdmF = 0, cCap = 0;
         T ui[4] = {0, 0, 0, 0};
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_flux(const T* __restrict__ U, const 
             const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp, NC + (int64_t)b * nc};
             cell_flux_sum_s<T, TA, DEG>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
         }
-        finish_cell<T, TA>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
+        finish_cell<T, TA, kFluxBlock>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
                            part_status, n_blocks);
     }
 }
@@ -761,6 +761,7 @@ void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, cons
 
 int64_t chem_blocks(int64_t nc) { return (int64_t)grid_for(nc, (int64_t)kBlock * chem_chunk(nc)); }
 int64_t transport_blocks(int64_t nc, int nb) { return (int64_t)grid_for(nc, kBlock) * nb; }
+int64_t partial_blocks(int64_t nc, int nb) { return (int64_t)grid_for(nc, kFluxBlock) * nb; }
 
 // The transport kernels are specialised for meshes whose slices all have 6
 // slots (lattices) or 14 (the staggered BCC mesh); other meshes take the
@@ -793,9 +794,9 @@ void launch_flux(const T* U, const T* FV, const T* NC, T* Unew, int64_t nc, int 
                  const GeomView<T>& geo,
                  const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
                  hipStream_t s) {
-    const int64_t nblk = transport_blocks(nc, nb);
+    const int64_t nblk = partial_blocks(nc, nb);
 #define RT_CALL(D)                                                                                               \
-    hipLaunchKernelGGL((k_flux<T, T, D>), dim3((unsigned)nblk), dim3(kBlock), 0, s, U, FV, NC, Unew, nc, nb, n_entries, \
+    hipLaunchKernelGGL((k_flux<T, T, D>), dim3((unsigned)nblk), dim3(kFluxBlock), 0, s, U, FV, NC, Unew, nc, nb, n_entries, \
                        geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk)
     RT_DEG_DISPATCH(sell.uniform_deg, RT_CALL)
 #undef RT_CALL
@@ -805,7 +806,7 @@ template <typename T, int D>
 static void launch_transport_deg(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>& geo,
                                  const SellView& sell, const TileView& tile, size_t lds_bytes, int use_limiter,
                                  double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
-    const int64_t nblk = transport_blocks(nc, nb);              // partial slots (256-cell blocks)
+    const int64_t nblk = partial_blocks(nc, nb);                // partial slots
     const int64_t ntile_blk = (int64_t)grid_for(nc, kTileCells) * nb;
     if (lds_bytes > 65536)
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_transport<T, T, D>),

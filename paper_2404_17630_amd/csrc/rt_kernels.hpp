@@ -27,7 +27,8 @@ void fill_words(void* p, int64_t n_words, uint32_t v, hipStream_t s);
 
 int chem_chunk(int64_t nc);
 int64_t chem_blocks(int64_t nc);
-int64_t transport_blocks(int64_t nc, int nb);
+int64_t transport_blocks(int64_t nc, int nb);   // workgroups of kBlock cells, times nb
+int64_t partial_blocks(int64_t nc, int nb);     // per-block partial slots (kFluxBlock cells), times nb
 int64_t cfl_partials(int64_t nc);
 
 template <typename T>

@@ -95,7 +95,10 @@ struct SellView {
 constexpr int kTileCells = 256;                 // cells per tile (RT_TILE_CELLS)
 constexpr int kTileThreads = 256;               // threads per tile workgroup: one per tile cell
 constexpr int kTileSlices = kTileCells / kSlice;
-constexpr int kTileBlocks = kTileCells / kBlock;  // 256-cell blocks per tile (partials layout)
+// Cells per workgroup of the flux kernel, which is also the granularity of
+// the per-block partials (photon sums, counters, status) of both paths.
+constexpr int kFluxBlock = 256;
+constexpr int kTileBlocks = kTileCells / kFluxBlock;  // partial slots per tile
 struct TileView {
     const int32_t* lds_opp;
     const int32_t* halo_ptr;
