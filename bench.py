@@ -165,6 +165,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--transport", choices=("auto", "fused", "split"), default="auto",
                     help="transport path of the headline run (the library's default is auto)")
+    ap.add_argument("--order", choices=("hilbert", "random"), default="hilbert",
+                    help="cell order of the headline run (random: for profiling the unordered case; "
+                         "the throughput figure is quoted in Hilbert order)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="first copy a GIB-sized device buffer three times (a plain copy kernel of known size, "
                          "for scaling hardware byte counters)")
@@ -195,12 +198,14 @@ def main() -> int:
     n_src = max(1, int(round(4096 * (args.n / 256) ** 3)))
     log(f"generating throughput workload {args.n}^3, {n_src} sources")
     cfg = rtgen.throughput_16m(n=args.n, n_src=n_src, n_sub=args.steps)
+    if args.order == "random":
+        cfg = rtgen.random_order(cfg)
     nc, nb, nf = cfg["mesh"]["n_cells"], cfg["params"]["nb"], cfg["mesh"]["n_faces"]
     n_sides = 2 * nf
     log("creating mesh")
     mesh = rt.Mesh(cfg["mesh"])
 
-    log(f"mixed, hilbert: {args.steps} subcycles")
+    log(f"mixed, {args.order}: {args.steps} subcycles")
     mode = {"auto": None, "fused": rt.RT_TRANSPORT_FUSED, "split": rt.RT_TRANSPORT_SPLIT}[args.transport]
     st_mixed, t_mixed, prof_mixed = timed_run(rt, mesh, cfg, rt.RT_MIXED, args.steps, args.warmup, torch,
                                               transport=mode)
@@ -228,7 +233,8 @@ def main() -> int:
     if TRAFFIC_FILE.exists():
         rec = json.loads(TRAFFIC_FILE.read_text())
         ent = rec.get("kernels", {}).get(dominant)
-        if ent and rec.get("source_digest") == kernel_source_digest() and rec.get("workload") == f"throughput_{args.n}":
+        if ent and rec.get("source_digest") == kernel_source_digest() and rec.get("workload") == f"throughput_{args.n}" \
+                and args.order == "hilbert":
             traffic = ent["bytes_per_launch"]
 
     out = {
@@ -245,7 +251,7 @@ def main() -> int:
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"throughput_{args.n}", "cells": nc, "bins": nb, "sources": int(n_src),
-                   "subcycles": args.steps, "order": "hilbert", "precision": "mixed", "c_reduced": "0.1c",
+                   "subcycles": args.steps, "order": args.order, "precision": "mixed", "c_reduced": "0.1c",
                    "transport": "fused" if st_mixed.fused else "split",
                    "sigma_ln": 1.5},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": dk["gbs"], "peak": HBM_PEAK_GBS,
@@ -258,7 +264,7 @@ def main() -> int:
         "chem_attempts_per_cell_subcycle": diag["substeps"] / (nc * args.steps),
     }
 
-    if not args.no_extras:
+    if not args.no_extras and args.order == "hilbert":
         fields_mixed = st_mixed.fields()
         st_mixed.close()
         other = "split" if out["config"]["transport"] == "fused" else "fused"
