@@ -183,11 +183,13 @@ __device__ inline void limited_gradient_c(int64_t i, int b, int64_t nc, const T*
     load4(U + urec(b, nc, i), u0);
 #pragma unroll
     for (int v = 0; v < 4; ++v) ui[v] = (double)u0[v];
-    double bs[4][3], umax[4], umin[4];
+    // neighbour extrema in the storage precision (exact: they are stored values)
+    double bs[4][3];
+    T umax[4], umin[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         bs[v][0] = bs[v][1] = bs[v][2] = 0.0;
-        umax[v] = umin[v] = ui[v];
+        umax[v] = umin[v] = u0[v];
     }
     // The neighbour records of a batch of slots are all requested before
     // any is used, so the gathers overlap instead of each waiting for the
@@ -214,8 +216,8 @@ __device__ inline void limited_gradient_c(int64_t i, int b, int64_t nc, const T*
                 bs[v][0] += w0 * dphi;
                 bs[v][1] += w1 * dphi;
                 bs[v][2] += w2 * dphi;
-                umax[v] = ujv > umax[v] ? ujv : umax[v];
-                umin[v] = ujv < umin[v] ? ujv : umin[v];
+                umax[v] = fmax(uj[q][v], umax[v]);
+                umin[v] = fmin(uj[q][v], umin[v]);
             }
         }
     }
@@ -234,7 +236,7 @@ __device__ inline void limited_gradient_c(int64_t i, int b, int64_t nc, const T*
         const double r0 = cs.r[k][0], r1 = cs.r[k][1], r2 = cs.r[k][2];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2, umax[v] - ui[v], ui[v] - umin[v]);
+            bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2, (double)umax[v] - ui[v], ui[v] - (double)umin[v]);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -309,11 +311,13 @@ __device__ inline void limited_gradient_s(int64_t i, int b, int64_t nc, const T*
     load4(U + urec(b, nc, i), u0);
 #pragma unroll
     for (int v = 0; v < 4; ++v) ui[v] = (double)u0[v];
-    double bs[4][3], umax[4], umin[4];
+    // neighbour extrema in the storage precision (exact: they are stored values)
+    double bs[4][3];
+    T umax[4], umin[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         bs[v][0] = bs[v][1] = bs[v][2] = 0.0;
-        umax[v] = umin[v] = ui[v];
+        umax[v] = umin[v] = u0[v];
     }
     const int64_t slice = i / kSlice;
     const int32_t deg = DEG > 0 ? DEG : sell.deg[slice];
@@ -337,8 +341,8 @@ __device__ inline void limited_gradient_s(int64_t i, int b, int64_t nc, const T*
             bs[v][0] += w0 * dphi;
             bs[v][1] += w1 * dphi;
             bs[v][2] += w2 * dphi;
-            umax[v] = ujv > umax[v] ? ujv : umax[v];
-            umin[v] = ujv < umin[v] ? ujv : umin[v];
+            umax[v] = fmax(uj[v], umax[v]);
+            umin[v] = fmin(uj[v], umin[v]);
         }
     }
     T c[8];
@@ -366,7 +370,7 @@ __device__ inline void limited_gradient_s(int64_t i, int b, int64_t nc, const T*
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2, umax[v] - ui[v], ui[v] - umin[v]);
+            bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2, (double)umax[v] - ui[v], ui[v] - (double)umin[v]);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {

@@ -123,3 +123,41 @@ def test_host_only_mesh_cannot_hold_a_state():
         rt.State.from_config(m, cfg)
     assert ei.value.code == rt.RT_EDEVICE
     m.close()
+
+
+def _hub_mesh(n_spokes):
+    """Cell 0 joined to cells 1..n; each of those also joined to its two
+    neighbours on either side of a ring, so it has five faces."""
+    n = n_spokes
+    nc = n + 1
+    L = [0] * n + list(range(1, n + 1)) * 2
+    R = list(range(1, n + 1)) + [k % n + 1 for k in range(1, n + 1)] + [(k + 1) % n + 1 for k in range(1, n + 1)]
+    nf = len(L)
+    rng = np.random.default_rng(7)
+    nrm = rng.normal(size=(3, nf))
+    nrm /= np.linalg.norm(nrm, axis=0)
+    return dict(n_cells=nc, volume=np.ones(nc), centre=rng.uniform(size=(3, nc)), n_faces=nf,
+                face_cells=np.array([L, R], dtype=np.int64), area=np.ones(nf), normal=nrm,
+                face_centre=rng.uniform(size=(3, nf)), box=np.zeros(3))
+
+
+def test_mesh_rejects_a_cell_with_more_faces_than_the_kernels_count():
+    """The per-block counters pack per-face counts in 21-bit fields, which
+    holds for cells of up to 4096 faces; rt_mesh_create refuses more."""
+    with pytest.raises(rt.RtError) as e:
+        rt.Mesh(_hub_mesh(4097), device=rt.RT_DEVICE_HOST_ONLY)
+    assert e.value.code == rt.RT_EMESH and "4097 faces (> 4096)" in str(e.value)
+
+
+def test_mesh_rejects_a_cell_with_fewer_than_four_faces():
+    m = _hub_mesh(8)
+    # drop the second ring of faces: every ring cell is left with three
+    keep = 2 * 8
+    m["area"] = m["area"][:keep]
+    m["face_cells"] = m["face_cells"][:, :keep]
+    m["normal"] = m["normal"][:, :keep]
+    m["face_centre"] = m["face_centre"][:, :keep]
+    m["n_faces"] = keep
+    with pytest.raises(rt.RtError) as e:
+        rt.Mesh(m, device=rt.RT_DEVICE_HOST_ONLY)
+    assert e.value.code == rt.RT_EMESH and "(< 4)" in str(e.value)
