@@ -128,10 +128,16 @@ template <int DEG>
 struct SlotBatch {
     static constexpr int kSize = DEG <= 8 ? DEG : (DEG + 1) / 2;
 };
+// The flux sum takes three slots at a time, loading their face records with
+// their gathers: the records of all slots held at once cost more in
+// occupancy than the extra overlap gains.
+template <int DEG>
+struct FluxBatch {
+    static constexpr int kSize = DEG < 3 ? DEG : 3;
+};
 
-// Side records of one cell's DEG slots (DEG > 0), loaded once and reused
-// for every bin: the neighbours, the least-squares weights and face offsets
-// (gradient), and the face's orientation, A, n and V/n_faces (flux).
+// Side records of one cell's DEG slots (DEG > 0) for the gradient: the
+// neighbours, the least-squares weights and the face offsets.
 template <typename T, int DEG>
 struct CellSides {
     int32_t nbr[DEG];
@@ -151,11 +157,16 @@ __device__ inline void load_cell_sides(int64_t i, const GeomView<T>& geo, const 
         cs.r[k][0] = g0[3]; cs.r[k][1] = g1[0]; cs.r[k][2] = g1[1];
     }
 }
+// Index records of one cell's DEG slots for the flux sum (neighbour,
+// opposite entry, orientation), loaded once and reused for every bin; the
+// face records (groups 2 and 3 of the side records) are read with each
+// batch of slots.
 template <typename T, int DEG>
 struct CellFaces {
     int32_t nbr[DEG], opp[DEG];
     bool isL[DEG];
-    T A[DEG], n[DEG][3], vL[DEG], vR[DEG];
+    const T* side2;        // (V_L/n, V_R/n) of every entry
+    const T* side3;        // (A, n) of every entry
 };
 template <typename T, int DEG>
 __device__ inline void load_cell_faces(int64_t i, const GeomView<T>& geo, const SellView& sell, CellFaces<T, DEG>& cf) {
@@ -167,12 +178,9 @@ __device__ inline void load_cell_faces(int64_t i, const GeomView<T>& geo, const 
         cf.nbr[k] = id.x;
         cf.isL[k] = id.y >= 0;
         cf.opp[k] = id.y >= 0 ? id.y : ~id.y;
-        T g2[2], g3[4];
-        load2(geo.sg(2, e), g2);
-        load4(geo.sg(3, e), g3);
-        cf.vL[k] = g2[0]; cf.vR[k] = g2[1];
-        cf.A[k] = g3[0]; cf.n[k][0] = g3[1]; cf.n[k][1] = g3[2]; cf.n[k][2] = g3[3];
     }
+    cf.side2 = geo.sg(2, 0);
+    cf.side3 = geo.sg(3, 0);
 }
 
 // Limited gradient of cell i (bin b) from its loaded side records (DEG > 0).
@@ -252,19 +260,21 @@ template <typename T, typename TA, int DEG, typename FS>
 __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __restrict__ U, const FS& fsv,
                                        int64_t base, const CellFaces<T, DEG>& cf, TA cdt, TA Ni, double* acc,
                                        int& cAdmN, int& cAdmF, int& cCap) {
-    // The two face states and the neighbour's N of a batch of slots are all
-    // requested before the first flux is computed, so the gathers overlap
-    // (a padding slot reads its own entry and the cell itself, and is
-    // skipped below).
-    constexpr int P = SlotBatch<DEG>::kSize;
+    // The face records, the two face states and the neighbour's N of a
+    // batch of slots are all requested before the batch's first flux is
+    // computed, so the gathers overlap (a padding slot reads its own entry
+    // and the cell itself, and is skipped below).
+    constexpr int P = FluxBatch<DEG>::kSize;
 #pragma unroll
     for (int k0 = 0; k0 < DEG; k0 += P) {
-        T so[P][4], sn[P][4], nj[P];
+        T so[P][4], sn[P][4], nj[P], gv[P][2], ga[P][4];
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             const int k = k0 + q;
             if (k >= DEG) break;
             const int64_t e = base + (int64_t)k * kSlice;
+            load2(cf.side2 + e * 2, gv[q]);
+            load4(cf.side3 + e * 4, ga[q]);
             const bool pad = cf.nbr[k] < 0;
             load4(fsv.own(e), so[q]);
             load4(pad ? fsv.own(e) : fsv.other(e, cf.opp[k]), sn[q]);
@@ -277,7 +287,7 @@ __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __
             const int32_t j = cf.nbr[k];
             if (j < 0) continue;
             const bool isL = cf.isL[k];
-            const TA A = (TA)cf.A[k];
+            const TA A = (TA)ga[q][0];
             const TA Nj = (TA)nj[q];
             TA sL[4], sR[4];
 #pragma unroll
@@ -288,8 +298,8 @@ __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __
             const TA NL = isL ? Ni : Nj, NR = isL ? Nj : Ni;
             int aN = 0, aF = 0;
             TA Phi[4];
-            const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)cf.vL[k], (TA)cf.vR[k], (TA)cf.n[k][0],
-                                                 (TA)cf.n[k][1], (TA)cf.n[k][2], A, cdt, Phi, aN, aF);
+            const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)gv[q][0], (TA)gv[q][1], (TA)ga[q][1],
+                                                 (TA)ga[q][2], (TA)ga[q][3], A, cdt, Phi, aN, aF);
             if (isL) {
                 cAdmN += aN; cAdmF += aF; cCap += capped ? 1 : 0;
             }
