@@ -238,7 +238,7 @@ def main() -> int:
             traffic = ent["bytes_per_launch"]
 
     out = {
-        "metric": "RT cell*bin updates/s per subcycle (mixed precision), with FP64 speedup, error and % HBM peak",
+        "metric": "RT cell\u00b7bin updates/s per subcycle, mixed vs FP64 at stated error; % HBM peak",
         "value": value,
         "unit": "cell*bin updates/s",
         "n_gpus": 1,
