@@ -226,3 +226,17 @@ def test_profile_counters(mode):
     for k in idle:
         assert prof[k][0] == 0
     assert prof[rt.RT_KERNEL_REDUCE][0] == 1
+
+
+def test_many_block_mesh_matches_oracle():
+    """81^3 = 531,441 cells, 3 bins, 2 FP64 subcycles: 2,076 partial rows
+    per bin, so each first-stage workgroup of the reduction folds several;
+    two cells a lane in the chemistry, so lanes refill from the workgroup's
+    counter.  Fields, photon sums and attempt counts against the oracle."""
+    cfg = rtgen.cosmological(81, 1.0, 1.0, 32, 0.01, 2, 7, name="blocks_531k")
+    say("81^3, 2 subcycles, fp64")
+    gpu = run_gpu(cfg)
+    ref = oracle.run(cfg)
+    assert_parity(cfg, gpu, ref)
+    assert gpu["diag"]["substeps"] == ref["diag"]["substeps"]
+    assert gpu["diag"]["max_substeps"] == ref["diag"]["max_substeps"]
