@@ -77,3 +77,20 @@ def test_mixed_determinism():
     b = run_gpu(cfg, precision=rt.RT_MIXED)
     for k in ("N", "F", "species", "T"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_mixed_throughput_recipe_at_531k_cells():
+    """The throughput recipe (sigma_ln = 1.5, c~ = 0.1 c, 3 bins) on 81^3 =
+    531,441 cells for 4 subcycles, the launch shapes of the large runs
+    (multi-row reduction workgroups, several cells a chemistry lane), against
+    the FP64 oracle at the stated bar."""
+    cfg = rtgen.cosmological(81, 1.0, 1.5, 64, 0.1, 4, 4, precision="mixed", name="throughput_531k")
+    say("throughput recipe 81^3, 4 subcycles, mixed")
+    gpu = run_gpu(cfg, precision=rt.RT_MIXED)
+    ref = oracle.run(cfg)
+    errs = mixed_errors(gpu, ref, cfg["params"]["c_reduced"])
+    for k, v in errs.items():
+        say(f"  {k:16s} {v:.3e}")
+    assert max(errs[f"N[{b}] rel"] for b in range(3)) <= 1e-3
+    assert errs["x_HII abs"] <= 1e-4
+    say(f"  chemistry attempts: gpu {gpu['diag']['substeps']} oracle {ref['diag']['substeps']}")
