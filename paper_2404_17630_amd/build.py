@@ -22,10 +22,6 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 arithmetic instructions in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # FP32 division and square root by the hardware reciprocal and square
-    # root (2.5 and 1 ulp) rather than correctly rounded sequences; only the
-    # mixed form's face physics computes in FP32
-    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wall", "-Wno-unused-result", "-Wno-unused-function",
     f"-I{ROOT / 'include'}", f"-I{CSRC}",
 ]

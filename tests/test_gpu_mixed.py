@@ -94,3 +94,44 @@ def test_mixed_throughput_recipe_at_531k_cells():
     assert max(errs[f"N[{b}] rel"] for b in range(3)) <= 1e-3
     assert errs["x_HII abs"] <= 1e-4
     say(f"  chemistry attempts: gpu {gpu['diag']['substeps']} oracle {ref['diag']['substeps']}")
+
+
+def test_mixed_hhe_2m_full_size():
+    """The mixed form of the 2.1M-cell H+He workload (3 bins, sigma_ln = 1.0,
+    256 sources) at full size: two subcycles against the oracle at the stated
+    bar; then all 50 subcycles against the FP64 form on the GPU (itself held
+    to the oracle at 1e-10 on this workload's first subcycles; an oracle run
+    of 50 subcycles takes minutes), at the stated bar.  The FP64 form
+    started from n_H rounded to FP32 (one FP32 rounding of the input) is run
+    beside it, and printed, as the measure of the workload's own
+    conditioning."""
+    cfg = rtgen.hhe_2m()
+    say("hhe_2m mixed: 2 subcycles against the oracle")
+    gpu2 = run_gpu(cfg, n_sub=2, precision=rt.RT_MIXED)
+    ref2 = oracle.run(cfg, n_sub=2)
+    e2 = mixed_errors(gpu2, ref2, cfg["params"]["c_reduced"])
+    for k, v in e2.items():
+        say(f"  {k:16s} {v:.3e}")
+    assert max(e2[f"N[{b}] rel"] for b in range(3)) <= 1e-3
+    assert e2["x_HII abs"] <= 1e-4
+    say("hhe_2m: 50 subcycles, mixed, fp64, and fp64 from n_H rounded to fp32")
+    mixed = run_gpu(cfg, precision=rt.RT_MIXED)
+    fp64 = run_gpu(cfg, precision=rt.RT_FP64)
+    nh32 = np.asarray(cfg["state"]["n_H"]).astype(np.float32).astype(np.float64)
+    pert = run_gpu(cfg, precision=rt.RT_FP64, n_H=nh32)
+    e50 = mixed_errors(mixed, fp64, cfg["params"]["c_reduced"])
+    c50 = mixed_errors(pert, fp64, cfg["params"]["c_reduced"])
+    for k in e50:
+        say(f"  {k:16s} mixed {e50[k]:.3e}   fp64 from fp32 n_H {c50[k]:.3e}")
+
+    def p999(a, r):
+        out = 0.0
+        for b in range(r["N"].shape[0]):
+            m = r["N"][b] > 1e-10 * r["N"][b].max()
+            out = max(out, float(np.quantile(np.abs(a["N"][b][m] - r["N"][b][m]) / r["N"][b][m], 0.999)))
+        return out
+
+    pm, pc = p999(mixed, fp64), p999(pert, fp64)
+    say(f"  N rel p99.9     mixed {pm:.3e}   fp64 from fp32 n_H {pc:.3e}")
+    assert max(e50[f"N[{b}] rel"] for b in range(3)) <= 1e-3
+    assert e50["x_HII abs"] <= 1e-4
