@@ -92,6 +92,13 @@ double oracle_chi(double f);
 void oracle_hll_flux(const double* UL, const double* UR, const double* n, double c, double* out);
 int oracle_chem_cell(const oracle_params* p, double dt, double n_H, double* N /*[nb]*/,
                      double* Fh /*[nb][3]*/, double* x /*[5]*/, double* T, int64_t* n_attempts);
+/* Rate coefficients and cooling of rate set 1 (Hui & Gnedin 1997, Cen 1992).
+ * Pinned against published atomic data: case-B recombination of H, the
+ * hydrogenic He III recombination, collisional ionisation of H I, He I and
+ * He II, free-free and H I collisional-excitation cooling.  Parity unpinned
+ * (checked only against the 8-cell calculator, which restates the same
+ * fits): He I recombination, dielectronic recombination, and the
+ * recombination, collisional-ionisation and He II excitation cooling terms. */
 void oracle_rates(const oracle_params* p, double T, double* out /*[7]: aHII aHeII aHeIII bHI bHeI bHeII ad*/);
 double oracle_cooling(const oracle_params* p, double T, double n_H, const double* x /*[5]*/);
 

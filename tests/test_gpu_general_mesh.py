@@ -55,7 +55,7 @@ def test_adjoint_on_fourteen_face_cells():
         ref = w @ jv[d]
         got = gq @ dq[d] + gn @ dn[d]
         say(f"bcc direction {d}: adjoint {got:.12e} oracle {ref:.12e}")
-        assert got == pytest.approx(ref, rel=1e-8)
+        assert got == pytest.approx(ref, rel=1e-8, abs=0.0)
 
 
 def test_expanding_hii_ionisation_zones():

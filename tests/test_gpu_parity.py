@@ -24,7 +24,7 @@ def assert_parity(cfg, gpu, ref, tol=TOL):
     assert not bad, bad
     # photon sums per bin
     assert np.allclose(gpu["diag"]["photon_sum"], ref["diag"]["photon_sum"], rtol=1e-12, atol=0)
-    assert gpu["diag"]["dt"] == pytest.approx(ref["diag"]["dt"], rel=1e-14)
+    assert gpu["diag"]["dt"] == pytest.approx(ref["diag"]["dt"], rel=1e-14, abs=0.0)
 
 
 def test_stromgren_fp64_matches_oracle():
