@@ -214,6 +214,26 @@ int rt_state_destroy(rt_state* state);
  * RT_ENUMERIC the state is restored to its value at entry. */
 int rt_subcycle(rt_state* state, int n_subcycles, double dt, void* hip_stream);
 
+/* rt_subcycle for callers that cannot allocate device memory during the call
+ * (code under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as rt_subcycle (bit for
+ * bit), with two differences:
+ *  - the per-workgroup partials, reduction records and diagnostics record
+ *    live in one static device array of RT_NOALLOC_SCRATCH_MB MiB per device
+ *    (held until the process ends) instead of the state's buffers; a state
+ *    whose partials need more (about 3.5 M cells per bin at 16 MiB) is
+ *    RT_EINVAL, and rt_subcycle serves it;
+ *  - no entry copy is kept: on RT_ENUMERIC the state is left as the failing
+ *    subcycle left it (rt_subcycle restores it).
+ * Every call on one device shares that array: calls that overlap on one
+ * device (several host threads, or several streams in flight) race.  The
+ * call synchronises `hip_stream` once at the end, like rt_subcycle.  The
+ * state's fields and its face-state buffer are allocated when it is created
+ * (or switched to the split path by rt_state_set_transport), so the call
+ * allocates nothing; profiling (rt_profile_enable) is ignored for it. */
+#define RT_NOALLOC_SCRATCH_MB 16
+int rt_subcycle_noalloc(rt_state* state, int n_subcycles, double dt, void* hip_stream);
+
 /* Reverse-mode derivative of L(x_HI after n_subcycles from `initial`) given
  * dL/dx_HI [nc] of the final state (host or device):
  *   dL_dlnQ [n_src]  derivative with respect to the log of each source's rate

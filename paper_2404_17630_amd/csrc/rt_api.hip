@@ -39,14 +39,6 @@ int rt_fail(int code, const char* fmt, ...) {
 
 extern "C" const char* rt_last_error(void) { return g_last_error.c_str(); }
 
-#define RT_HIP(expr)                                                                                   \
-    do {                                                                                               \
-        hipError_t e_ = (expr);                                                                        \
-        if (e_ != hipSuccess) {                                                                        \
-            int code_ = (e_ == hipErrorOutOfMemory) ? RT_ENOMEM : RT_EDEVICE;                          \
-            return rt_fail(code_, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
-        }                                                                                              \
-    } while (0)
 
 namespace {
 
@@ -82,18 +74,6 @@ bool finite_all(const std::vector<double>& v) {
     return true;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (dev < 0) return;    // host-only mesh: no device to select
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 constexpr double kBoltzH = 1.380649e-16;
 constexpr double kProtonMassH = 1.67262192369e-24;
@@ -627,11 +607,34 @@ static double pow2_at_least(double m) {
 
 size_t rt_state::tbytes() const { return precision == RT_MIXED ? 4 : 8; }
 
-// The face-state array of the split path, allocated on first use.
+// The face-state array of the split path, allocated when a state is created,
+// cloned or switched to that path.
 int rt_state::ensure_face_states() {
     if (FV.ptr) return RT_OK;
     // face states [nb][n_entries][4], then the cells' N [nb][nc]
     return FV.alloc(((size_t)nb * 4 * mesh->n_entries + (size_t)nb * nc) * tbytes());
+}
+
+static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+size_t rt_partial_bytes(int64_t n_fblk, int64_t n_cblk) {
+    return align256(n_fblk * 8) + align256(5 * n_fblk * 8) + align256(n_fblk * 4) + align256(n_cblk * 8) +
+           align256(n_cblk * 8) + align256(n_cblk * 4) + align256(kReduceBlocks * sizeof(DiagDev)) +
+           align256(sizeof(DiagDev));
+}
+
+PartialBufs rt_partials_at(void* base, int64_t n_fblk, int64_t n_cblk) {
+    char* p = (char*)base;
+    PartialBufs b;
+    b.nv = (double*)p;         p += align256(n_fblk * 8);
+    b.cnt = (int64_t*)p;       p += align256(5 * n_fblk * 8);
+    b.fst = (int32_t*)p;       p += align256(n_fblk * 4);
+    b.csum = (int64_t*)p;      p += align256(n_cblk * 8);
+    b.cmax = (int64_t*)p;      p += align256(n_cblk * 8);
+    b.cst = (int32_t*)p;       p += align256(n_cblk * 4);
+    b.red = (DiagDev*)p;       p += align256(kReduceBlocks * sizeof(DiagDev));
+    b.diag = (DiagDev*)p;
+    return b;
 }
 
 int rt_state::alloc_buffers() {
@@ -642,11 +645,8 @@ int rt_state::alloc_buffers() {
         return rc;
     n_fblk = partial_blocks(nc, nb);
     n_cblk = chem_blocks(nc);
-    if ((rc = part_nv.alloc(n_fblk * 8)) || (rc = part_cnt.alloc(5 * n_fblk * 8)) ||
-        (rc = part_fst.alloc(n_fblk * 4)) || (rc = chem_sum.alloc(n_cblk * 8)) || (rc = chem_max.alloc(n_cblk * 8)) ||
-        (rc = chem_st.alloc(n_cblk * 4)) || (rc = d_diag.alloc(sizeof(DiagDev))) ||
-        (rc = d_red.alloc(kReduceBlocks * sizeof(DiagDev))))
-        return rc;
+    if ((rc = part_mem.alloc(rt_partial_bytes(n_fblk, n_cblk)))) return rc;
+    pb = rt_partials_at(part_mem.ptr, n_fblk, n_cblk);
     RT_HIP(hipHostMalloc((void**)&h_diag, sizeof(DiagDev), hipHostMallocDefault));
     return RT_OK;
 }
@@ -761,7 +761,8 @@ extern "C" int rt_state_create(const rt_mesh* mesh_c, const rt_params* params, i
             s->scale[b] = pow2_at_least(mx);
         }
     }
-    if ((rc = s->alloc_buffers()) || (rc = s->upload_scales()) || (rc = s->upload_sources())) {
+    if ((rc = s->alloc_buffers()) || (rc = s->upload_scales()) || (rc = s->upload_sources()) ||
+        (!s->fused() && (rc = s->ensure_face_states()))) {
         rt_state_destroy(s);
         return rc;
     }
@@ -853,7 +854,8 @@ extern "C" int rt_state_clone(const rt_state* src, rt_state** out) {
     int rc;
     if ((rc = s->alloc_buffers()) || (rc = s->upload_scales()) || (rc = s->upload_sources()) ||
         (rc = copy_dev(s->U[0], src->U[src->cur])) || (rc = copy_dev(s->X, src->X)) ||
-        (rc = copy_dev(s->Ue, src->Ue)) || (rc = copy_dev(s->nH, src->nH))) {
+        (rc = copy_dev(s->Ue, src->Ue)) || (rc = copy_dev(s->nH, src->nH)) ||
+        (!s->fused() && (rc = s->ensure_face_states()))) {
         rt_state_destroy(s);
         return rc;
     }
@@ -946,12 +948,12 @@ void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStr
     s->prof_begin(RT_KERNEL_CHEM, st);
     if (s->precision == RT_MIXED)
         launch_chem<float>((float*)U, X, Ue, (const double*)s->nH.ptr, s->nc, s->cp, dt, (const double*)s->d_scale.ptr,
-                           (const double*)s->d_inv_scale.ptr, (int64_t*)s->chem_sum.ptr, (int64_t*)s->chem_max.ptr,
-                           (int32_t*)s->chem_st.ptr, st);
+                           (const double*)s->d_inv_scale.ptr, s->pb.csum, s->pb.cmax,
+                           s->pb.cst, st);
     else
         launch_chem<double>((double*)U, X, Ue, (const double*)s->nH.ptr, s->nc, s->cp, dt,
                             (const double*)s->d_scale.ptr, (const double*)s->d_inv_scale.ptr,
-                            (int64_t*)s->chem_sum.ptr, (int64_t*)s->chem_max.ptr, (int32_t*)s->chem_st.ptr, st);
+                            s->pb.csum, s->pb.cmax, s->pb.cst, st);
     s->prof_end(st);
 }
 
@@ -974,13 +976,13 @@ void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double d
     if (s->precision == RT_MIXED)
         launch_flux<float>((const float*)U, (const float*)FV, (const float*)FV + nfv, (float*)Un, s->nc, s->nb,
                            s->mesh->n_entries,
-                           geom_view<float>(s->mesh), rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr,
-                           (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
+                           geom_view<float>(s->mesh), rt_sell(s->mesh), cdt, s->pb.nv,
+                           s->pb.cnt, s->pb.fst, st);
     else
         launch_flux<double>((const double*)U, (const double*)FV, (const double*)FV + nfv, (double*)Un, s->nc,
                             s->nb, s->mesh->n_entries,
-                            geom_view<double>(s->mesh), rt_sell(s->mesh), cdt, (double*)s->part_nv.ptr,
-                            (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
+                            geom_view<double>(s->mesh), rt_sell(s->mesh), cdt, s->pb.nv,
+                            s->pb.cnt, s->pb.fst, st);
     s->prof_end(st);
 }
 
@@ -1011,11 +1013,11 @@ void rt_step_transport(rt_state* s, const void* U, void* Un, double dt, hipStrea
     if (s->precision == RT_MIXED)
         launch_transport<float>((const float*)U, (float*)Un, s->nc, s->nb, geom_view<float>(s->mesh),
                                 rt_sell(s->mesh), rt_tiles(s->mesh), lds, s->params.use_limiter, cdt,
-                                (double*)s->part_nv.ptr, (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
+                                s->pb.nv, s->pb.cnt, s->pb.fst, st);
     else
         launch_transport<double>((const double*)U, (double*)Un, s->nc, s->nb, geom_view<double>(s->mesh),
                                  rt_sell(s->mesh), rt_tiles(s->mesh), lds, s->params.use_limiter, cdt,
-                                 (double*)s->part_nv.ptr, (int64_t*)s->part_cnt.ptr, (int32_t*)s->part_fst.ptr, st);
+                                 s->pb.nv, s->pb.cnt, s->pb.fst, st);
     s->prof_end(st);
 }
 
@@ -1044,6 +1046,8 @@ extern "C" int rt_state_set_transport(rt_state* s, int mode) {
         return rt_fail(RT_ESTATE, "fused transport needs %zu bytes of LDS per workgroup, the device has %zu",
                        s->mesh->tile_lds_bytes(s->tbytes()), s->mesh->lds_limit);
     s->transport_mode = mode;
+    DeviceGuard dg(s->mesh->device);
+    if (!s->fused()) return s->ensure_face_states();
     return RT_OK;
 }
 
@@ -1054,58 +1058,50 @@ extern "C" int rt_state_transport(const rt_state* s, int32_t* fused) {
 }
 
 void rt_reset_partials(rt_state* s, hipStream_t st) {
-    fill_words(s->part_cnt.ptr, 5 * s->n_fblk * 2, 0, st);
-    fill_words(s->part_fst.ptr, s->n_fblk, 0, st);
-    fill_words(s->part_nv.ptr, s->n_fblk * 2, 0, st);
-    fill_words(s->chem_sum.ptr, s->n_cblk * 2, 0, st);
-    fill_words(s->chem_max.ptr, s->n_cblk * 2, 0, st);
-    fill_words(s->chem_st.ptr, s->n_cblk, 0, st);
+    fill_words(s->pb.cnt, 5 * s->n_fblk * 2, 0, st);
+    fill_words(s->pb.fst, s->n_fblk, 0, st);
+    fill_words(s->pb.nv, s->n_fblk * 2, 0, st);
+    fill_words(s->pb.csum, s->n_cblk * 2, 0, st);
+    fill_words(s->pb.cmax, s->n_cblk * 2, 0, st);
+    fill_words(s->pb.cst, s->n_cblk, 0, st);
 }
 
 int rt_read_status(rt_state* s, hipStream_t st, int* status) {
-    launch_reduce((const double*)s->part_nv.ptr, (const int64_t*)s->part_cnt.ptr, (const int32_t*)s->part_fst.ptr,
-                  s->n_fblk, s->nb, (const int64_t*)s->chem_sum.ptr, (const int64_t*)s->chem_max.ptr,
-                  (const int32_t*)s->chem_st.ptr, s->n_cblk, (const double*)s->d_nv_scale.ptr, (DiagDev*)s->d_red.ptr,
-                  (DiagDev*)s->d_diag.ptr,
+    launch_reduce(s->pb.nv, s->pb.cnt, s->pb.fst,
+                  s->n_fblk, s->nb, s->pb.csum, s->pb.cmax,
+                  s->pb.cst, s->n_cblk, (const double*)s->d_nv_scale.ptr, s->pb.red,
+                  s->pb.diag,
                   st);
     RT_HIP(hipGetLastError());
-    RT_HIP(hipMemcpyAsync(s->h_diag, s->d_diag.ptr, sizeof(DiagDev), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipMemcpyAsync(s->h_diag, s->pb.diag, sizeof(DiagDev), hipMemcpyDeviceToHost, st));
     RT_HIP(hipStreamSynchronize(st));
     *status = s->h_diag->status;
     return RT_OK;
 }
 
-extern "C" int rt_subcycle(rt_state* s, int n, double dt, void* hip_stream) {
-    if (!s) return rt_fail(RT_EINVAL, "null state");
-    if (n < 0) return rt_fail(RT_EINVAL, "n_subcycles=%d", n);
-    if (!(dt <= 0) && !(dt <= s->dt_cfl)) return rt_fail(RT_EINVAL, "dt=%g above the CFL step %g", dt, s->dt_cfl);
-    if (!std::isfinite(dt)) return rt_fail(RT_EINVAL, "dt=%g", dt);
-    const double step = dt <= 0 ? s->dt_cfl : dt;
-    DeviceGuard dg(s->mesh->device);
-    hipStream_t st = (hipStream_t)hip_stream;
+int rt_subcycle_run(rt_state* s, int n, double step, hipStream_t st, bool rollback) {
     const size_t t = s->tbytes();
     const size_t ubytes = (size_t)s->nb * 4 * s->nc * t;
-    // Entry copy for roll-back on error.
     int rc;
-    if ((!s->bU.ptr && (rc = s->bU.alloc(ubytes))) || (!s->bX.ptr && (rc = s->bX.alloc(5 * s->nc * 8))) ||
-        (!s->bUe.ptr && (rc = s->bUe.alloc(s->nc * 8))))
-        return rc;
     const int cur0 = s->cur;
-    RT_HIP(hipMemcpyAsync(s->bU.ptr, s->U[cur0].ptr, ubytes, hipMemcpyDeviceToDevice, st));
-    RT_HIP(hipMemcpyAsync(s->bX.ptr, s->X.ptr, 5 * s->nc * 8, hipMemcpyDeviceToDevice, st));
-    RT_HIP(hipMemcpyAsync(s->bUe.ptr, s->Ue.ptr, s->nc * 8, hipMemcpyDeviceToDevice, st));
-    if (!s->fused() && (rc = s->ensure_face_states())) return rc;
+    if (rollback) {
+        // Entry copy for roll-back on error.
+        if ((!s->bU.ptr && (rc = s->bU.alloc(ubytes))) || (!s->bX.ptr && (rc = s->bX.alloc(5 * s->nc * 8))) ||
+            (!s->bUe.ptr && (rc = s->bUe.alloc(s->nc * 8))))
+            return rc;
+        RT_HIP(hipMemcpyAsync(s->bU.ptr, s->U[cur0].ptr, ubytes, hipMemcpyDeviceToDevice, st));
+        RT_HIP(hipMemcpyAsync(s->bX.ptr, s->X.ptr, 5 * s->nc * 8, hipMemcpyDeviceToDevice, st));
+        RT_HIP(hipMemcpyAsync(s->bUe.ptr, s->Ue.ptr, s->nc * 8, hipMemcpyDeviceToDevice, st));
+    }
+    if (!s->fused() && !s->FV.ptr) return rt_fail(RT_ESTATE, "the split transport path has no face-state buffer");
     rt_reset_partials(s, st);
     rt_run_subcycles(s, n, step, st);
     s->prof_begin(RT_KERNEL_REDUCE, st);
-    launch_reduce((const double*)s->part_nv.ptr, (const int64_t*)s->part_cnt.ptr, (const int32_t*)s->part_fst.ptr,
-                  s->n_fblk, s->nb, (const int64_t*)s->chem_sum.ptr, (const int64_t*)s->chem_max.ptr,
-                  (const int32_t*)s->chem_st.ptr, s->n_cblk, (const double*)s->d_nv_scale.ptr, (DiagDev*)s->d_red.ptr,
-                  (DiagDev*)s->d_diag.ptr,
-                  st);
+    launch_reduce(s->pb.nv, s->pb.cnt, s->pb.fst, s->n_fblk, s->nb, s->pb.csum, s->pb.cmax, s->pb.cst, s->n_cblk,
+                  (const double*)s->d_nv_scale.ptr, s->pb.red, s->pb.diag, st);
     s->prof_end(st);
     RT_HIP(hipGetLastError());
-    RT_HIP(hipMemcpyAsync(s->h_diag, s->d_diag.ptr, sizeof(DiagDev), hipMemcpyDeviceToHost, st));
+    RT_HIP(hipMemcpyAsync(s->h_diag, s->pb.diag, sizeof(DiagDev), hipMemcpyDeviceToHost, st));
     RT_HIP(hipStreamSynchronize(st));
     if ((rc = s->prof_collect())) return rc;
     const DiagDev& d = *s->h_diag;
@@ -1121,16 +1117,30 @@ extern "C" int rt_subcycle(rt_state* s, int n, double dt, void* hip_stream) {
     o.status = d.status;
     o.n_subcycles = n;
     if (n > 0 && d.status != 0) {
+        const char* what = (d.status & 1) ? ((d.status & 2) ? "non-finite value, chemistry substep cap"
+                                                             : "non-finite value")
+                                          : "chemistry substep cap";
+        if (!rollback) return rt_fail(RT_ENUMERIC, "subcycle status 0x%x (%s); state not restored", d.status, what);
         // Roll back to the entry state.
         s->cur = cur0;
         RT_HIP(hipMemcpyAsync(s->U[cur0].ptr, s->bU.ptr, ubytes, hipMemcpyDeviceToDevice, st));
         RT_HIP(hipMemcpyAsync(s->X.ptr, s->bX.ptr, 5 * s->nc * 8, hipMemcpyDeviceToDevice, st));
         RT_HIP(hipMemcpyAsync(s->Ue.ptr, s->bUe.ptr, s->nc * 8, hipMemcpyDeviceToDevice, st));
         RT_HIP(hipStreamSynchronize(st));
-        return rt_fail(RT_ENUMERIC, "subcycle status 0x%x (%s%s); state restored", d.status,
-                       (d.status & 1) ? "non-finite value " : "", (d.status & 2) ? "chemistry substep cap" : "");
+        return rt_fail(RT_ENUMERIC, "subcycle status 0x%x (%s); state restored", d.status, what);
     }
     return RT_OK;
+}
+
+extern "C" int rt_subcycle(rt_state* s, int n, double dt, void* hip_stream) {
+    if (!s) return rt_fail(RT_EINVAL, "null state");
+    if (n < 0) return rt_fail(RT_EINVAL, "n_subcycles=%d", n);
+    if (!(dt <= 0) && !(dt <= s->dt_cfl)) return rt_fail(RT_EINVAL, "dt=%g above the CFL step %g", dt, s->dt_cfl);
+    if (!std::isfinite(dt)) return rt_fail(RT_EINVAL, "dt=%g", dt);
+    DeviceGuard dg(s->mesh->device);
+    int rc;
+    if (!s->fused() && (rc = s->ensure_face_states())) return rc;
+    return rt_subcycle_run(s, n, dt <= 0 ? s->dt_cfl : dt, (hipStream_t)hip_stream, true);
 }
 
 // ---------------------------------------------------------------------------

@@ -15,6 +15,30 @@
 // Sets the thread-local error message and returns `code`.
 int rt_fail(int code, const char* fmt, ...);
 
+// Return RT_ENOMEM or RT_EDEVICE with a message when a HIP call fails.
+#define RT_HIP(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) {                                                                        \
+            int code_ = (e_ == hipErrorOutOfMemory) ? RT_ENOMEM : RT_EDEVICE;                          \
+            return rt_fail(code_, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+        }                                                                                              \
+    } while (0)
+
+// Makes `dev` the current device for a scope and restores the previous one.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (dev < 0) return;    // host-only mesh: no device to select
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
 // Owning device allocation.
 struct DevMem {
     void* ptr = nullptr;
@@ -64,6 +88,25 @@ struct rt_mesh {
 
 void rt_mesh_release(rt_mesh* m);
 
+// Where the kernels of a call write their per-block partials and the
+// diagnostics record: normally the state's own buffers; rt_subcycle_noalloc
+// points them into its static device array for the duration of its call.
+struct PartialBufs {
+    double* nv = nullptr;          // [n_fblk] photon sums of the flux workgroups
+    int64_t* cnt = nullptr;        // [5][n_fblk] admissibility, cap and guard counts
+    int32_t* fst = nullptr;        // [n_fblk] status bits of the flux workgroups
+    int64_t* csum = nullptr;       // [n_cblk] chemistry attempts
+    int64_t* cmax = nullptr;       // [n_cblk] largest attempts of one cell
+    int32_t* cst = nullptr;        // [n_cblk] status bits of the chemistry workgroups
+    rtk::DiagDev* red = nullptr;   // [kReduceBlocks] first-stage reduction records
+    rtk::DiagDev* diag = nullptr;  // the folded diagnostics record
+};
+// Bytes of the partials above for n_fblk flux and n_cblk chemistry
+// workgroups, each array starting on a 256-byte boundary.
+size_t rt_partial_bytes(int64_t n_fblk, int64_t n_cblk);
+// Carve the partials out of `base` (rt_partial_bytes bytes, 256-byte aligned).
+PartialBufs rt_partials_at(void* base, int64_t n_fblk, int64_t n_cblk);
+
 struct rt_state {
     rt_mesh* mesh = nullptr;
     rt_params params{};
@@ -94,8 +137,8 @@ struct rt_state {
 
     // Per-block partials and the diagnostics record.
     int64_t n_fblk = 0, n_cblk = 0;
-    DevMem part_nv, part_cnt, part_fst, chem_sum, chem_max, chem_st, d_diag;
-    DevMem d_red;                // first-stage records of the reduction [kReduceBlocks]
+    DevMem part_mem;             // the state's own partials (rt_partial_bytes)
+    PartialBufs pb;              // the buffers the kernels use (part_mem unless redirected)
     rtk::DiagDev* h_diag = nullptr;
     rt_diag diag{};
 
@@ -138,3 +181,9 @@ void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st);
 void rt_reset_partials(rt_state* s, hipStream_t st);
 // Folds the partials and returns the status word (synchronises the stream).
 int rt_read_status(rt_state* s, hipStream_t st, int* status);
+// Body of rt_subcycle after argument checks: n subcycles of length `step`,
+// the diagnostics fold and read-back into s->diag.  With `rollback` the
+// fields are copied at entry (into buffers the state allocates on first use)
+// and restored on RT_ENUMERIC; without it nothing is allocated and a failed
+// call leaves the state as the failing subcycle left it.
+int rt_subcycle_run(rt_state* s, int n, double step, hipStream_t st, bool rollback);

@@ -28,6 +28,7 @@ KERNEL_NAMES = ("k_sources", "k_chem", "k_facestate", "k_flux", "k_reduce", "k_t
 RT_TRANSPORT_AUTO, RT_TRANSPORT_FUSED, RT_TRANSPORT_SPLIT = 0, 1, 2
 RT_DEVICE_HOST_ONLY = -1
 RT_TILE_CELLS = 256
+RT_NOALLOC_SCRATCH_MB = 16
 TABLES = ("nbr", "fsf", "opp", "sptr", "sdeg", "lds_opp", "halo_ptr", "halo_cell", "hside_ptr", "hside_entry")
 
 ERROR_NAMES = {RT_EINVAL: "RT_EINVAL", RT_EMESH: "RT_EMESH", RT_ESTATE: "RT_ESTATE", RT_EDEVICE: "RT_EDEVICE",
@@ -77,6 +78,7 @@ _SIGNATURES = [
     ("rt_state_clone", C.c_int, [_vp, C.POINTER(_vp)]),
     ("rt_state_destroy", C.c_int, [_vp]),
     ("rt_subcycle", C.c_int, [_vp, C.c_int, C.c_double, _vp]),
+    ("rt_subcycle_noalloc", C.c_int, [_vp, C.c_int, C.c_double, _vp]),
     ("rt_subcycle_adjoint", C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     ("rt_state_get_field", C.c_int, [_vp, C.c_int, _vp, C.c_int]),
     ("rt_state_set_field", C.c_int, [_vp, C.c_int, _vp, C.c_int]),
@@ -196,6 +198,10 @@ def rt_state_destroy(state):
 
 def rt_subcycle(state, n_subcycles: int, dt: float = 0.0, stream=None):
     _check(lib().rt_subcycle(state, int(n_subcycles), float(dt), _stream_ptr(stream)))
+
+
+def rt_subcycle_noalloc(state, n_subcycles: int, dt: float = 0.0, stream=None):
+    _check(lib().rt_subcycle_noalloc(state, int(n_subcycles), float(dt), _stream_ptr(stream)))
 
 
 def rt_subcycle_adjoint(initial, n_subcycles: int, checkpoint_every: int, dL_dxHI_final, dL_dlnQ, dL_dln_nH,
