@@ -221,8 +221,8 @@ int rt_subcycle(rt_state* state, int n_subcycles, double dt, void* hip_stream);
  *  - the per-workgroup partials, reduction records and diagnostics record
  *    live in one static device array of RT_NOALLOC_SCRATCH_MB MiB per device
  *    (held until the process ends) instead of the state's buffers; a state
- *    whose partials need more (about 3.5 M cells per bin at 16 MiB) is
- *    RT_EINVAL, and rt_subcycle serves it;
+ *    whose partials need more (52 bytes per 64 cells and bin: about 80 M
+ *    cells x bins at 64 MiB) is RT_EINVAL, and rt_subcycle serves it;
  *  - no entry copy is kept: on RT_ENUMERIC the state is left as the failing
  *    subcycle left it (rt_subcycle restores it).
  * Every call on one device shares that array: calls that overlap on one
@@ -231,7 +231,7 @@ int rt_subcycle(rt_state* state, int n_subcycles, double dt, void* hip_stream);
  * state's fields and its face-state buffer are allocated when it is created
  * (or switched to the split path by rt_state_set_transport), so the call
  * allocates nothing; profiling (rt_profile_enable) is ignored for it. */
-#define RT_NOALLOC_SCRATCH_MB 16
+#define RT_NOALLOC_SCRATCH_MB 64
 int rt_subcycle_noalloc(rt_state* state, int n_subcycles, double dt, void* hip_stream);
 
 /* Reverse-mode derivative of L(x_HI after n_subcycles from `initial`) given

@@ -111,10 +111,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_guard(const double* __restrict__
     load4(U + urec(b, nc, i), ui);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int c0 = 0, c1 = 0, c2 = 0;
-    // the cells' N follow the face states in FV
+    // the cells' cap numerators N V / n_faces follow the face states in FV
     const GlobalFaceStates<double> fsv{FV + (int64_t)b * n_entries * 4, sell.opp,
                                        FV + (int64_t)nb * n_entries * 4 + (int64_t)b * nc};
-    cell_flux_sum_s<double, double, 0>(i, b, nc, U, fsv, geo, sell, cdt, ui[0], acc, c0, c1, c2);
+    cell_flux_sum_s<double, double, 0>(i, b, nc, U, fsv, geo, sell, cdt, fsv.cellN((int32_t)i), acc, c0, c1, c2);
     const double coef = cdt / geo.cell[i * kCellRec + 6];
     Dual<4> un[4];
 #pragma unroll

@@ -144,6 +144,8 @@ static double min_image(double x, double box) {
     return x;
 }
 
+static int upload_volumes(rt_mesh* m, bool fp32);
+
 int rt_mesh::build_float_geometry() {
     if (geo32_ready) return RT_OK;
     std::vector<float> f(face.size()), c(cell.size());
@@ -152,6 +154,7 @@ int rt_mesh::build_float_geometry() {
     int rc;
     if ((rc = d_face32.upload(f.data(), f.size() * 4))) return rc;
     if ((rc = d_cell32.upload(c.data(), c.size() * 4))) return rc;
+    if ((rc = upload_volumes(this, true))) return rc;
     geo32_ready = true;
     return RT_OK;
 }
@@ -256,12 +259,23 @@ int rt_mesh::build_side_geometry(size_t tbytes) {
 // (nbr, opp for an L side or ~opp for an R side) of every sliced-ELL entry
 // as one 8-byte record.
 static int upload_packed_index(rt_mesh* m) {
-    std::vector<int32_t> p((size_t)2 * m->n_entries, 0);
+    std::vector<int32_t> p((size_t)2 * m->n_entries, 0), q((size_t)m->n_entries, 0);
     for (int64_t e = 0; e < m->n_entries; ++e) {
         p[2 * e] = m->nbr[e];
         p[2 * e + 1] = m->nbr[e] < 0 ? 0 : (m->fsf[e] >= 0 ? m->opp[e] : ~m->opp[e]);
+        q[e] = m->nbr[e] < 0 ? INT32_MIN : p[2 * e + 1];
     }
-    return m->d_idx.upload(p.data(), p.size() * 4);
+    int rc = m->d_idx.upload(p.data(), p.size() * 4);
+    return rc ? rc : m->d_ops.upload(q.data(), q.size() * 4);
+}
+
+// The cells' V (units of h_ref^3) as one array per precision.
+static int upload_volumes(rt_mesh* m, bool fp32) {
+    std::vector<double> v(m->nc);
+    for (int64_t i = 0; i < m->nc; ++i) v[i] = m->cell[(size_t)i * kCellRec + 6];
+    if (!fp32) return m->d_vol64.upload(v.data(), v.size() * 8);
+    std::vector<float> f(v.begin(), v.end());
+    return m->d_vol32.upload(f.data(), f.size() * 4);
 }
 
 extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const double* centre, int64_t n_faces,
@@ -467,7 +481,7 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
     DeviceGuard dg(device);
 
     if ((rc = m->d_face64.upload(m->face.data(), m->face.size() * 8)) ||
-        (rc = m->d_cell64.upload(m->cell.data(), m->cell.size() * 8)) ||
+        (rc = m->d_cell64.upload(m->cell.data(), m->cell.size() * 8)) || (rc = upload_volumes(m, false)) ||
         (rc = m->d_vphys.upload(m->vphys.data(), m->vphys.size() * 8)) ||
         (rc = m->d_nbr.upload(m->nbr.data(), m->nbr.size() * 4)) ||
         (rc = m->d_fsf.upload(m->fsf.data(), m->fsf.size() * 4)) ||
@@ -611,7 +625,7 @@ size_t rt_state::tbytes() const { return precision == RT_MIXED ? 4 : 8; }
 // cloned or switched to that path.
 int rt_state::ensure_face_states() {
     if (FV.ptr) return RT_OK;
-    // face states [nb][n_entries][4], then the cells' N [nb][nc]
+    // face states [nb][n_entries][4], then the cells' cap numerators N V / n_faces [nb][nc]
     return FV.alloc(((size_t)nb * 4 * mesh->n_entries + (size_t)nb * nc) * tbytes());
 }
 
@@ -914,6 +928,7 @@ static GeomView<T> geom_view(const rt_mesh* m) {
         geo.cell = (const T*)m->d_cell32.ptr;
     }
     geo.side = (const T*)(sizeof(T) == 8 ? m->d_side64.ptr : m->d_side32.ptr);
+    geo.vol = (const T*)(sizeof(T) == 8 ? m->d_vol64.ptr : m->d_vol32.ptr);
     geo.nf = m->nf;
     geo.ne = m->n_entries;
     return geo;
@@ -924,7 +939,7 @@ GeomView<double> rt_geo64(const rt_mesh* m) { return geom_view<double>(m); }
 SellView rt_sell(const rt_mesh* m) {
     return SellView{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_opp.ptr,
                     (const int32_t*)m->d_sptr.ptr, (const int32_t*)m->d_sdeg.ptr, (const int2*)m->d_idx.ptr,
-                    m->uniform_deg};
+                    (const int32_t*)m->d_ops.ptr, m->uniform_deg};
 }
 
 // One piece of a subcycle on explicit buffers (U, G in the state's precision).
@@ -959,7 +974,7 @@ void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStr
 
 void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st) {
     s->prof_begin(RT_KERNEL_GRADIENT, st);
-    const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;   // the cells' N follow the face states
+    const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;   // the cells' cap numerators follow the face states
     if (s->precision == RT_MIXED)
         launch_facestate<float>((const float*)U, (float*)FV, (float*)FV + nfv, s->nc, s->nb, s->mesh->n_entries,
                                 geom_view<float>(s->mesh), rt_sell(s->mesh), s->params.use_limiter, st);

@@ -26,6 +26,7 @@ constexpr double kCapNoise = 1.0e-12;
 
 template <typename R, typename G>
 __device__ inline void make_admissible(R* U, int& cN, int& cF) {
+#pragma clang fp contract(off)
     if (val(U[0]) < 0) { U[0] = R(G(0)); ++cN; }
     const R F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
     if (val(F2) > val(U[0] * U[0])) {
@@ -42,6 +43,7 @@ __device__ inline void make_admissible(R* U, int& cN, int& cF) {
 // N D n for state U = (N, Fh).
 template <typename R, typename G>
 __device__ inline void radiation_pressure_n(const R* U, G n0, G n1, G n2, R* P) {
+#pragma clang fp contract(off)
     const R N = U[0];
     const R F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
     // Isotropic when f = |Fh|/N <= 1e-8: the anisotropic part of D is
@@ -72,6 +74,7 @@ __device__ inline void radiation_pressure_n(const R* U, G n0, G n1, G n2, R* P) 
 
 template <typename R, typename G>
 __device__ inline void hll_flux(const R* UL, const R* UR, G n0, G n1, G n2, R* Phi) {
+#pragma clang fp contract(off)
     R PL[3], PR[3];
     radiation_pressure_n<R, G>(UL, n0, n1, n2, PL);
     radiation_pressure_n<R, G>(UR, n0, n1, n2, PR);
@@ -83,12 +86,17 @@ __device__ inline void hll_flux(const R* UL, const R* UR, G n0, G n1, G n2, R* P
     Phi[3] = G(0.5) * (PL[2] + PR[2]) - G(0.5) * (UR[3] - UL[3]);
 }
 
+// The face physics is evaluated without contracting products into fused
+// multiply-adds, so every kernel that inlines it (the split and fused
+// transport, the adjoint) rounds a face's flux the same way.
+
 // Full face flux from the raw extrapolated states sL, sR (modified in place
 // by the admissibility fix) and the cell averages NL, NR of the two cells.
 // vcL, vcR = V / n_faces of the cells; cdt = c~ dt / h.  Returns capped.
 template <typename R, typename G>
 __device__ inline bool face_flux(R* sL, R* sR, const R& NL, const R& NR, G vcL, G vcR, G n0, G n1, G n2, G A,
                                  G cdt, R* Phi, int& aN, int& aF) {
+#pragma clang fp contract(off)
     make_admissible<R, G>(sL, aN, aF);
     make_admissible<R, G>(sR, aN, aF);
     hll_flux<R, G>(sL, sR, n0, n1, n2, Phi);

@@ -72,7 +72,8 @@ struct rt_mesh {
     bool geo32_ready = false;
     DevMem d_side32, d_side64;   // per face side records (rtk::SideComp), built on first use
     int32_t uniform_deg = 0;     // rtk::SellView::uniform_deg
-    DevMem d_nbr, d_fsf, d_opp, d_sptr, d_sdeg, d_idx;
+    DevMem d_nbr, d_fsf, d_opp, d_sptr, d_sdeg, d_idx, d_ops;
+    DevMem d_vol32, d_vol64;     // [nc] V in units of h_ref^3
     // Tiles of the fused transport kernel (rtk::TileView).
     std::vector<int32_t> lds_opp, halo_ptr, halo_cell, hside_ptr, hside_entry;
     int64_t tile_max_sides = 0;  // largest tile + halo side count
@@ -118,9 +119,9 @@ struct rt_state {
     double dt_cfl = 0.0;
 
     // Fields: U[b][nc][4] = (N, Fh_x, Fh_y, Fh_z) / scale_b in the transport
-    // precision, double-buffered; face states FV[b][entry][4] followed by a
-    // copy of the cells' N [b][nc] (split path only, allocated on first
-    // use); chemistry FP64.
+    // precision, double-buffered; face states FV[b][entry][4] followed by
+    // the cells' cap numerators N V / n_faces [b][nc] (split path only,
+    // allocated with the state); chemistry FP64.
     DevMem U[2];
     int cur = 0;
     DevMem FV;

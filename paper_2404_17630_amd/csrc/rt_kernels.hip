@@ -249,9 +249,11 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
 // k_facestate: limited gradients of N, Fh_x, Fh_y, Fh_z of one bin in FP64
 // (Sec. 2.3.2), then the extrapolated state U_i + g . r_if at each face
 // centre (Sec. 2.3.3), stored in the transport precision as one record per
-// face side: FV[b][e][4].  Keeping g in registers means a limited face
-// state is rounded once, relative to its own size (an FP32-stored gradient
-// would cancel at steep fronts, where U + g.r is much smaller than U).
+// face side: FV[b][e][4]; and the numerator N V / n_faces of the cell's
+// outflow cap, NC[b][nc], for the flux kernel.  Keeping g in registers
+// means a limited face state is rounded once, relative to its own size (an
+// FP32-stored gradient would cancel at steep fronts, where U + g.r is much
+// smaller than U).
 // ---------------------------------------------------------------------------
 
 // Store the limited state of cell i at each of its faces: entry e goes to
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T
         const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
         double ui[4], g[4][3];
         limited_gradient_c<T, DEG>(i, b, nc, U, cell, cs, use_limiter, ui, g);
-        NC[(int64_t)b * nc + i] = (T)ui[0];
+        NC[(int64_t)b * nc + i] = (T)ui[0] * cell[7];
         T* FVb = FV + (int64_t)b * n_entries * 4;
 #pragma unroll
         for (int k = 0; k < DEG; ++k) {
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_facestate(const T* __restrict__ U, T
         T rr[SlotCount<DEG>::kMax][3];
         bool ok[SlotCount<DEG>::kMax];
         limited_gradient_s<T, DEG>(i, b, nc, U, geo, sell, use_limiter, ui, g, rr, ok);
-        NC[(int64_t)b * nc + i] = (T)ui[0];
+        NC[(int64_t)b * nc + i] = (T)ui[0] * geo.cell[i * kCellRec + 7];
         export_face_states<T, DEG>(i, ui, g, rr, ok, geo, sell, FV + (int64_t)b * n_entries * 4, 0);
     }
 }
@@ -353,11 +355,14 @@ __global__ __launch_bounds__(kBlock) void k_gradient(const double* __restrict__ 
 
 // Divergence update of cell i from its flux sum, post-update guards and the
 // new record; adds the cell's N V, guard counts and status to the thread's.
+// Divergence update of cell i (volume vol_t) from its flux sum, post-update
+// guards and the new record; adds the cell's N V, guard counts and status to
+// the thread's.  Not contracted, so the split and fused paths round it alike.
 template <typename T, typename TA>
-__device__ inline void update_cell(int64_t i, int b, int64_t nc, const T* ui, const double* acc, TA cdt,
-                                   const GeomView<T>& geo, T* __restrict__ Unew, double& nv, int& cGN, int& cGF,
-                                   int& status) {
-    const double vol = (double)geo.cell[i * kCellRec + 6];
+__device__ inline void update_cell_v(int64_t i, int b, int64_t nc, const T* ui, T vol_t, const double* acc, TA cdt,
+                                     T* __restrict__ Unew, double& nv, int& cGN, int& cGF, int& status) {
+#pragma clang fp contract(off)
+    const double vol = (double)vol_t;
     const double coef = (double)cdt / vol;
     double un[4];
 #pragma unroll
@@ -371,6 +376,48 @@ __device__ inline void update_cell(int64_t i, int b, int64_t nc, const T* ui, co
     }
     store4(Unew + urec(b, nc, i), o);
     nv += (double)o[0] * vol;
+}
+
+template <typename T, typename TA>
+__device__ inline void update_cell(int64_t i, int b, int64_t nc, const T* ui, const double* acc, TA cdt,
+                                   const GeomView<T>& geo, T* __restrict__ Unew, double& nv, int& cGN, int& cGF,
+                                   int& status) {
+    update_cell_v<T, TA>(i, b, nc, ui, geo.cell[i * kCellRec + 6], acc, cdt, Unew, nv, cGN, cGF, status);
+}
+
+// Adds a workgroup's counts to its partial slots, accumulated across the
+// subcycles of one call.  Integer sums do not depend on order, so the adds
+// are atomics whose results are not waited for (a load and a store per
+// counter would hold the wavefront for a memory round trip each); zero
+// counts, the common case, are skipped.
+__device__ inline void add_counts(int64_t* __restrict__ part_cnt, int64_t n_blocks, int64_t blk, int64_t c0, int64_t c1,
+                                  int64_t c2, int64_t c3, int64_t c4, int32_t status,
+                                  int32_t* __restrict__ part_status) {
+    const int64_t c[5] = {c0, c1, c2, c3, c4};
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+        if (c[q] != 0) atomicAdd(reinterpret_cast<unsigned long long*>(part_cnt + q * n_blocks + blk),
+                                 (unsigned long long)c[q]);
+    if (status != 0) atomicOr(part_status + blk, status);
+}
+
+// The partials of a workgroup whose cells are one wavefront (the
+// slot-parallel flux kernel): shuffle sums and ballots, no barrier; lane 0
+// writes them.
+__device__ inline void wave_partials(double nv, int cAdmN, int cAdmF, int cCap, int cGN, int cGF, int status,
+                                     int64_t blk, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
+                                     int32_t* __restrict__ part_status, int64_t n_blocks) {
+    const uint64_t packed = (uint64_t)cAdmN | ((uint64_t)cAdmF << 21) | ((uint64_t)cCap << 42);
+    const double snv = wave_sum(nv);
+    const uint64_t spk = wave_sum(packed);
+    const uint64_t bGN = __ballot(cGN != 0), bGF = __ballot(cGF != 0), bST = __ballot(status != 0);
+    if ((threadIdx.x & 63) == 0) {
+        constexpr uint64_t kField = (1ull << 21) - 1;
+        part_nv[blk] = snv;
+        add_counts(part_cnt, n_blocks, blk, (int64_t)(spk & kField), (int64_t)((spk >> 21) & kField),
+                   (int64_t)((spk >> 42) & kField), (int64_t)__popcll(bGN), (int64_t)__popcll(bGF),
+                   bST != 0 ? 1 : 0, part_status);
+    }
 }
 
 // The block's partials (sum N V of this bin, counters, status), accumulated
@@ -414,12 +461,8 @@ __device__ inline void block_partials(double nv, int cAdmN, int cAdmF, int cCap,
         }
         constexpr uint64_t kField = (1ull << 21) - 1;
         part_nv[blk] = sn;
-        part_cnt[0 * n_blocks + blk] += (int64_t)(sc & kField);
-        part_cnt[1 * n_blocks + blk] += (int64_t)((sc >> 21) & kField);
-        part_cnt[2 * n_blocks + blk] += (int64_t)((sc >> 42) & kField);
-        part_cnt[3 * n_blocks + blk] += g0;
-        part_cnt[4 * n_blocks + blk] += g1;
-        part_status[blk] |= (int32_t)st;
+        add_counts(part_cnt, n_blocks, blk, (int64_t)(sc & kField), (int64_t)((sc >> 21) & kField),
+                   (int64_t)((sc >> 42) & kField), g0, g1, (int32_t)st, part_status);
     }
 }
 
@@ -434,45 +477,125 @@ __device__ inline void finish_cell(int64_t i, int b, int64_t nc, const T* ui, co
     block_partials<NT>(nv, cAdmN, cAdmF, cCap, cGN, cGF, status, blk, part_nv, part_cnt, part_status, n_blocks);
 }
 
-template <typename T, typename TA, int DEG>
+// General meshes (any degree): one lane per (cell, bin), the cell's slots in
+// a loop.
+template <typename T, typename TA>
 __global__ __launch_bounds__(kFluxBlock) void k_flux(const T* __restrict__ U, const T* __restrict__ FV,
                                                  const T* __restrict__ NC, T* __restrict__ Unew,
                                                  int64_t nc, int nb, int64_t n_entries, GeomView<T> geo, SellView sell,
                                                  TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
                                                  int32_t* __restrict__ part_status, int64_t n_blocks) {
     const int64_t blk = xcd_logical_block();
-    if constexpr (DEG > 0) {
-        // One lane per (cell, bin); the geometry of the three or more bins of
-        // a tile is read by neighbouring workgroups on the same XCD.
-        const int b = (int)(blk % nb);
-        const int64_t i = (blk / nb) * kFluxBlock + threadIdx.x;
-        int cAdmN = 0, cAdmF = 0, cCap = 0;
-        T ui[4] = {0, 0, 0, 0};
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        if (i < nc) {
-            CellFaces<T, DEG> cf;
-            load_cell_faces<T, DEG>(i, geo, sell, cf);
-            load4(U + urec(b, nc, i), ui);
-            const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp, NC + (int64_t)b * nc};
-            cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, (int64_t)sell.ptr[i / kSlice] + (i % kSlice), cf, cdt,
-                                        (TA)ui[0], acc, cAdmN, cAdmF, cCap);
-        }
-        finish_cell<T, TA, kFluxBlock>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
-                           part_status, n_blocks);
-    } else {
-        const int b = (int)(blk % nb);
-        const int64_t i = (blk / nb) * kFluxBlock + threadIdx.x;
-        int cAdmN = 0, cAdmF = 0, cCap = 0;
-        T ui[4] = {0, 0, 0, 0};
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        if (i < nc) {
-            load4(U + urec(b, nc, i), ui);
-            const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp, NC + (int64_t)b * nc};
-            cell_flux_sum_s<T, TA, DEG>(i, b, nc, U, fsv, geo, sell, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap);
-        }
-        finish_cell<T, TA, kFluxBlock>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
-                           part_status, n_blocks);
+    const int b = (int)(blk % nb);
+    const int64_t i = (blk / nb) * kFluxBlock + threadIdx.x;
+    int cAdmN = 0, cAdmF = 0, cCap = 0;
+    T ui[4] = {0, 0, 0, 0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < nc) {
+        load4(U + urec(b, nc, i), ui);
+        const GlobalFaceStates<T> fsv{FV + (int64_t)b * n_entries * 4, sell.opp, NC + (int64_t)b * nc};
+        cell_flux_sum_s<T, TA, 0>(i, b, nc, U, fsv, geo, sell, cdt, (TA)fsv.cellN((int32_t)i), acc, cAdmN, cAdmF,
+                                  cCap);
     }
+    finish_cell<T, TA, kFluxBlock>(i, b, nc, ui, acc, cdt, geo, Unew, cAdmN, cAdmF, cCap, blk, part_nv, part_cnt,
+                                   part_status, n_blocks);
+}
+
+// Meshes whose slices all have DEG slots: one workgroup per (64-cell slice,
+// bin) with one wavefront per slot, so every lane computes one face flux and
+// the gathers of a cell's faces are in flight together in DEG wavefronts
+// instead of one after the other in one lane.  Each lane's only dependent
+// loads are the opposite face state and the neighbour's N, behind its own
+// 8-byte index record.  The products sigma A Phi go through LDS; after one
+// barrier the first wavefront adds each cell's slots in slot (face-index)
+// order in FP64, exactly as the one-lane form does, and updates the cell.
+template <typename T, typename TA, int DEG>
+__global__ __launch_bounds__(DEG * kSlice) void k_flux_slots(const T* __restrict__ U, const T* __restrict__ FV,
+                                                             const T* __restrict__ NC, T* __restrict__ Unew,
+                                                             int64_t nc, int nb, int64_t n_entries, GeomView<T> geo,
+                                                             SellView sell, TA cdt, double* __restrict__ part_nv,
+                                                             int64_t* __restrict__ part_cnt,
+                                                             int32_t* __restrict__ part_status, int64_t n_blocks) {
+    static_assert(DEG > 0 && DEG * kSlice <= 1024, "one wavefront per slot");
+    __shared__ TA lflux[DEG][4][kSlice];
+    __shared__ uint8_t lcnt[DEG][kSlice];   // bit 7: a face; bits 0-1, 2-3, 4: admissibility N, F, cap (L side)
+    const uint32_t blk32 = xcd_logical_block32();
+    const int64_t blk = blk32;
+    const int b = (int)(blk32 % (uint32_t)nb);
+    const int64_t sl = blk32 / (uint32_t)nb;
+    const int k = threadIdx.x / kSlice;
+    const int l = threadIdx.x % kSlice;
+    const int64_t i = sl * kSlice + l;
+    const int64_t ic = i < nc ? i : nc - 1;
+    const int64_t e = (sl * DEG + k) * kSlice + l;     // every slice has DEG slots
+    const T* FVb = FV + (int64_t)b * n_entries * 4;
+    const T* NCb = NC + (int64_t)b * nc;
+    // The first wavefront also updates the slice's cells.  Every wavefront
+    // requests the cell's record and volume with the rest (under a branch
+    // on the wavefront they would be waited for at once; the other five
+    // find them in the cache), and everything of the own entry before the
+    // index is used.  The flux is evaluated on every lane, a padding entry's
+    // result being discarded, so that no load waits behind a branch on the
+    // index (a padding entry reads zeros, its own unused face-state slot and
+    // cell 0).  The neighbour follows from its entry: slot k' of lane l' of
+    // slice s' is entry (s' DEG + k') 64 + l'.
+    const int32_t os = sell.ops[e];
+    T ga[4], so[4], sn[4];
+    load4(geo.sg(3, e), ga);
+    load4(FVb + e * 4, so);
+    const TA Ni = (TA)NCb[ic];
+    const TA A = (TA)ga[0];
+    const bool face = os != INT32_MIN;
+    const bool isL = os >= 0;
+    const int64_t eo = face ? (int64_t)(isL ? os : ~os) : e;
+    const int64_t j = face ? (eo / (DEG * kSlice)) * kSlice + eo % kSlice : 0;
+    const T nj = NCb[j];
+    load4(FVb + eo * 4, sn);
+    const TA Nj = (TA)nj;
+    T ui[4];
+    load4(U + urec(b, nc, ic), ui);
+    const T vol = geo.vol[ic];
+    // all loads are issued before any arithmetic that waits for one
+    __builtin_amdgcn_sched_barrier(0);
+    TA sL[4], sR[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        sL[v] = (TA)(isL ? so[v] : sn[v]);
+        sR[v] = (TA)(isL ? sn[v] : so[v]);
+    }
+    const TA NL = isL ? Ni : Nj, NR = isL ? Nj : Ni;   // cap numerators N V / n_faces
+    int aN = 0, aF = 0;
+    TA Phi[4];
+    const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)1, (TA)1, (TA)ga[1], (TA)ga[2], (TA)ga[3], A, cdt, Phi,
+                                         aN, aF);
+    const TA sA = isL ? A : -A;
+    TA ph[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ph[v] = face ? mul_nc(sA, Phi[v]) : (TA)0;
+    const uint32_t cnt =
+        face ? 0x80u | (isL ? ((uint32_t)aN | ((uint32_t)aF << 2) | ((capped ? 1u : 0u) << 4)) : 0u) : 0u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) lflux[k][v][l] = ph[v];
+    lcnt[k][l] = (uint8_t)cnt;
+    __syncthreads();
+    if (k != 0) return;
+    int cAdmN = 0, cAdmF = 0, cCap = 0, cGN = 0, cGF = 0, status = 0;
+    double nv = 0.0;
+    if (i < nc) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < DEG; ++q) {
+            const uint32_t c = lcnt[q][l];
+            if (!(c & 0x80u)) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += (double)lflux[q][v][l];
+            cAdmN += (int)(c & 3u);
+            cAdmF += (int)((c >> 2) & 3u);
+            cCap += (int)((c >> 4) & 1u);
+        }
+        update_cell_v<T, TA>(i, b, nc, ui, vol, acc, cdt, Unew, nv, cGN, cGF, status);
+    }
+    wave_partials(nv, cAdmN, cAdmF, cCap, cGN, cGF, status, blk, part_nv, part_cnt, part_status, n_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -798,11 +921,18 @@ void launch_flux(const T* U, const T* FV, const T* NC, T* Unew, int64_t nc, int 
                  const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
                  hipStream_t s) {
     const int64_t nblk = partial_blocks(nc, nb);
+    switch (sell.uniform_deg) {
 #define RT_CALL(D)                                                                                               \
-    hipLaunchKernelGGL((k_flux<T, T, D>), dim3((unsigned)nblk), dim3(kFluxBlock), 0, s, U, FV, NC, Unew, nc, nb, n_entries, \
-                       geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk)
-    RT_DEG_DISPATCH(sell.uniform_deg, RT_CALL)
+    hipLaunchKernelGGL((k_flux_slots<T, T, D>), dim3((unsigned)nblk), dim3(D * kSlice), 0, s, U, FV, NC, Unew, nc, nb, \
+                       n_entries, geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk)
+        case 6: RT_CALL(6); break;
+        case 14: RT_CALL(14); break;
 #undef RT_CALL
+        default:
+            hipLaunchKernelGGL((k_flux<T, T>), dim3((unsigned)nblk), dim3(kFluxBlock), 0, s, U, FV, NC, Unew, nc, nb,
+                               n_entries, geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk);
+            break;
+    }
 }
 
 template <typename T, int D>

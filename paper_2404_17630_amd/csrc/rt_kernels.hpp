@@ -41,9 +41,10 @@ void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, cons
                  const double* scale, const double* inv_scale, int64_t* part_sum, int64_t* part_max,
                  int32_t* part_status, hipStream_t s);
 
-// FV[b][e][4]: face states; NC[b][nc]: a copy of each cell's N, which
-// launch_flux gathers for the outflow cap (4 bytes a cell instead of a
-// 16-byte field record).
+// FV[b][e][4]: face states; NC[b][nc]: each cell's N V / n_faces (the
+// numerator of the outflow cap, one product of the stored N and V / n_faces),
+// which launch_flux gathers instead of a 16-byte field record and a side
+// record of V / n_faces.
 template <typename T>
 void launch_facestate(const T* U, T* FV, T* NC, int64_t nc, int nb, int64_t n_entries, const GeomView<T>& geo,
                       const SellView& sell, int use_limiter, hipStream_t s);

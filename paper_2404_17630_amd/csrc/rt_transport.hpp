@@ -45,6 +45,15 @@ __device__ inline void store4_stream(float* __restrict__ p, const float* v) {
 }
 __device__ inline void store4_stream(double* __restrict__ p, const double* v) { store4(p, v); }
 
+// a * b rounded on its own: never contracted with the sum it feeds, so a
+// face's contribution to a flux sum is the same value in every kernel that
+// forms it (the slot-parallel flux kernel passes it through LDS).
+template <typename R>
+__device__ inline R mul_nc(R a, R b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
 // The face record: A, n, rL, rR, vcap_L, vcap_R.
 template <typename T>
 struct FaceRec {
@@ -63,20 +72,26 @@ __device__ inline FaceRec<T> load_face(const T* __restrict__ face, int64_t f) {
 // Where the limited face states of a cell's sides are read from: the
 // face-state array FV[b][e][4] of the split path, or the LDS tile of the
 // fused kernel.
-// Both also give a neighbour's cell value of N (for the outflow cap).
+// Both also give the numerator N V / n_faces of the outflow cap of a cell:
+// the split path reads it as the product k_facestate stored (4 bytes a
+// cell, kCapProduct), the fused path forms it from the cell's N and the
+// side record's V / n_faces.  Either way it is the same product of the same
+// two stored values, rounded once.
 template <typename T>
 struct GlobalFaceStates {
+    static constexpr bool kCapProduct = true;
     const T* FVb;          // FV of bin b
     const int32_t* opp;
-    const T* Nb;           // N of every cell of bin b, copied by k_facestate (4 bytes a cell)
+    const T* NVb;          // N V / n_faces of every cell of bin b, written by k_facestate
     __device__ const T* own(int64_t e) const { return FVb + e * 4; }
     __device__ const T* other(int64_t e) const { return FVb + (int64_t)opp[e] * 4; }
     // with the entry's opposite entry already loaded
     __device__ const T* other(int64_t e, int32_t eo) const { return FVb + (int64_t)eo * 4; }
-    __device__ T cellN(int32_t j) const { return Nb[j]; }
+    __device__ T cellN(int32_t j) const { return NVb[j]; }
 };
 template <typename T>
 struct TileFaceStates {
+    static constexpr bool kCapProduct = false;
     const T* lds;
     int64_t e0;            // first entry of the tile
     const int32_t* lds_opp;
@@ -298,14 +313,15 @@ __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __
             const TA NL = isL ? Ni : Nj, NR = isL ? Nj : Ni;
             int aN = 0, aF = 0;
             TA Phi[4];
-            const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)gv[q][0], (TA)gv[q][1], (TA)ga[q][1],
-                                                 (TA)ga[q][2], (TA)ga[q][3], A, cdt, Phi, aN, aF);
+            const TA vcL = FS::kCapProduct ? (TA)1 : (TA)gv[q][0], vcR = FS::kCapProduct ? (TA)1 : (TA)gv[q][1];
+            const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, vcL, vcR, (TA)ga[q][1], (TA)ga[q][2], (TA)ga[q][3],
+                                                 A, cdt, Phi, aN, aF);
             if (isL) {
                 cAdmN += aN; cAdmF += aF; cCap += capped ? 1 : 0;
             }
             const TA sA = isL ? A : -A;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] += (double)(sA * Phi[v]);
+            for (int v = 0; v < 4; ++v) acc[v] += (double)mul_nc(sA, Phi[v]);
         }
     }
 }
@@ -407,7 +423,8 @@ __device__ inline void cell_flux_sum_s(int64_t i, int b, int64_t nc, const T* __
         const bool isL = sell.fsf[e] >= 0;
         const TA A = (TA)geo.sv(kSA, e);
         const TA n0 = (TA)geo.sv(kSN0, e), n1 = (TA)geo.sv(kSN1, e), n2 = (TA)geo.sv(kSN2, e);
-        const TA vcL = (TA)geo.sv(kSVL, e), vcR = (TA)geo.sv(kSVR, e);
+        const TA vcL = FS::kCapProduct ? (TA)1 : (TA)geo.sv(kSVL, e);
+        const TA vcR = FS::kCapProduct ? (TA)1 : (TA)geo.sv(kSVR, e);
         T so[4], sn[4];
         load4(fsv.own(e), so);
         load4(fsv.other(e), sn);
@@ -427,7 +444,7 @@ __device__ inline void cell_flux_sum_s(int64_t i, int b, int64_t nc, const T* __
         }
         const TA sA = isL ? A : -A;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] += (double)(sA * Phi[v]);
+        for (int v = 0; v < 4; ++v) acc[v] += (double)mul_nc(sA, Phi[v]);
     }
 }
 

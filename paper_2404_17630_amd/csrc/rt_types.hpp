@@ -51,6 +51,7 @@ struct GeomView {
     const T* face;
     const T* cell;
     const T* side;
+    const T* vol;          // [nc] V (the cell record's V as its own array, for the flux update)
     int64_t nf;
     int64_t ne;
     // group g of entry e (kSideGroupFirst[g+1] - kSideGroupFirst[g] values)
@@ -77,6 +78,9 @@ struct SellView {
     const int32_t* ptr;
     const int32_t* deg;
     const int2* nop;       // (nbr, opp for an L side or ~opp for an R side) of each entry, one 8-byte load
+    const int32_t* ops;    // opp for an L side, ~opp for an R side, INT32_MIN for padding (nop's second
+                           // half as its own array); with DEG slots in every slice the neighbour
+                           // follows from the entry
     int32_t uniform_deg;   // slots of every slice when all are equal and specialised (6, 14), else 0
 };
 
@@ -95,9 +99,10 @@ struct SellView {
 constexpr int kTileCells = 256;                 // cells per tile (RT_TILE_CELLS)
 constexpr int kTileThreads = 256;               // threads per tile workgroup: one per tile cell
 constexpr int kTileSlices = kTileCells / kSlice;
-// Cells per workgroup of the flux kernel, which is also the granularity of
-// the per-block partials (photon sums, counters, status) of both paths.
-constexpr int kFluxBlock = 256;
+// Cells per workgroup of the flux kernels (one slice), which is also the
+// granularity of the per-block partials (photon sums, counters, status) of
+// both paths.
+constexpr int kFluxBlock = kSlice;
 constexpr int kTileBlocks = kTileCells / kFluxBlock;  // partial slots per tile
 struct TileView {
     const int32_t* lds_opp;
@@ -111,14 +116,16 @@ struct TileView {
 // Workgroup id -> logical block: hardware hands workgroups to the 8 XCDs in
 // turn, so consecutive logical blocks (neighbouring cells in a locality
 // order) are remapped to run on the same XCD and share its L2.
-__device__ inline int64_t xcd_logical_block() {
-    const int64_t w = blockIdx.x;
-    const int64_t G = gridDim.x;
-    const int64_t xcd = w % kNumXcd;
-    const int64_t local = w / kNumXcd;
-    const int64_t per = G / kNumXcd;
-    const int64_t rem = G % kNumXcd;
+// (32-bit arithmetic: grids stay below 2^31 workgroups.)
+__device__ inline uint32_t xcd_logical_block32() {
+    const uint32_t w = blockIdx.x;
+    const uint32_t G = gridDim.x;
+    const uint32_t xcd = w % kNumXcd;
+    const uint32_t local = w / kNumXcd;
+    const uint32_t per = G / kNumXcd;
+    const uint32_t rem = G % kNumXcd;
     return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
+__device__ inline int64_t xcd_logical_block() { return (int64_t)xcd_logical_block32(); }
 
 }  // namespace rtk

@@ -28,7 +28,7 @@ KERNEL_NAMES = ("k_sources", "k_chem", "k_facestate", "k_flux", "k_reduce", "k_t
 RT_TRANSPORT_AUTO, RT_TRANSPORT_FUSED, RT_TRANSPORT_SPLIT = 0, 1, 2
 RT_DEVICE_HOST_ONLY = -1
 RT_TILE_CELLS = 256
-RT_NOALLOC_SCRATCH_MB = 16
+RT_NOALLOC_SCRATCH_MB = 64
 TABLES = ("nbr", "fsf", "opp", "sptr", "sdeg", "lds_opp", "halo_ptr", "halo_cell", "hside_ptr", "hside_entry")
 
 ERROR_NAMES = {RT_EINVAL: "RT_EINVAL", RT_EMESH: "RT_EMESH", RT_ESTATE: "RT_ESTATE", RT_EDEVICE: "RT_EDEVICE",
