@@ -72,6 +72,9 @@ extern "C" {
 #define RT_FIELD_NH      2   /* [nc]        hydrogen number density, cm^-3 (get only) */
 #define RT_FIELD_SPECIES 3   /* [5][nc]     x_HI, x_HII, y_HeI, y_HeII, y_HeIII */
 #define RT_FIELD_T       4   /* [nc]        gas temperature, K */
+#define RT_FIELD_ATTEMPTS 5  /* [nc]        chemistry step attempts of each cell (accepted and rejected,
+                                            Sec. 4.1.1), summed over the subcycles of the last
+                                            rt_subcycle call (get only) */
 
 /* Kernel ids for the profiling counters. */
 #define RT_KERNEL_SOURCES  0
@@ -187,6 +190,14 @@ int rt_mesh_destroy(rt_mesh* mesh);
 #define RT_TABLE_HALO_CELL   7
 #define RT_TABLE_HSIDE_PTR   8
 #define RT_TABLE_HSIDE_ENTRY 9
+/* Face evaluations of the flux kernel on meshes whose slices all have 6 or
+ * 14 slots (empty otherwise): slice s evaluates items fitem_ptr[s] ..
+ * fitem_ptr[s+1] - 1; item q is the pair fitem[2q], fitem[2q+1]: the entry,
+ * with bit 30 set when the face's other side is in the same slice
+ * (evaluated once, from its L side), and the opposite entry (complemented
+ * for an R side). */
+#define RT_TABLE_FITEM_PTR   10
+#define RT_TABLE_FITEM       11
 int rt_mesh_table(const rt_mesh* mesh, int table, const int32_t** data, int64_t* length);
 
 /* Create a radiation + gas state on a mesh.
@@ -234,15 +245,17 @@ int rt_subcycle(rt_state* state, int n_subcycles, double dt, void* hip_stream);
 #define RT_NOALLOC_SCRATCH_MB 64
 int rt_subcycle_noalloc(rt_state* state, int n_subcycles, double dt, void* hip_stream);
 
-/* Reverse-mode derivative of L(x_HI after n_subcycles from `initial`) given
- * dL/dx_HI [nc] of the final state (host or device):
+/* Reverse-mode derivative of L(x_HI after n_subcycles of length dt from
+ * `initial`) given dL/dx_HI [nc] of the final state (host or device); dt as
+ * in rt_subcycle (<= 0: the CFL step; above it: RT_EINVAL), so the gradient
+ * is that of the run the caller made:
  *   dL_dlnQ [n_src]  derivative with respect to the log of each source's rate
  *                    (all bins of a source scaled together),
  *   dL_dln_nH [nc]   derivative with respect to the log of the initial n_H.
  * Outputs may be host or device memory.  The forward pass is recomputed from
  * checkpoints taken every `checkpoint_every` subcycles; `initial` is not
  * modified.  FP64 states only (RT_ESTATE otherwise). */
-int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int checkpoint_every,
+int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int checkpoint_every, double dt,
                         const double* dL_dxHI_final, double* dL_dlnQ, double* dL_dln_nH,
                         void* hip_stream);
 

@@ -54,7 +54,7 @@ def build(force: bool = False) -> Path:
     if force or not LIB_PATH.exists() or LIB_PATH.stat().st_mtime < max(src.stat().st_mtime,
                                                                        (HERE / "m1rt_oracle.h").stat().st_mtime):
         tmp = LIB_PATH.with_suffix(".so.tmp")
-        subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                str(src), "-o", str(tmp)])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -93,8 +93,23 @@ def lib():
         L.oracle_rates.argtypes = [C.POINTER(Params), C.c_double, _f64p]
         L.oracle_cooling.restype = C.c_double
         L.oracle_cooling.argtypes = [C.POINTER(Params), C.c_double, C.c_double, _f64p]
+        L.oracle_set_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the oracle's subcycle loop (1 = the plain loops; more
+    give the same results bit for bit).  Returns the previous setting."""
+    global _threads
+    if lib().oracle_set_threads(int(n)) != 0:
+        raise ValueError(f"threads={n}")
+    prev, _threads = _threads, int(n)
+    return prev
+
+
+_threads = 1
 
 
 def _ptr(a: np.ndarray, ty=_f64p):

@@ -521,6 +521,13 @@ void make_admissible(R U[4], int64_t* cntN, int64_t* cntF) {
 // One subcycle.
 // ---------------------------------------------------------------------------
 
+// Host threads of a subcycle (oracle_set_threads).  With one thread the
+// subcycle runs as the plain loops below; with more, the per-cell loops are
+// shared out and the face loop becomes two passes (every face's flux, then
+// each cell's sum over its faces in face-index order), which adds the same
+// terms in the same order, so the results are the same bit for bit.
+int g_threads = 1;
+
 template <class R>
 struct Sources {
     int64_t n = 0;
@@ -529,8 +536,13 @@ struct Sources {
 };
 
 template <class R>
+int subcycle_threads(const Geometry& g, const oracle_params* p, double Dt, State<R>& s, const Sources<R>& src,
+                     oracle_diag* dg);
+
+template <class R>
 int subcycle(const Geometry& g, const oracle_params* p, double Dt, State<R>& s, const Sources<R>& src,
              oracle_diag* dg) {
+    if (g_threads > 1) return subcycle_threads(g, p, Dt, s, src, dg);
     const int nb = p->nb;
     const int64_t nc = g.nc;
     const double ct = p->c_reduced;
@@ -631,6 +643,125 @@ int subcycle(const Geometry& g, const oracle_params* p, double Dt, State<R>& s, 
             s.Nb(b, i) = U[0];
             for (int k = 0; k < 3; ++k) s.Fb(b, k, i) = U[1 + k];
         }
+    return 0;
+}
+
+// The same subcycle on g_threads host threads (see g_threads).
+template <class R>
+int subcycle_threads(const Geometry& g, const oracle_params* p, double Dt, State<R>& s, const Sources<R>& src,
+                     oracle_diag* dg) {
+    const int nb = p->nb;
+    const int64_t nc = g.nc, nf = g.nf;
+    const double ct = p->c_reduced;
+    const int nt = g_threads;
+
+    for (int64_t k = 0; k < src.n; ++k) {
+        int64_t i = src.cell[k];
+        for (int b = 0; b < nb; ++b) s.Nb(b, i) += src.rate[b * src.n + k] * Dt / g.V[i];
+    }
+
+    if (p->chem_mode != OR_CHEM_NONE) {
+        int64_t sum_att = 0, max_att = 0;
+        int err = 0;
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 256) reduction(+ : sum_att) reduction(max : max_att) \
+    reduction(min : err)
+        for (int64_t i = 0; i < nc; ++i) {
+            CellChem<R> c;
+            for (int b = 0; b < nb; ++b) {
+                c.N[b] = s.Nb(b, i);
+                for (int k = 0; k < 3; ++k) c.Fh[b][k] = s.Fb(b, k, i);
+            }
+            for (int q = 0; q < 5; ++q) c.x[q] = s.x[q * nc + i];
+            c.u = s.u[i];
+            c.nH = s.nH[i];
+            int64_t att = 0;
+            int rc = chem_cell(p, Dt, c, &att);
+            sum_att += att;
+            max_att = std::max<int64_t>(max_att, att);
+            if (rc) { err = std::min(err, rc); continue; }
+            for (int b = 0; b < nb; ++b) {
+                s.Nb(b, i) = c.N[b];
+                for (int k = 0; k < 3; ++k) s.Fb(b, k, i) = c.Fh[b][k];
+            }
+            for (int q = 0; q < 5; ++q) s.x[q * nc + i] = c.x[q];
+            s.u[i] = c.u;
+        }
+        dg->substeps += sum_att;
+        dg->max_substeps = std::max<int64_t>(dg->max_substeps, max_att);
+        if (err) { dg->status = err; return err; }
+    }
+
+    std::vector<R> grad((size_t)nb * 4 * 3 * nc);
+    for (int b = 0; b < nb; ++b)
+        for (int v = 0; v < 4; ++v) {
+            const R* phi = v == 0 ? &s.N[(size_t)b * nc] : &s.Fh[((size_t)b * 3 + (v - 1)) * nc];
+#pragma omp parallel for num_threads(nt) schedule(static)
+            for (int64_t i = 0; i < nc; ++i) {
+                R gi[3];
+                gradient_of(g, i, phi, p->use_limiter != 0, gi);
+                for (int k = 0; k < 3; ++k) grad[(((size_t)b * 4 + v) * 3 + k) * nc + i] = gi[k];
+            }
+        }
+
+    // Pass 1: A_f Phi_f of every face and bin.
+    std::vector<R> aphi((size_t)nf * nb * 4);
+    int64_t admN = 0, admF = 0, caps = 0;
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : admN, admF, caps)
+    for (int64_t f = 0; f < nf; ++f) {
+        const int64_t L = g.L[f], Rr = g.R[f];
+        const double* n = &g.n[3 * f];
+        for (int b = 0; b < nb; ++b) {
+            R UL[4], UR[4];
+            for (int v = 0; v < 4; ++v) {
+                const R* phi = v == 0 ? &s.N[(size_t)b * nc] : &s.Fh[((size_t)b * 3 + (v - 1)) * nc];
+                const R* gv = &grad[(((size_t)b * 4 + v) * 3) * nc];
+                UL[v] = phi[L] + gv[L] * g.rL[3 * f] + gv[nc + L] * g.rL[3 * f + 1] + gv[2 * nc + L] * g.rL[3 * f + 2];
+                UR[v] = phi[Rr] + gv[Rr] * g.rR[3 * f] + gv[nc + Rr] * g.rR[3 * f + 1] + gv[2 * nc + Rr] * g.rR[3 * f + 2];
+            }
+            make_admissible(UL, &admN, &admF);
+            make_admissible(UR, &admN, &admF);
+            R Phi[4];
+            hll_flux(UL, UR, n, ct, Phi);
+            if (val(Phi[0]) != 0.0) {
+                int64_t up = val(Phi[0]) > 0.0 ? L : Rr;
+                double nfs = (double)g.sides[up].size();
+                R cap = s.Nb(b, up) * g.V[up] / (nfs * rabs(Phi[0]) * Dt * g.A[f]);
+                if (val(cap) < 1.0) {
+                    ++caps;
+                    for (int v = 0; v < 4; ++v) Phi[v] = cap * Phi[v];
+                }
+            }
+            for (int v = 0; v < 4; ++v) aphi[((size_t)f * nb + b) * 4 + v] = g.A[f] * Phi[v];
+        }
+    }
+    dg->adm_N += admN; dg->adm_F += admF; dg->flux_caps += caps;
+    // Pass 2: each cell's sum over its faces in face-index order, then the
+    // update and the guards.
+    int64_t gN = 0, gF = 0;
+#pragma omp parallel for num_threads(nt) schedule(static) reduction(+ : gN, gF)
+    for (int64_t i = 0; i < nc; ++i) {
+        for (int b = 0; b < nb; ++b) {
+            R a[4] = {R(0.0), R(0.0), R(0.0), R(0.0)};
+            for (const FaceSide& fs : g.sides[i])
+                for (int v = 0; v < 4; ++v) {
+                    const R& t = aphi[((size_t)fs.face * nb + b) * 4 + v];
+                    if (fs.sign > 0) a[v] += t; else a[v] -= t;
+                }
+            R U[4];
+            U[0] = s.Nb(b, i) - (Dt / g.V[i]) * a[0];
+            for (int k = 0; k < 3; ++k) U[1 + k] = s.Fb(b, k, i) - (Dt / g.V[i]) * a[1 + k];
+            if (val(U[0]) < 0.0) { U[0] = 0.0; ++gN; }
+            R F2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+            if (val(F2) > val(U[0] * U[0])) {
+                ++gF;
+                if (val(U[0]) <= 0.0) { U[1] = 0.0; U[2] = 0.0; U[3] = 0.0; }
+                else { R sc = U[0] / sqrt(F2); for (int k = 1; k < 4; ++k) U[k] = U[k] * sc; }
+            }
+            s.Nb(b, i) = U[0];
+            for (int k = 0; k < 3; ++k) s.Fb(b, k, i) = U[1 + k];
+        }
+    }
+    dg->guard_N += gN; dg->guard_F += gF;
     return 0;
 }
 
@@ -738,6 +869,12 @@ int run_jvp_block(const oracle_mesh* m, const oracle_params* p, double* N, doubl
 // ---------------------------------------------------------------------------
 // C entry points
 // ---------------------------------------------------------------------------
+
+extern "C" int oracle_set_threads(int n) {
+    if (n < 1) return -1;
+    g_threads = n;
+    return 0;
+}
 
 extern "C" double oracle_cfl_dt(const oracle_mesh* m, const oracle_params* p) {
     Geometry g;

@@ -64,6 +64,12 @@ typedef struct oracle_diag {
     double loop_seconds;                  /* wall time of the subcycle loop (steady clock) */
 } oracle_diag;
 
+/* Host threads of the subcycle loop (default 1).  With more than one, the
+ * per-cell loops are shared out and the face loop becomes a pass over the
+ * faces and a per-cell pass that adds each cell's faces in face-index order:
+ * the results are the same bit for bit.  Returns 0, or -1 for n < 1. */
+int oracle_set_threads(int n);
+
 /* Global CFL step eta * min (3V/4pi)^(1/3) / c~ (eq. timestep, v_c = 0). */
 double oracle_cfl_dt(const oracle_mesh* m, const oracle_params* p);
 

@@ -29,6 +29,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -514,10 +516,13 @@ struct Segment {
 
 }  // namespace
 
-extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int checkpoint_every,
+extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int checkpoint_every, double dt_in,
                                    const double* dL_dxHI_final, double* dL_dlnQ, double* dL_dln_nH,
                                    void* hip_stream) {
     if (!initial) return rt_fail(RT_EINVAL, "null state");
+    if (!std::isfinite(dt_in)) return rt_fail(RT_EINVAL, "dt=%g", dt_in);
+    if (!(dt_in <= 0) && !(dt_in <= initial->dt_cfl))
+        return rt_fail(RT_EINVAL, "dt=%g above the CFL step %g", dt_in, initial->dt_cfl);
     if (n_subcycles < 0 || checkpoint_every < 1) return rt_fail(RT_EINVAL, "n_subcycles=%d checkpoint_every=%d",
                                                                 n_subcycles, checkpoint_every);
     if (!dL_dxHI_final || !dL_dln_nH || (initial->n_src > 0 && !dL_dlnQ)) return rt_fail(RT_EINVAL, "null array");
@@ -548,7 +553,7 @@ extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int
     if ((rc = w->ensure_face_states())) return rc;
     const int64_t nc = w->nc;
     const int nb = w->nb;
-    const double dt = w->dt_cfl;
+    const double dt = dt_in <= 0 ? w->dt_cfl : dt_in;
     const double cdt = w->params.c_reduced * dt / m->h_ref;
     const size_t ub = (size_t)nb * 4 * nc * 8;
     const int C = checkpoint_every;

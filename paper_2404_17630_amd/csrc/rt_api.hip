@@ -159,6 +159,32 @@ int rt_mesh::build_float_geometry() {
     return RT_OK;
 }
 
+// Face evaluations of the flux kernel on a uniform-degree mesh: slice s
+// evaluates the faces of its entries, once for a face whose other side is in
+// the slice too (from the L side, with kFluxPairBit), once per side for a
+// face that crosses to another slice.  Each item is the entry and its signed
+// opposite entry (opp for an L side, ~opp for an R side).
+void rt_mesh::build_flux_items() {
+    fitem_ptr.clear();
+    fitem.clear();
+    if (uniform_deg == 0) return;
+    const int64_t ns = (int64_t)sdeg.size();
+    const int64_t per = (int64_t)uniform_deg * kSlice;
+    fitem_ptr.assign(ns + 1, 0);
+    fitem.reserve(2 * n_entries);
+    for (int64_t s = 0; s < ns; ++s) {
+        for (int64_t q = 0; q < per; ++q) {
+            const int64_t e = s * per + q;
+            if (nbr[e] < 0) continue;
+            const bool same = (int64_t)opp[e] / per == s;
+            if (same && fsf[e] < 0) continue;      // evaluated from its L side
+            fitem.push_back((int32_t)e | (same ? kFluxPairBit : 0));
+            fitem.push_back(fsf[e] >= 0 ? opp[e] : ~opp[e]);
+        }
+        fitem_ptr[s + 1] = (int32_t)(fitem.size() / 2);
+    }
+}
+
 // Tiles of kTileCells cells for the fused transport kernel: the LDS slot of every
 // face side's opposite state, and the halo cells with the sides they
 // contribute, grouped per tile in (cell, entry) order.
@@ -259,14 +285,12 @@ int rt_mesh::build_side_geometry(size_t tbytes) {
 // (nbr, opp for an L side or ~opp for an R side) of every sliced-ELL entry
 // as one 8-byte record.
 static int upload_packed_index(rt_mesh* m) {
-    std::vector<int32_t> p((size_t)2 * m->n_entries, 0), q((size_t)m->n_entries, 0);
+    std::vector<int32_t> p((size_t)2 * m->n_entries, 0);
     for (int64_t e = 0; e < m->n_entries; ++e) {
         p[2 * e] = m->nbr[e];
         p[2 * e + 1] = m->nbr[e] < 0 ? 0 : (m->fsf[e] >= 0 ? m->opp[e] : ~m->opp[e]);
-        q[e] = m->nbr[e] < 0 ? INT32_MIN : p[2 * e + 1];
     }
-    int rc = m->d_idx.upload(p.data(), p.size() * 4);
-    return rc ? rc : m->d_ops.upload(q.data(), q.size() * 4);
+    return m->d_idx.upload(p.data(), p.size() * 4);
 }
 
 // The cells' V (units of h_ref^3) as one array per precision.
@@ -463,6 +487,7 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
         return rt_fail(RT_EINVAL, "too many face sides for the tile tables");
     }
     m->build_tiles();
+    m->build_flux_items();
     if (device == RT_DEVICE_HOST_ONLY) {
         m->refs.store(1);
         *out = m;
@@ -492,7 +517,9 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
         (rc = m->d_halo_ptr.upload(m->halo_ptr.data(), m->halo_ptr.size() * 4)) ||
         (rc = m->d_halo_cell.upload(m->halo_cell.data(), m->halo_cell.size() * 4)) ||
         (rc = m->d_hside_ptr.upload(m->hside_ptr.data(), m->hside_ptr.size() * 4)) ||
-        (rc = m->d_hside_entry.upload(m->hside_entry.data(), m->hside_entry.size() * 4))) {
+        (rc = m->d_hside_entry.upload(m->hside_entry.data(), m->hside_entry.size() * 4)) ||
+        (rc = m->d_fitem_ptr.upload(m->fitem_ptr.data(), m->fitem_ptr.size() * 4)) ||
+        (rc = m->d_fitem.upload(m->fitem.data(), m->fitem.size() * 4))) {
         delete m;
         return rc;
     }
@@ -542,6 +569,8 @@ extern "C" int rt_mesh_table(const rt_mesh* m, int table, const int32_t** data, 
         case RT_TABLE_HALO_CELL: v = &m->halo_cell; break;
         case RT_TABLE_HSIDE_PTR: v = &m->hside_ptr; break;
         case RT_TABLE_HSIDE_ENTRY: v = &m->hside_entry; break;
+        case RT_TABLE_FITEM_PTR: v = &m->fitem_ptr; break;
+        case RT_TABLE_FITEM: v = &m->fitem; break;
         default: return rt_fail(RT_EINVAL, "table %d", table);
     }
     *data = v->data();
@@ -655,7 +684,8 @@ int rt_state::alloc_buffers() {
     const size_t t = tbytes();
     int rc;
     if ((rc = U[0].alloc((size_t)nb * 4 * nc * t)) || (rc = U[1].alloc((size_t)nb * 4 * nc * t)) ||
-        (rc = X.alloc(5 * nc * 8)) || (rc = Ue.alloc(nc * 8)) || (rc = nH.alloc(nc * 8)))
+        (rc = X.alloc(5 * nc * 8)) || (rc = Ue.alloc(nc * 8)) || (rc = nH.alloc(nc * 8)) ||
+        (rc = att.alloc(nc * 4)))
         return rc;
     n_fblk = partial_blocks(nc, nb);
     n_cblk = chem_blocks(nc);
@@ -939,7 +969,7 @@ GeomView<double> rt_geo64(const rt_mesh* m) { return geom_view<double>(m); }
 SellView rt_sell(const rt_mesh* m) {
     return SellView{(const int32_t*)m->d_nbr.ptr, (const int32_t*)m->d_fsf.ptr, (const int32_t*)m->d_opp.ptr,
                     (const int32_t*)m->d_sptr.ptr, (const int32_t*)m->d_sdeg.ptr, (const int2*)m->d_idx.ptr,
-                    (const int32_t*)m->d_ops.ptr, m->uniform_deg};
+                    (const int32_t*)m->d_fitem_ptr.ptr, (const int2*)m->d_fitem.ptr, m->uniform_deg};
 }
 
 // One piece of a subcycle on explicit buffers (U, G in the state's precision).
@@ -964,11 +994,11 @@ void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStr
     if (s->precision == RT_MIXED)
         launch_chem<float>((float*)U, X, Ue, (const double*)s->nH.ptr, s->nc, s->cp, dt, (const double*)s->d_scale.ptr,
                            (const double*)s->d_inv_scale.ptr, s->pb.csum, s->pb.cmax,
-                           s->pb.cst, st);
+                           s->pb.cst, (int32_t*)s->att.ptr, st);
     else
         launch_chem<double>((double*)U, X, Ue, (const double*)s->nH.ptr, s->nc, s->cp, dt,
                             (const double*)s->d_scale.ptr, (const double*)s->d_inv_scale.ptr,
-                            s->pb.csum, s->pb.cmax, s->pb.cst, st);
+                            s->pb.csum, s->pb.cmax, s->pb.cst, (int32_t*)s->att.ptr, st);
     s->prof_end(st);
 }
 
@@ -1073,6 +1103,7 @@ extern "C" int rt_state_transport(const rt_state* s, int32_t* fused) {
 }
 
 void rt_reset_partials(rt_state* s, hipStream_t st) {
+    fill_words(s->att.ptr, s->nc, 0, st);
     fill_words(s->pb.cnt, 5 * s->n_fblk * 2, 0, st);
     fill_words(s->pb.fst, s->n_fblk, 0, st);
     fill_words(s->pb.nv, s->n_fblk * 2, 0, st);
@@ -1169,6 +1200,7 @@ static size_t field_count(const rt_state* s, int field) {
         case RT_FIELD_NH: return s->nc;
         case RT_FIELD_SPECIES: return 5 * s->nc;
         case RT_FIELD_T: return s->nc;
+        case RT_FIELD_ATTEMPTS: return s->nc;
         default: return 0;
     }
 }
@@ -1181,6 +1213,13 @@ extern "C" int rt_state_get_field(const rt_state* s, int field, double* out, int
     DeviceGuard dg(s->mesh->device);
     if (field == RT_FIELD_NH) { RT_HIP(hipMemcpy(out, s->nH.ptr, n * 8, hipMemcpyDefault)); return RT_OK; }
     if (field == RT_FIELD_SPECIES) { RT_HIP(hipMemcpy(out, s->X.ptr, n * 8, hipMemcpyDefault)); return RT_OK; }
+    if (field == RT_FIELD_ATTEMPTS) {
+        std::vector<int32_t> a(n);
+        RT_HIP(hipMemcpy(a.data(), s->att.ptr, n * 4, hipMemcpyDeviceToHost));
+        std::vector<double> d(a.begin(), a.end());
+        RT_HIP(hipMemcpy(out, d.data(), n * 8, hipMemcpyDefault));
+        return RT_OK;
+    }
     DevMem tmp;
     int rc = tmp.alloc(n * 8);
     if (rc) return rc;
@@ -1201,6 +1240,7 @@ extern "C" int rt_state_set_field(rt_state* s, int field, const double* in, int 
     (void)in_on_device;
     if (!s || !in) return rt_fail(RT_EINVAL, "null argument");
     if (field == RT_FIELD_NH) return rt_fail(RT_EINVAL, "n_H is fixed at create time");
+    if (field == RT_FIELD_ATTEMPTS) return rt_fail(RT_EINVAL, "the attempt counts are read only");
     const size_t n = field_count(s, field);
     if (!n) return rt_fail(RT_EINVAL, "field=%d", field);
     DeviceGuard dg(s->mesh->device);

@@ -72,7 +72,7 @@ struct rt_mesh {
     bool geo32_ready = false;
     DevMem d_side32, d_side64;   // per face side records (rtk::SideComp), built on first use
     int32_t uniform_deg = 0;     // rtk::SellView::uniform_deg
-    DevMem d_nbr, d_fsf, d_opp, d_sptr, d_sdeg, d_idx, d_ops;
+    DevMem d_nbr, d_fsf, d_opp, d_sptr, d_sdeg, d_idx;
     DevMem d_vol32, d_vol64;     // [nc] V in units of h_ref^3
     // Tiles of the fused transport kernel (rtk::TileView).
     std::vector<int32_t> lds_opp, halo_ptr, halo_cell, hside_ptr, hside_entry;
@@ -81,7 +81,16 @@ struct rt_mesh {
     size_t lds_limit = 0;        // LDS bytes a workgroup may use on the device
     DevMem d_lds_opp, d_halo_ptr, d_halo_cell, d_hside_ptr, d_hside_entry;
 
+    // Face evaluations of the flux kernel on uniform-degree meshes: per
+    // slice, the entries whose face is evaluated there, fitem_ptr [n_slices
+    // + 1] into the pairs of fitem: the entry, with kFluxPairBit set when the
+    // face's other side is in the same slice and takes the negated result,
+    // and the signed opposite entry (opp for an L side, ~opp for an R side).
+    std::vector<int32_t> fitem_ptr, fitem;
+    DevMem d_fitem_ptr, d_fitem;
+
     int build_float_geometry();
+    void build_flux_items();
     int build_side_geometry(size_t tbytes);
     void build_tiles();
     size_t tile_lds_bytes(size_t tbytes) const { return (size_t)tile_max_sides * 4 * tbytes; }
@@ -126,6 +135,7 @@ struct rt_state {
     int cur = 0;
     DevMem FV;
     DevMem X, Ue, nH;            // [5][nc], [nc], [nc]
+    DevMem att;                  // [nc] int32 chemistry attempts of each cell in the current call
     double scale[RT_MAX_BINS];
     DevMem d_scale, d_inv_scale, d_nv_scale;
 

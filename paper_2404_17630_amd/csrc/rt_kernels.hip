@@ -146,17 +146,20 @@ template <int NB, typename T>
 struct ChemInput {
     T U[NB][4];
     double x[5], u, nh;
+    int32_t att;           // the cell's attempts so far in this call
 };
 
 template <int NB, typename T>
 __device__ inline void chem_fetch(const T* __restrict__ U, const double* __restrict__ X, const double* __restrict__ Ue,
-                                  const double* __restrict__ nH, int64_t nc, int64_t i, ChemInput<NB, T>& in) {
+                                  const double* __restrict__ nH, const int32_t* __restrict__ att, int64_t nc, int64_t i,
+                                  ChemInput<NB, T>& in) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) load4(U + urec(b, nc, i), in.U[b]);
 #pragma unroll
     for (int q = 0; q < 5; ++q) in.x[q] = X[(int64_t)q * nc + i];
     in.u = Ue[i];
     in.nh = nH[i];
+    in.att = att[i];
 }
 
 template <int NB, typename T>
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
                                                  int64_t nc, int chunk, ChemParams P, double dt,
                                                  const double* __restrict__ scale, const double* __restrict__ inv_scale,
                                                  int64_t* __restrict__ part_sum, int64_t* __restrict__ part_max,
-                                                 int32_t* __restrict__ part_status) {
+                                                 int32_t* __restrict__ part_status, int32_t* __restrict__ att_cell) {
     __shared__ int next;
     __shared__ int64_t lds64[kBlock / 64];
     __shared__ int lds32[kBlock / 64];
@@ -197,20 +200,23 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
     ChemState<NB, double> s;
     ChemInput<NB, T> pf;
     double nh = 0.0;
+    int32_t att0 = 0;
     int64_t inext = c1;
     if (active) {
-        chem_fetch<NB, T>(U, X, Ue, nH, nc, i, pf);
+        chem_fetch<NB, T>(U, X, Ue, nH, att_cell, nc, i, pf);
         chem_unpack<NB, T>(pf, scale, s);
         nh = pf.nh;
+        att0 = pf.att;
         chem_begin<NB, double>(dt, s);
         inext = c0 + atomicAdd(&next, 1);
-        if (inext < c1) chem_fetch<NB, T>(U, X, Ue, nH, nc, inext, pf);
+        if (inext < c1) chem_fetch<NB, T>(U, X, Ue, nH, att_cell, nc, inext, pf);
     }
     while (active) {
         const int r = chem_attempt<NB, double>(P, dt, nh, s);
         if (r == 0) continue;
         sum_att += s.attempts;
         max_att = s.attempts > max_att ? s.attempts : max_att;
+        att_cell[i] = att0 + (int32_t)s.attempts;
         if (r < 0) {
             status |= 2;            // leave the cell untouched; the call is rolled back
         } else {
@@ -230,9 +236,10 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
         if (active) {
             chem_unpack<NB, T>(pf, scale, s);
             nh = pf.nh;
+            att0 = pf.att;
             chem_begin<NB, double>(dt, s);
             inext = c0 + atomicAdd(&next, 1);
-            if (inext < c1) chem_fetch<NB, T>(U, X, Ue, nH, nc, inext, pf);
+            if (inext < c1) chem_fetch<NB, T>(U, X, Ue, nH, att_cell, nc, inext, pf);
         }
     }
     const int64_t sm = block_sum<int64_t>(sum_att, lds64);
@@ -502,93 +509,96 @@ __global__ __launch_bounds__(kFluxBlock) void k_flux(const T* __restrict__ U, co
 }
 
 // Meshes whose slices all have DEG slots: one workgroup per (64-cell slice,
-// bin) with one wavefront per slot, so every lane computes one face flux and
-// the gathers of a cell's faces are in flight together in DEG wavefronts
-// instead of one after the other in one lane.  Each lane's only dependent
-// loads are the opposite face state and the neighbour's N, behind its own
-// 8-byte index record.  The products sigma A Phi go through LDS; after one
-// barrier the first wavefront adds each cell's slots in slot (face-index)
-// order in FP64, exactly as the one-lane form does, and updates the cell.
+// bin).  Its threads share out the slice's face evaluations (the mesh's
+// fitem list): a face whose two sides are both in the slice is evaluated
+// once, from its L side, and its R side takes the negated product, which is
+// the value that side would compute itself (the flux is formed in the
+// face's canonical orientation, so it is the same to the last bit); a face
+// that crosses to another slice is evaluated here for this slice's side.
+// On a Hilbert-ordered lattice a 64-cell slice is a 4x4x4 block whose 144
+// inner faces are evaluated once: 240 evaluations instead of 384.  Each
+// evaluation's loads are its entry's index, face record and face state and
+// the cell's cap numerator, then the opposite face state and the
+// neighbour's cap numerator.  The products sigma A Phi go through LDS by
+// entry; after one barrier the first wavefront adds each cell's slots in
+// slot (face-index) order in FP64, as the one-lane form does, and updates
+// the cell.
 template <typename T, typename TA, int DEG>
-__global__ __launch_bounds__(DEG * kSlice) void k_flux_slots(const T* __restrict__ U, const T* __restrict__ FV,
-                                                             const T* __restrict__ NC, T* __restrict__ Unew,
-                                                             int64_t nc, int nb, int64_t n_entries, GeomView<T> geo,
-                                                             SellView sell, TA cdt, double* __restrict__ part_nv,
-                                                             int64_t* __restrict__ part_cnt,
-                                                             int32_t* __restrict__ part_status, int64_t n_blocks) {
-    static_assert(DEG > 0 && DEG * kSlice <= 1024, "one wavefront per slot");
-    __shared__ TA lflux[DEG][4][kSlice];
-    __shared__ uint8_t lcnt[DEG][kSlice];   // bit 7: a face; bits 0-1, 2-3, 4: admissibility N, F, cap (L side)
+__global__ __launch_bounds__(kFluxPairThreads) void k_flux_pairs(
+    const T* __restrict__ U, const T* __restrict__ FV, const T* __restrict__ NC, T* __restrict__ Unew, int64_t nc,
+    int nb, int64_t n_entries, GeomView<T> geo, SellView sell, TA cdt, double* __restrict__ part_nv,
+    int64_t* __restrict__ part_cnt, int32_t* __restrict__ part_status, int64_t n_blocks) {
+    static_assert(DEG > 0, "uniform-degree meshes");
+    constexpr int kPer = DEG * kSlice;                 // entries of a slice
+    __shared__ TA lflux[4][kPer];
+    __shared__ uint8_t lcnt[kPer];                    // bits 0-1, 2-3, 4: admissibility N, F, cap (L side)
     const uint32_t blk32 = xcd_logical_block32();
     const int64_t blk = blk32;
     const int b = (int)(blk32 % (uint32_t)nb);
     const int64_t sl = blk32 / (uint32_t)nb;
-    const int k = threadIdx.x / kSlice;
+    const T* FVb = FV + (int64_t)b * n_entries * 4;
+    const T* NCb = NC + (int64_t)b * nc;
     const int l = threadIdx.x % kSlice;
     const int64_t i = sl * kSlice + l;
     const int64_t ic = i < nc ? i : nc - 1;
-    const int64_t e = (sl * DEG + k) * kSlice + l;     // every slice has DEG slots
-    const T* FVb = FV + (int64_t)b * n_entries * 4;
-    const T* NCb = NC + (int64_t)b * nc;
-    // The first wavefront also updates the slice's cells.  Every wavefront
-    // requests the cell's record and volume with the rest (under a branch
-    // on the wavefront they would be waited for at once; the other five
-    // find them in the cache), and everything of the own entry before the
-    // index is used.  The flux is evaluated on every lane, a padding entry's
-    // result being discarded, so that no load waits behind a branch on the
-    // index (a padding entry reads zeros, its own unused face-state slot and
-    // cell 0).  The neighbour follows from its entry: slot k' of lane l' of
-    // slice s' is entry (s' DEG + k') 64 + l'.
-    const int32_t os = sell.ops[e];
-    T ga[4], so[4], sn[4];
-    load4(geo.sg(3, e), ga);
-    load4(FVb + e * 4, so);
-    const TA Ni = (TA)NCb[ic];
-    const TA A = (TA)ga[0];
-    const bool face = os != INT32_MIN;
-    const bool isL = os >= 0;
-    const int64_t eo = face ? (int64_t)(isL ? os : ~os) : e;
-    const int64_t j = face ? (eo / (DEG * kSlice)) * kSlice + eo % kSlice : 0;
-    const T nj = NCb[j];
-    load4(FVb + eo * 4, sn);
-    const TA Nj = (TA)nj;
+    // The first wavefront's cell record and volume, for the update (every
+    // wavefront requests them: under a branch they would be waited for at
+    // once; the others find them in the cache).
     T ui[4];
     load4(U + urec(b, nc, ic), ui);
     const T vol = geo.vol[ic];
-    // all loads are issued before any arithmetic that waits for one
-    __builtin_amdgcn_sched_barrier(0);
-    TA sL[4], sR[4];
+    const int32_t it0 = sell.fitem_ptr[sl], it1 = sell.fitem_ptr[sl + 1];
+    for (int32_t it = it0 + (int32_t)threadIdx.x; it < it1; it += kFluxPairThreads) {
+        const int2 item = sell.fitem[it];
+        const bool pair = (item.x & kFluxPairBit) != 0;
+        const int64_t e = item.x & ~kFluxPairBit;
+        const int32_t os = item.y;
+        T ga[4], so[4], sn[4];
+        load4(geo.sg(3, e), ga);
+        load4(FVb + e * 4, so);
+        const int64_t ci = (e / kPer) * kSlice + e % kSlice;     // the entry's cell
+        const T ni = NCb[ci];
+        const bool isL = os >= 0;
+        const int64_t eo = isL ? os : ~os;
+        const int64_t j = (eo / kPer) * kSlice + eo % kSlice;    // the neighbour
+        const T nj = NCb[j];
+        load4(FVb + eo * 4, sn);
+        __builtin_amdgcn_sched_barrier(0);
+        const TA A = (TA)ga[0];
+        TA sL[4], sR[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        sL[v] = (TA)(isL ? so[v] : sn[v]);
-        sR[v] = (TA)(isL ? sn[v] : so[v]);
+        for (int v = 0; v < 4; ++v) {
+            sL[v] = (TA)(isL ? so[v] : sn[v]);
+            sR[v] = (TA)(isL ? sn[v] : so[v]);
+        }
+        const TA NL = (TA)(isL ? ni : nj), NR = (TA)(isL ? nj : ni);   // cap numerators N V / n_faces
+        int aN = 0, aF = 0;
+        TA Phi[4];
+        const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)1, (TA)1, (TA)ga[1], (TA)ga[2], (TA)ga[3], A, cdt,
+                                             Phi, aN, aF);
+        const TA sA = isL ? A : -A;
+        const int q = (int)(e - sl * kPer);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const TA ph = mul_nc(sA, Phi[v]);
+            lflux[v][q] = ph;
+            if (pair) lflux[v][(int)(eo - sl * kPer)] = -ph;
+        }
+        lcnt[q] = (uint8_t)(isL ? ((uint32_t)aN | ((uint32_t)aF << 2) | ((capped ? 1u : 0u) << 4)) : 0u);
+        if (pair) lcnt[(int)(eo - sl * kPer)] = 0;
     }
-    const TA NL = isL ? Ni : Nj, NR = isL ? Nj : Ni;   // cap numerators N V / n_faces
-    int aN = 0, aF = 0;
-    TA Phi[4];
-    const bool capped = face_flux<TA, TA>(sL, sR, NL, NR, (TA)1, (TA)1, (TA)ga[1], (TA)ga[2], (TA)ga[3], A, cdt, Phi,
-                                         aN, aF);
-    const TA sA = isL ? A : -A;
-    TA ph[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) ph[v] = face ? mul_nc(sA, Phi[v]) : (TA)0;
-    const uint32_t cnt =
-        face ? 0x80u | (isL ? ((uint32_t)aN | ((uint32_t)aF << 2) | ((capped ? 1u : 0u) << 4)) : 0u) : 0u;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) lflux[k][v][l] = ph[v];
-    lcnt[k][l] = (uint8_t)cnt;
     __syncthreads();
-    if (k != 0) return;
+    if (threadIdx.x >= kSlice) return;
     int cAdmN = 0, cAdmF = 0, cCap = 0, cGN = 0, cGF = 0, status = 0;
     double nv = 0.0;
     if (i < nc) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < DEG; ++q) {
-            const uint32_t c = lcnt[q][l];
-            if (!(c & 0x80u)) continue;
+        for (int k = 0; k < DEG; ++k) {
+            const int q = k * kSlice + l;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] += (double)lflux[q][v][l];
+            for (int v = 0; v < 4; ++v) acc[v] += (double)lflux[v][q];
+            const uint32_t c = lcnt[q];
             cAdmN += (int)(c & 3u);
             cAdmF += (int)((c >> 2) & 3u);
             cCap += (int)((c >> 4) & 1u);
@@ -865,19 +875,19 @@ int chem_chunk(int64_t nc) {
 template <typename T, int NB>
 static void launch_chem_nb(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
                            const double* scale, const double* inv_scale, int64_t* ps, int64_t* pm, int32_t* pst,
-                           hipStream_t s) {
+                           int32_t* att, hipStream_t s) {
     const int chunk = chem_chunk(nc);
     hipLaunchKernelGGL((k_chem<NB, T>), dim3((unsigned)chem_blocks(nc)), dim3(kBlock), 0, s, U, X, Ue, nH, nc, chunk,
-                       P, dt, scale, inv_scale, ps, pm, pst);
+                       P, dt, scale, inv_scale, ps, pm, pst, att);
 }
 
 template <typename T>
 void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
-                 const double* scale, const double* inv_scale, int64_t* ps, int64_t* pm, int32_t* pst,
+                 const double* scale, const double* inv_scale, int64_t* ps, int64_t* pm, int32_t* pst, int32_t* att,
                  hipStream_t s) {
     switch (P.nb) {
 #define RT_CHEM_CASE(K) \
-    case K: launch_chem_nb<T, K>(U, X, Ue, nH, nc, P, dt, scale, inv_scale, ps, pm, pst, s); break;
+    case K: launch_chem_nb<T, K>(U, X, Ue, nH, nc, P, dt, scale, inv_scale, ps, pm, pst, att, s); break;
         RT_CHEM_CASE(1) RT_CHEM_CASE(2) RT_CHEM_CASE(3) RT_CHEM_CASE(4)
         RT_CHEM_CASE(5) RT_CHEM_CASE(6) RT_CHEM_CASE(7) RT_CHEM_CASE(8)
 #undef RT_CHEM_CASE
@@ -923,8 +933,8 @@ void launch_flux(const T* U, const T* FV, const T* NC, T* Unew, int64_t nc, int 
     const int64_t nblk = partial_blocks(nc, nb);
     switch (sell.uniform_deg) {
 #define RT_CALL(D)                                                                                               \
-    hipLaunchKernelGGL((k_flux_slots<T, T, D>), dim3((unsigned)nblk), dim3(D * kSlice), 0, s, U, FV, NC, Unew, nc, nb, \
-                       n_entries, geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk)
+    hipLaunchKernelGGL((k_flux_pairs<T, T, D>), dim3((unsigned)nblk), dim3(kFluxPairThreads), 0, s, U, FV, NC, Unew, \
+                       nc, nb, n_entries, geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk)
         case 6: RT_CALL(6); break;
         case 14: RT_CALL(14); break;
 #undef RT_CALL
@@ -994,7 +1004,7 @@ void launch_set_fields(T* U, const double* X, double* Ue, int64_t nc, int nb, in
     template void launch_sources<T>(T*, int64_t, int, int32_t, const int32_t*, const int32_t*, const double*,       \
                                     int64_t, const double*, const double*, const double*, double, hipStream_t);    \
     template void launch_chem<T>(T*, double*, double*, const double*, int64_t, const ChemParams&, double,           \
-                                 const double*, const double*, int64_t*, int64_t*, int32_t*, hipStream_t);          \
+                                 const double*, const double*, int64_t*, int64_t*, int32_t*, int32_t*, hipStream_t); \
     template void launch_facestate<T>(const T*, T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, int, \
                                       hipStream_t);                                                                \
     template void launch_flux<T>(const T*, const T*, const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, \

@@ -39,7 +39,7 @@ void launch_sources(T* U, int64_t nc, int nb, int32_t n_cells_src, const int32_t
 template <typename T>
 void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
                  const double* scale, const double* inv_scale, int64_t* part_sum, int64_t* part_max,
-                 int32_t* part_status, hipStream_t s);
+                 int32_t* part_status, int32_t* att_cell /*[nc] attempts of each cell, accumulated*/, hipStream_t s);
 
 // FV[b][e][4]: face states; NC[b][nc]: each cell's N V / n_faces (the
 // numerator of the outflow cap, one product of the stored N and V / n_faces),

@@ -78,11 +78,15 @@ struct SellView {
     const int32_t* ptr;
     const int32_t* deg;
     const int2* nop;       // (nbr, opp for an L side or ~opp for an R side) of each entry, one 8-byte load
-    const int32_t* ops;    // opp for an L side, ~opp for an R side, INT32_MIN for padding (nop's second
-                           // half as its own array); with DEG slots in every slice the neighbour
-                           // follows from the entry
+    const int32_t* fitem_ptr;   // face evaluations per slice (uniform-degree meshes; see kFluxPairBit)
+    const int2* fitem;          // (entry | kFluxPairBit if paired, signed opposite entry) of each evaluation
     int32_t uniform_deg;   // slots of every slice when all are equal and specialised (6, 14), else 0
 };
+
+// A face whose two sides are in one slice is evaluated once there, from its
+// L side; the item carries this bit and the R side takes the negated
+// product.  Entries stay below 2^30 (rt_mesh_create), so the bit is free.
+constexpr int32_t kFluxPairBit = 1 << 30;
 
 // Tiles of the fused transport kernel: tile t is cells [T t, T t + T) with
 // T = kTileCells (whole slices, so its face sides are the contiguous entries
@@ -103,6 +107,7 @@ constexpr int kTileSlices = kTileCells / kSlice;
 // granularity of the per-block partials (photon sums, counters, status) of
 // both paths.
 constexpr int kFluxBlock = kSlice;
+constexpr int kFluxPairThreads = 256;           // threads of the flux workgroup of uniform-degree meshes
 constexpr int kTileBlocks = kTileCells / kFluxBlock;  // partial slots per tile
 struct TileView {
     const int32_t* lds_opp;

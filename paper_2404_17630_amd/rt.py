@@ -20,7 +20,7 @@ RT_OK, RT_EINVAL, RT_EMESH, RT_ESTATE, RT_EDEVICE, RT_ENOMEM, RT_ENUMERIC = 0, -
 RT_FP64, RT_MIXED = 0, 1
 RT_CHEM_NONE, RT_CHEM_H, RT_CHEM_HHE = 0, 1, 2
 RT_RATES_CASEB_CONST, RT_RATES_HG97 = 0, 1
-RT_FIELD_N, RT_FIELD_F, RT_FIELD_NH, RT_FIELD_SPECIES, RT_FIELD_T = 0, 1, 2, 3, 4
+RT_FIELD_N, RT_FIELD_F, RT_FIELD_NH, RT_FIELD_SPECIES, RT_FIELD_T, RT_FIELD_ATTEMPTS = 0, 1, 2, 3, 4, 5
 RT_KERNEL_SOURCES, RT_KERNEL_CHEM, RT_KERNEL_GRADIENT, RT_KERNEL_FLUX, RT_KERNEL_REDUCE = 0, 1, 2, 3, 4
 RT_KERNEL_TRANSPORT = 5
 RT_N_KERNELS = 6
@@ -29,7 +29,8 @@ RT_TRANSPORT_AUTO, RT_TRANSPORT_FUSED, RT_TRANSPORT_SPLIT = 0, 1, 2
 RT_DEVICE_HOST_ONLY = -1
 RT_TILE_CELLS = 256
 RT_NOALLOC_SCRATCH_MB = 64
-TABLES = ("nbr", "fsf", "opp", "sptr", "sdeg", "lds_opp", "halo_ptr", "halo_cell", "hside_ptr", "hside_entry")
+TABLES = ("nbr", "fsf", "opp", "sptr", "sdeg", "lds_opp", "halo_ptr", "halo_cell", "hside_ptr", "hside_entry",
+          "fitem_ptr", "fitem")
 
 ERROR_NAMES = {RT_EINVAL: "RT_EINVAL", RT_EMESH: "RT_EMESH", RT_ESTATE: "RT_ESTATE", RT_EDEVICE: "RT_EDEVICE",
                RT_ENOMEM: "RT_ENOMEM", RT_ENUMERIC: "RT_ENUMERIC"}
@@ -79,7 +80,7 @@ _SIGNATURES = [
     ("rt_state_destroy", C.c_int, [_vp]),
     ("rt_subcycle", C.c_int, [_vp, C.c_int, C.c_double, _vp]),
     ("rt_subcycle_noalloc", C.c_int, [_vp, C.c_int, C.c_double, _vp]),
-    ("rt_subcycle_adjoint", C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
+    ("rt_subcycle_adjoint", C.c_int, [_vp, C.c_int, C.c_int, C.c_double, _vp, _vp, _vp, _vp]),
     ("rt_state_get_field", C.c_int, [_vp, C.c_int, _vp, C.c_int]),
     ("rt_state_set_field", C.c_int, [_vp, C.c_int, _vp, C.c_int]),
     ("rt_state_info", C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
@@ -205,8 +206,8 @@ def rt_subcycle_noalloc(state, n_subcycles: int, dt: float = 0.0, stream=None):
 
 
 def rt_subcycle_adjoint(initial, n_subcycles: int, checkpoint_every: int, dL_dxHI_final, dL_dlnQ, dL_dln_nH,
-                        stream=None):
-    _check(lib().rt_subcycle_adjoint(initial, int(n_subcycles), int(checkpoint_every),
+                        stream=None, dt: float = 0.0):
+    _check(lib().rt_subcycle_adjoint(initial, int(n_subcycles), int(checkpoint_every), float(dt),
                                      _ptr(dL_dxHI_final, np.float64), _ptr(dL_dlnQ, np.float64),
                                      _ptr(dL_dln_nH, np.float64), _stream_ptr(stream)))
 
@@ -336,7 +337,7 @@ class State:
     def get(self, field: int) -> np.ndarray:
         nc, nb = self.n_cells, self.nb
         shape = {RT_FIELD_N: (nb, nc), RT_FIELD_F: (nb, 3, nc), RT_FIELD_NH: (nc,), RT_FIELD_SPECIES: (5, nc),
-                 RT_FIELD_T: (nc,)}[field]
+                 RT_FIELD_T: (nc,), RT_FIELD_ATTEMPTS: (nc,)}[field]
         out = np.zeros(shape)
         rt_state_get_field(self.h, field, out)
         return out
@@ -347,6 +348,10 @@ class State:
     def fields(self) -> dict:
         return dict(N=self.get(RT_FIELD_N), F=self.get(RT_FIELD_F), species=self.get(RT_FIELD_SPECIES),
                     T=self.get(RT_FIELD_T), n_H=self.get(RT_FIELD_NH))
+
+    def attempts(self) -> np.ndarray:
+        """Chemistry attempts of each cell over the last subcycle call (int64)."""
+        return self.get(RT_FIELD_ATTEMPTS).astype(np.int64)
 
     def diagnostics(self) -> dict:
         return rt_state_diagnostics(self.h, self.nb)

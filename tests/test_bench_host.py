@@ -20,9 +20,42 @@ def test_kernel_bytes_per_lattice_cell():
     """Per cell of a six-face lattice (3 faces, 6 face sides), 3 bins, FP32."""
     per_cell = {k: bench.algorithmic_bytes(k, 1, 3, 3, 6, 0, 4, 4)
                 for k in ("k_facestate", "k_flux", "k_transport", "k_chem")}
-    assert per_cell == {"k_facestate": 548, "k_flux": 616, "k_transport": 344, "k_chem": 200}
+    assert per_cell == {"k_facestate": 548, "k_flux": 520, "k_transport": 488, "k_chem": 208}
     # linear in the cell count
-    assert bench.algorithmic_bytes("k_flux", 1000, 3, 3000, 6000, 0, 4, 4) == 616 * 1000
+    assert bench.algorithmic_bytes("k_flux", 1000, 3, 3000, 6000, 0, 4, 4) == 520 * 1000
+
+
+def test_model_bytes_of_each_pass_add_up_to_the_two_pass_subcycle():
+    # gradient pass 16 nb p + 52 g + 48, flux pass 20 nb p + 52 g + 48, chemistry 104
+    m = {k: bench.model_bytes_per_cell(k, 3, 4, 4) for k in ("k_facestate", "k_flux", "k_chem", "k_transport")}
+    assert m == {"k_facestate": 448, "k_flux": 496, "k_chem": 104, "k_transport": 944}
+    assert m["k_facestate"] + m["k_flux"] + m["k_chem"] == bench.subcycle_bytes_per_cell(3, 4, 4)["two_pass"]
+    assert bench.model_bytes_per_cell("k_flux", 3, 8, 8) == 20 * 3 * 8 + 52 * 8 + 48
+
+
+def test_field_errors_find_planted_differences():
+    import numpy as np
+    rng = np.random.default_rng(3)
+    nb, nc, c = 2, 50, 3.0e9
+    N = rng.uniform(1.0, 2.0, size=(nb, nc))
+    r = dict(N=N, F=0.5 * c * N[:, None, :] * np.ones((nb, 3, nc)) / np.sqrt(3), species=rng.uniform(size=(5, nc)),
+             T=rng.uniform(1e3, 1e4, nc))
+    a = {k: v.copy() for k, v in r.items()}
+    a["N"][1, 7] *= 1 + 5e-3          # one cell over the N bar
+    a["F"][0, 2, 9] += 1e-2 * c * r["N"][0, 9]
+    a["species"][1, 3] += 2e-4
+    att_r = np.ones(nc, np.int64)
+    att_a = att_r.copy()
+    att_a[7] = 2
+    e, over = bench.field_errors(a, r, None, c, att_a, att_r)
+    assert abs(e["N_rel_max(N>1e-10 max)"] - 5e-3) < 1e-12
+    assert e["cells_N_rel>1e-3"] == 1 and over[7] and over.sum() == 1
+    assert abs(e["F_rel_to_cN_max(N>1e-10 max)"] - 1e-2) < 1e-9
+    assert abs(e["x_HII_abs_max"] - 2e-4) < 1e-12
+    assert not e["meets_stated_bar"]
+    assert e["cells_N_rel>1e-3_with_other_attempt_count"] == 1 and e["cells_with_other_attempt_count"] == 1
+    e2, _ = bench.field_errors(r, r, None, c)
+    assert e2["meets_stated_bar"] and e2["cells_N_rel>1e-3"] == 0
 
 
 def test_more_than_one_gpu_is_refused():

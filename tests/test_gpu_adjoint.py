@@ -26,7 +26,7 @@ def adjoint(problem, log_lum, log_nH, w):
 
 def forward_xhi(problem, log_lum, log_nH):
     s = problem.state(log_lum, log_nH)
-    s.subcycle(problem.n_subcycles)
+    s.subcycle(problem.n_subcycles, problem.dt)
     x = s.get(rt.RT_FIELD_SPECIES)[0]
     s.close()
     return x
@@ -78,6 +78,54 @@ def test_adjoint_matches_central_differences():
     fd = (w @ forward_xhi(pb, lq0, ln0 + h * v) - w @ forward_xhi(pb, lq0, ln0 - h * v)) / (2 * h)
     say(f"density direction: adjoint {gn @ v:.10e} fd {fd:.10e}")
     assert gn @ v == pytest.approx(fd, rel=1e-5, abs=0.0)
+
+
+def test_adjoint_of_a_run_with_a_shorter_subcycle():
+    """The adjoint differentiates the run the caller made: with dt at 0.6 of
+    the CFL step it matches central differences of runs at that dt, and
+    differs from the gradient of the CFL-step run."""
+    cfg = small_cfg(n_sub=5)
+    probe = Problem(cfg)
+    s = probe.state(probe.log_lum0, np.log(cfg["state"]["n_H"]))
+    dt = 0.6 * s.info()["dt_cfl"]
+    s.close()
+    pb = Problem(cfg, checkpoint_every=2, dt=dt)
+    nc = cfg["mesh"]["n_cells"]
+    w = np.random.default_rng(12).normal(size=nc)
+    lq0, ln0 = pb.log_lum0.copy(), np.log(cfg["state"]["n_H"])
+    gq, gn, _ = adjoint(pb, lq0, ln0, w)
+    gq_cfl, _, _ = adjoint(Problem(cfg, checkpoint_every=2), lq0, ln0, w)
+    assert np.abs(gq - gq_cfl).max() > 1e-3 * np.abs(gq).max()
+    h = 1e-6
+    for k in range(4):
+        e = np.zeros(4)
+        e[k] = h
+        fd = (w @ forward_xhi(pb, lq0 + e, ln0) - w @ forward_xhi(pb, lq0 - e, ln0)) / (2 * h)
+        say(f"dt = 0.6 CFL, source {k}: adjoint {gq[k]:.10e} fd {fd:.10e}")
+        assert gq[k] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(gq).max())
+    m = rt.Mesh(cfg["mesh"])
+    s = rt.State.from_config(m, cfg)
+    with pytest.raises(rt.RtError) as e:
+        rt.rt_subcycle_adjoint(s.h, 2, 1, np.zeros(nc), np.zeros(4), np.zeros(nc), dt=1.5 * s.info()["dt_cfl"])
+    assert e.value.code == rt.RT_EINVAL
+    s.close()
+    m.close()
+
+
+def test_second_backward_gives_the_same_gradient():
+    cfg = small_cfg(n_sub=3)
+    pb = Problem(cfg, checkpoint_every=2)
+    nc = cfg["mesh"]["n_cells"]
+    w = torch.tensor(np.random.default_rng(13).normal(size=nc), device="cuda")
+    a = torch.tensor(pb.log_lum0, dtype=torch.float64, device="cuda", requires_grad=True)
+    b = torch.tensor(np.log(cfg["state"]["n_H"]), dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = (w * RTSubcycles.apply(a, b, pb)).sum()
+    loss.backward(retain_graph=True)
+    g1 = (a.grad.clone(), b.grad.clone())
+    a.grad = None
+    b.grad = None
+    loss.backward()
+    assert torch.equal(a.grad, g1[0]) and torch.equal(b.grad, g1[1])
 
 
 def test_checkpoint_spacing_does_not_change_the_gradient():

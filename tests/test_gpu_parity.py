@@ -240,3 +240,25 @@ def test_many_block_mesh_matches_oracle():
     assert_parity(cfg, gpu, ref)
     assert gpu["diag"]["substeps"] == ref["diag"]["substeps"]
     assert gpu["diag"]["max_substeps"] == ref["diag"]["max_substeps"]
+
+
+def test_per_cell_attempt_counts():
+    """RT_FIELD_ATTEMPTS: each cell's chemistry attempts over the last call.
+    They add up to the call's total, every cell takes at least one attempt a
+    subcycle, the source cell at the ionisation front takes the most, and the
+    counts start from zero at every call."""
+    cfg = rtgen.cosmological(0, 1.0, 1.0, 6, 0.01, 4, 2, dims=(20, 18, 17), name="attempts")
+    m = rt.Mesh(cfg["mesh"])
+    s = rt.State.from_config(m, cfg)
+    for n in (4, 1):
+        s.subcycle(n)
+        att = s.attempts()
+        d = s.diagnostics()
+        assert att.sum() == d["substeps"], (att.sum(), d["substeps"])
+        assert att.min() >= n
+        assert att.max() >= d["max_substeps"]
+    with pytest.raises(rt.RtError) as e:
+        s.set(rt.RT_FIELD_ATTEMPTS, np.zeros(cfg["mesh"]["n_cells"]))
+    assert e.value.code == rt.RT_EINVAL
+    s.close()
+    m.close()

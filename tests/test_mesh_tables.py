@@ -116,6 +116,50 @@ def test_tile_tables_route_every_opposite_state(mesh):
                     assert t["hside_entry"][hs0 + slot - n_own] == eo
 
 
+def test_flux_items_evaluate_every_face_side_once(mesh):
+    """The flux kernel's per-slice face evaluations on uniform-degree meshes:
+    every face side of a slice's cells gets its product exactly once, either
+    from its own evaluation or, for a face whose two sides are in the slice,
+    negated from the L side's; an item's second value is the signed opposite
+    entry.  A Hilbert-ordered lattice evaluates 240 of a 4x4x4 slice's 384
+    sides."""
+    m, tabs = mesh
+    nc = m["n_cells"]
+    sdeg, nbr, fsf, opp = tabs["sdeg"], tabs["nbr"], tabs["fsf"], tabs["opp"]
+    ptr, items = tabs["fitem_ptr"], tabs["fitem"].reshape(-1, 2)
+    uniform = sdeg.size > 0 and int(sdeg[0]) in (6, 14) and np.all(sdeg == sdeg[0])
+    deg_ok = uniform and np.all(np.bincount(m["face_cells"].ravel(), minlength=nc) == sdeg[0])
+    if not deg_ok:
+        assert ptr.size == 0 and items.size == 0
+        return
+    per = int(sdeg[0]) * SLICE
+    assert ptr.size == sdeg.size + 1 and ptr[0] == 0 and ptr[-1] == items.shape[0]
+    pair_bit = 1 << 30
+    for s in range(sdeg.size):
+        got = np.zeros(per, int)
+        for e_raw, os_ in items[ptr[s]:ptr[s + 1]]:
+            pair = bool(e_raw & pair_bit)
+            e = int(e_raw & ~pair_bit)
+            assert e // per == s and nbr[e] >= 0
+            assert os_ == (opp[e] if fsf[e] >= 0 else ~opp[e])
+            got[e - s * per] += 1
+            if pair:
+                assert fsf[e] >= 0 and opp[e] // per == s
+                got[opp[e] - s * per] += 1
+            else:
+                assert opp[e] // per != s
+        valid = nbr[s * per:(s + 1) * per] >= 0
+        assert np.array_equal(got, valid.astype(int)), s
+
+
+def test_hilbert_slice_of_a_lattice_evaluates_240_sides():
+    m = rtgen.jittered_lattice((8, 8, 8), 1.0, 0.2, 3, "hilbert").as_dict()
+    h = rt.Mesh(m, device=rt.RT_DEVICE_HOST_ONLY)
+    ptr = h.table("fitem_ptr")
+    h.close()
+    assert np.all(np.diff(ptr) == 240)
+
+
 def test_host_only_mesh_cannot_hold_a_state():
     cfg = rtgen.stromgren(n=4, n_sub=1)
     m = rt.Mesh(cfg["mesh"], device=rt.RT_DEVICE_HOST_ONLY)
