@@ -728,6 +728,7 @@ int rt_state::upload_sources() {
     }
     ptr.push_back((int32_t)n_src);
     n_src_cells = (int32_t)cells.size();
+
     int rc;
     if ((rc = d_src_cell.upload(cells.data(), cells.size() * 4)) || (rc = d_src_ptr.upload(ptr.data(), ptr.size() * 4)) ||
         (rc = d_src_rate.upload(rate.data(), rate.size() * 8)) || (rc = d_src_vphys.upload(vp.data(), vp.size() * 8)))
@@ -855,6 +856,7 @@ extern "C" int rt_state_create(const rt_mesh* mesh_c, const rt_params* params, i
 
 rt_state::~rt_state() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+
     if (h_diag) (void)hipHostFree(h_diag);
 }
 
@@ -973,32 +975,42 @@ SellView rt_sell(const rt_mesh* m) {
 }
 
 // One piece of a subcycle on explicit buffers (U, G in the state's precision).
-void rt_step_sources(rt_state* s, void* U, double dt, hipStream_t st) {
+// Sources of the source cells [src0, src1) of the cell-sorted list (all by
+// default).
+void rt_step_sources(rt_state* s, void* U, double dt, hipStream_t st, int32_t src0, int32_t src1) {
+    if (src1 < 0) src1 = s->n_src_cells;
+    const int32_t n = src1 - src0;
+    if (n <= 0) return;
+    const int32_t* cell = (const int32_t*)s->d_src_cell.ptr + src0;
+    const int32_t* ptr = (const int32_t*)s->d_src_ptr.ptr + src0;
     s->prof_begin(RT_KERNEL_SOURCES, st);
     if (s->precision == RT_MIXED)
-        launch_sources<float>((float*)U, s->nc, s->nb, s->n_src_cells, (const int32_t*)s->d_src_cell.ptr,
-                              (const int32_t*)s->d_src_ptr.ptr, (const double*)s->d_src_rate.ptr, s->n_src,
+        launch_sources<float>((float*)U, s->nc, s->nb, n, cell, ptr, (const double*)s->d_src_rate.ptr, s->n_src,
                               (const double*)s->d_src_vphys.ptr, (const double*)s->d_inv_scale.ptr,
                               (const double*)s->d_scale.ptr, dt, st);
     else
-        launch_sources<double>((double*)U, s->nc, s->nb, s->n_src_cells, (const int32_t*)s->d_src_cell.ptr,
-                               (const int32_t*)s->d_src_ptr.ptr, (const double*)s->d_src_rate.ptr, s->n_src,
+        launch_sources<double>((double*)U, s->nc, s->nb, n, cell, ptr, (const double*)s->d_src_rate.ptr, s->n_src,
                                (const double*)s->d_src_vphys.ptr, (const double*)s->d_inv_scale.ptr,
                                (const double*)s->d_scale.ptr, dt, st);
     s->prof_end(st);
 }
 
-void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStream_t st) {
+// Chemistry of cells [cell0, cell1) (all by default), its partials from
+// chemistry slot cblk0.
+void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStream_t st, int64_t cell0,
+                  int64_t cell1, int64_t cblk0) {
     if (s->params.chem_mode == RT_CHEM_NONE) return;
+    if (cell1 < 0) cell1 = s->nc;
+    if (cell1 <= cell0) return;
     s->prof_begin(RT_KERNEL_CHEM, st);
     if (s->precision == RT_MIXED)
-        launch_chem<float>((float*)U, X, Ue, (const double*)s->nH.ptr, s->nc, s->cp, dt, (const double*)s->d_scale.ptr,
-                           (const double*)s->d_inv_scale.ptr, s->pb.csum, s->pb.cmax,
-                           s->pb.cst, (int32_t*)s->att.ptr, st);
+        launch_chem<float>((float*)U, X, Ue, (const double*)s->nH.ptr, s->nc, cell0, cell1, s->cp, dt,
+                           (const double*)s->d_scale.ptr, (const double*)s->d_inv_scale.ptr, s->pb.csum + cblk0,
+                           s->pb.cmax + cblk0, s->pb.cst + cblk0, (int32_t*)s->att.ptr, st);
     else
-        launch_chem<double>((double*)U, X, Ue, (const double*)s->nH.ptr, s->nc, s->cp, dt,
-                            (const double*)s->d_scale.ptr, (const double*)s->d_inv_scale.ptr,
-                            s->pb.csum, s->pb.cmax, s->pb.cst, (int32_t*)s->att.ptr, st);
+        launch_chem<double>((double*)U, X, Ue, (const double*)s->nH.ptr, s->nc, cell0, cell1, s->cp, dt,
+                            (const double*)s->d_scale.ptr, (const double*)s->d_inv_scale.ptr, s->pb.csum + cblk0,
+                            s->pb.cmax + cblk0, s->pb.cst + cblk0, (int32_t*)s->att.ptr, st);
     s->prof_end(st);
 }
 
@@ -1014,20 +1026,21 @@ void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st) {
     s->prof_end(st);
 }
 
-void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st) {
+// Fluxes and update of slices [slice0, slice1) (all by default).
+void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st, int64_t slice0,
+                  int64_t slice1) {
+    if (slice1 < 0) slice1 = (int64_t)s->mesh->sdeg.size();
     const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
     s->prof_begin(RT_KERNEL_FLUX, st);
-    const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;
+    const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;   // the cells' cap numerators follow the face states
     if (s->precision == RT_MIXED)
         launch_flux<float>((const float*)U, (const float*)FV, (const float*)FV + nfv, (float*)Un, s->nc, s->nb,
-                           s->mesh->n_entries,
-                           geom_view<float>(s->mesh), rt_sell(s->mesh), cdt, s->pb.nv,
-                           s->pb.cnt, s->pb.fst, st);
+                           s->mesh->n_entries, geom_view<float>(s->mesh), rt_sell(s->mesh), cdt, s->pb.nv, s->pb.cnt,
+                           s->pb.fst, slice0, slice1, st);
     else
-        launch_flux<double>((const double*)U, (const double*)FV, (const double*)FV + nfv, (double*)Un, s->nc,
-                            s->nb, s->mesh->n_entries,
-                            geom_view<double>(s->mesh), rt_sell(s->mesh), cdt, s->pb.nv,
-                            s->pb.cnt, s->pb.fst, st);
+        launch_flux<double>((const double*)U, (const double*)FV, (const double*)FV + nfv, (double*)Un, s->nc, s->nb,
+                            s->mesh->n_entries, geom_view<double>(s->mesh), rt_sell(s->mesh), cdt, s->pb.nv,
+                            s->pb.cnt, s->pb.fst, slice0, slice1, st);
     s->prof_end(st);
 }
 

@@ -179,7 +179,8 @@ __device__ inline void chem_unpack(const ChemInput<NB, T>& in, const double* __r
 template <int NB, typename T>
 __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __restrict__ X /*[5][nc]*/,
                                                  double* __restrict__ Ue /*[nc]*/, const double* __restrict__ nH,
-                                                 int64_t nc, int chunk, ChemParams P, double dt,
+                                                 int64_t nc, int64_t cell0, int64_t cell1, int chunk,
+                                                 ChemParams P, double dt,
                                                  const double* __restrict__ scale, const double* __restrict__ inv_scale,
                                                  int64_t* __restrict__ part_sum, int64_t* __restrict__ part_max,
                                                  int32_t* __restrict__ part_status, int32_t* __restrict__ att_cell) {
@@ -187,8 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_chem(T* __restrict__ U, double* __re
     __shared__ int64_t lds64[kBlock / 64];
     __shared__ int lds32[kBlock / 64];
     const int64_t blk = xcd_logical_block();
-    const int64_t c0 = blk * (int64_t)kBlock * chunk;
-    const int64_t c1 = c0 + (int64_t)kBlock * chunk < nc ? c0 + (int64_t)kBlock * chunk : nc;
+    const int64_t c0 = cell0 + blk * (int64_t)kBlock * chunk;
+    const int64_t c1 = c0 + (int64_t)kBlock * chunk < cell1 ? c0 + (int64_t)kBlock * chunk : cell1;
     if (threadIdx.x == 0) next = kBlock;
     __syncthreads();
     int64_t sum_att = 0, max_att = 0;
@@ -491,8 +492,8 @@ __global__ __launch_bounds__(kFluxBlock) void k_flux(const T* __restrict__ U, co
                                                  const T* __restrict__ NC, T* __restrict__ Unew,
                                                  int64_t nc, int nb, int64_t n_entries, GeomView<T> geo, SellView sell,
                                                  TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
-                                                 int32_t* __restrict__ part_status, int64_t n_blocks) {
-    const int64_t blk = xcd_logical_block();
+                                                 int32_t* __restrict__ part_status, int64_t n_blocks, int64_t slice0) {
+    const int64_t blk = slice0 * nb + xcd_logical_block();   // partial slot: (slice, bin) of the whole mesh
     const int b = (int)(blk % nb);
     const int64_t i = (blk / nb) * kFluxBlock + threadIdx.x;
     int cAdmN = 0, cAdmF = 0, cCap = 0;
@@ -527,15 +528,15 @@ template <typename T, typename TA, int DEG>
 __global__ __launch_bounds__(kFluxPairThreads) void k_flux_pairs(
     const T* __restrict__ U, const T* __restrict__ FV, const T* __restrict__ NC, T* __restrict__ Unew, int64_t nc,
     int nb, int64_t n_entries, GeomView<T> geo, SellView sell, TA cdt, double* __restrict__ part_nv,
-    int64_t* __restrict__ part_cnt, int32_t* __restrict__ part_status, int64_t n_blocks) {
+    int64_t* __restrict__ part_cnt, int32_t* __restrict__ part_status, int64_t n_blocks, int64_t slice0) {
     static_assert(DEG > 0, "uniform-degree meshes");
     constexpr int kPer = DEG * kSlice;                 // entries of a slice
     __shared__ TA lflux[4][kPer];
     __shared__ uint8_t lcnt[kPer];                    // bits 0-1, 2-3, 4: admissibility N, F, cap (L side)
     const uint32_t blk32 = xcd_logical_block32();
-    const int64_t blk = blk32;
     const int b = (int)(blk32 % (uint32_t)nb);
-    const int64_t sl = blk32 / (uint32_t)nb;
+    const int64_t sl = slice0 + blk32 / (uint32_t)nb;
+    const int64_t blk = sl * nb + b;                   // partial slot of the whole mesh
     const T* FVb = FV + (int64_t)b * n_entries * 4;
     const T* NCb = NC + (int64_t)b * nc;
     const int l = threadIdx.x % kSlice;
@@ -873,21 +874,23 @@ int chem_chunk(int64_t nc) {
 }
 
 template <typename T, int NB>
-static void launch_chem_nb(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
-                           const double* scale, const double* inv_scale, int64_t* ps, int64_t* pm, int32_t* pst,
-                           int32_t* att, hipStream_t s) {
-    const int chunk = chem_chunk(nc);
-    hipLaunchKernelGGL((k_chem<NB, T>), dim3((unsigned)chem_blocks(nc)), dim3(kBlock), 0, s, U, X, Ue, nH, nc, chunk,
-                       P, dt, scale, inv_scale, ps, pm, pst, att);
+static void launch_chem_nb(T* U, double* X, double* Ue, const double* nH, int64_t nc, int64_t cell0, int64_t cell1,
+                           const ChemParams& P, double dt, const double* scale, const double* inv_scale, int64_t* ps,
+                           int64_t* pm, int32_t* pst, int32_t* att, hipStream_t s) {
+    const int64_t n = cell1 - cell0;
+    if (n <= 0) return;
+    const int chunk = chem_chunk(n);
+    hipLaunchKernelGGL((k_chem<NB, T>), dim3((unsigned)chem_blocks(n)), dim3(kBlock), 0, s, U, X, Ue, nH, nc, cell0,
+                       cell1, chunk, P, dt, scale, inv_scale, ps, pm, pst, att);
 }
 
 template <typename T>
-void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
-                 const double* scale, const double* inv_scale, int64_t* ps, int64_t* pm, int32_t* pst, int32_t* att,
-                 hipStream_t s) {
+void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, int64_t cell0, int64_t cell1,
+                 const ChemParams& P, double dt, const double* scale, const double* inv_scale, int64_t* ps,
+                 int64_t* pm, int32_t* pst, int32_t* att, hipStream_t s) {
     switch (P.nb) {
 #define RT_CHEM_CASE(K) \
-    case K: launch_chem_nb<T, K>(U, X, Ue, nH, nc, P, dt, scale, inv_scale, ps, pm, pst, att, s); break;
+    case K: launch_chem_nb<T, K>(U, X, Ue, nH, nc, cell0, cell1, P, dt, scale, inv_scale, ps, pm, pst, att, s); break;
         RT_CHEM_CASE(1) RT_CHEM_CASE(2) RT_CHEM_CASE(3) RT_CHEM_CASE(4)
         RT_CHEM_CASE(5) RT_CHEM_CASE(6) RT_CHEM_CASE(7) RT_CHEM_CASE(8)
 #undef RT_CHEM_CASE
@@ -927,20 +930,21 @@ void launch_gradient(const double* U, double* G, int64_t nc, int nb, const GeomV
 
 template <typename T>
 void launch_flux(const T* U, const T* FV, const T* NC, T* Unew, int64_t nc, int nb, int64_t n_entries,
-                 const GeomView<T>& geo,
-                 const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
-                 hipStream_t s) {
-    const int64_t nblk = partial_blocks(nc, nb);
+                 const GeomView<T>& geo, const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt,
+                 int32_t* part_status, int64_t slice0, int64_t slice1, hipStream_t s) {
+    const int64_t nblk = partial_blocks(nc, nb);          // partial slots of the whole mesh
+    const int64_t grid = (slice1 - slice0) * nb;
+    if (grid <= 0) return;
     switch (sell.uniform_deg) {
 #define RT_CALL(D)                                                                                               \
-    hipLaunchKernelGGL((k_flux_pairs<T, T, D>), dim3((unsigned)nblk), dim3(kFluxPairThreads), 0, s, U, FV, NC, Unew, \
-                       nc, nb, n_entries, geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk)
+    hipLaunchKernelGGL((k_flux_pairs<T, T, D>), dim3((unsigned)grid), dim3(kFluxPairThreads), 0, s, U, FV, NC, Unew, \
+                       nc, nb, n_entries, geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk, slice0)
         case 6: RT_CALL(6); break;
         case 14: RT_CALL(14); break;
 #undef RT_CALL
         default:
-            hipLaunchKernelGGL((k_flux<T, T>), dim3((unsigned)nblk), dim3(kFluxBlock), 0, s, U, FV, NC, Unew, nc, nb,
-                               n_entries, geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk);
+            hipLaunchKernelGGL((k_flux<T, T>), dim3((unsigned)grid), dim3(kFluxBlock), 0, s, U, FV, NC, Unew, nc, nb,
+                               n_entries, geo, sell, (T)cdt, part_nv, part_cnt, part_status, nblk, slice0);
             break;
     }
 }
@@ -1003,12 +1007,13 @@ void launch_set_fields(T* U, const double* X, double* Ue, int64_t nc, int nb, in
 #define RT_INSTANTIATE(T)                                                                                          \
     template void launch_sources<T>(T*, int64_t, int, int32_t, const int32_t*, const int32_t*, const double*,       \
                                     int64_t, const double*, const double*, const double*, double, hipStream_t);    \
-    template void launch_chem<T>(T*, double*, double*, const double*, int64_t, const ChemParams&, double,           \
-                                 const double*, const double*, int64_t*, int64_t*, int32_t*, int32_t*, hipStream_t); \
+    template void launch_chem<T>(T*, double*, double*, const double*, int64_t, int64_t, int64_t, const ChemParams&,  \
+                                 double, const double*, const double*, int64_t*, int64_t*, int32_t*, int32_t*,     \
+                                 hipStream_t);                                                                      \
     template void launch_facestate<T>(const T*, T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, int, \
                                       hipStream_t);                                                                \
     template void launch_flux<T>(const T*, const T*, const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, \
-                                 double, double*, int64_t*, int32_t*, hipStream_t);                                 \
+                                 double, double*, int64_t*, int32_t*, int64_t, int64_t, hipStream_t);               \
     template void launch_transport<T>(const T*, T*, int64_t, int, const GeomView<T>&, const SellView&,             \
                                       const TileView&, size_t, int, double, double*, int64_t*, int32_t*,           \
                                       hipStream_t);                                                                \

@@ -36,10 +36,13 @@ void launch_sources(T* U, int64_t nc, int nb, int32_t n_cells_src, const int32_t
                     const double* rate, int64_t n_src, const double* vphys, const double* inv_scale,
                     const double* scale, double dt, hipStream_t s);
 
+// Cells [cell0, cell1) of the mesh's nc; the partial arrays start at the
+// range's first chemistry workgroup (chem_blocks(cell1 - cell0) of them).
 template <typename T>
-void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, const ChemParams& P, double dt,
-                 const double* scale, const double* inv_scale, int64_t* part_sum, int64_t* part_max,
-                 int32_t* part_status, int32_t* att_cell /*[nc] attempts of each cell, accumulated*/, hipStream_t s);
+void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, int64_t cell0, int64_t cell1,
+                 const ChemParams& P, double dt, const double* scale, const double* inv_scale, int64_t* part_sum,
+                 int64_t* part_max, int32_t* part_status, int32_t* att_cell /*[nc] attempts of each cell, accumulated*/,
+                 hipStream_t s);
 
 // FV[b][e][4]: face states; NC[b][nc]: each cell's N V / n_faces (the
 // numerator of the outflow cap, one product of the stored N and V / n_faces),
@@ -52,11 +55,11 @@ void launch_facestate(const T* U, T* FV, T* NC, int64_t nc, int nb, int64_t n_en
 void launch_gradient(const double* U, double* G, int64_t nc, int nb, const GeomView<double>& geo, const SellView& sell,
                      int use_limiter, hipStream_t s);
 
+// Slices [slice0, slice1); the partial arrays are those of the whole mesh.
 template <typename T>
 void launch_flux(const T* U, const T* FV, const T* NC, T* Unew, int64_t nc, int nb, int64_t n_entries,
-                 const GeomView<T>& geo,
-                 const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
-                 hipStream_t s);
+                 const GeomView<T>& geo, const SellView& sell, double cdt, double* part_nv, int64_t* part_cnt,
+                 int32_t* part_status, int64_t slice0, int64_t slice1, hipStream_t s);
 
 template <typename T>
 void launch_transport(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>& geo, const SellView& sell,
