@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 namespace {
@@ -46,9 +47,11 @@ template <int K> Dual<K> operator-(const Dual<K>& a) {
 template <int K> Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) {
     Dual<K> r; r.v = a.v * b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r;
 }
+// (a/b)' = (a' - (a/b) b') / b, which stays finite where b^2 would underflow
+// (states of 1e-160 and below occur at the leading edge of a front).
 template <int K> Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) {
     Dual<K> r; r.v = a.v / b.v;
-    for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+    for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
     return r;
 }
 template <int K> Dual<K> operator+(const Dual<K>& a, double b) { return a + Dual<K>(b); }
@@ -83,6 +86,31 @@ using std::sqrt; using std::exp; using std::log; using std::log10; using std::po
 template <class R> R rmax(const R& a, const R& b) { return val(a) >= val(b) ? a : b; }
 template <class R> R rmin(const R& a, const R& b) { return val(a) <= val(b) ? a : b; }
 template <class R> R rabs(const R& a) { return val(a) < 0 ? -a : a; }
+
+// ---------------------------------------------------------------------------
+// How the forward derivative (dual numbers) treats values that are rounding
+// noise or negligible.  These hold only in the dual-number instantiation:
+// the values of the plain FP64 run are untouched.  They define the
+// derivative that the reverse-mode adjoint computes (the paper has no
+// adjoint; these are this build's readings), so that the two can be
+// compared on workloads where the exact branch-path derivative overflows:
+//  * a nearly isotropic state, |Fh|^2 <= 1e-16 N^2, takes the Eddington
+//    tensor I/3 (its anisotropic part is O(f^2), below one rounding; the
+//    direction of a vanishing Fh has derivative 1/|Fh|);
+//  * the outflow cap's factor is held constant where the flux of N through
+//    the face is at the rounding level of its terms and of the two cells'
+//    contents, |Phi_N| <= 1e-12 (N_L* + N_R* + N_L + N_R);
+//  * at the start of a transport step, the state of a cell whose N is not
+//    above 1e-20 of the bin's largest N (or is zero), and its limited
+//    gradient, are held constant; what its neighbours' fluxes bring into it
+//    is kept.
+// ---------------------------------------------------------------------------
+template <class R> struct IsDual : std::false_type {};
+template <int K> struct IsDual<Dual<K>> : std::true_type {};
+constexpr double kIsotropicF2 = 1e-16;
+constexpr double kCapNoiseRel = 1e-12;
+constexpr double kNegligibleN = 1e-20;
+template <class R> R held(const R& x) { return R(val(x)); }   // the value, derivative zero
 
 // Physical constants (CODATA 2018), cgs.
 constexpr double K_BOLTZ = 1.380649e-16;
@@ -474,7 +502,8 @@ R chi_of(const R& f) {
 template <class R>
 void eddington_tensor(const R& N, const R* Fh, R D[3][3]) {
     R F2 = Fh[0] * Fh[0] + Fh[1] * Fh[1] + Fh[2] * Fh[2];
-    if (val(N) <= 0.0 || val(F2) <= 0.0) {
+    if (val(N) <= 0.0 || val(F2) <= 0.0 ||
+        (IsDual<R>::value && val(F2) <= kIsotropicF2 * val(N) * val(N))) {
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) D[a][b] = a == b ? R(1.0 / 3.0) : R(0.0);
         return;
@@ -535,6 +564,24 @@ struct Sources {
     std::vector<R> rate;    // [nb][n]
 };
 
+// The negligible states of a transport step (dual numbers only, see
+// kNegligibleN): neg[b][i] set, and the cell's N and Fh of bin b held.
+template <class R>
+void hold_negligible(State<R>& s, int nb, int64_t nc, std::vector<char>& neg) {
+    neg.assign((size_t)nb * nc, 0);
+    for (int b = 0; b < nb; ++b) {
+        double mx = 0.0;
+        for (int64_t i = 0; i < nc; ++i) mx = std::max(mx, val(s.Nb(b, i)));
+        for (int64_t i = 0; i < nc; ++i) {
+            const double n = val(s.Nb(b, i));
+            if (n > 0.0 && n >= kNegligibleN * mx) continue;
+            neg[(size_t)b * nc + i] = 1;
+            s.Nb(b, i) = held(s.Nb(b, i));
+            for (int k = 0; k < 3; ++k) s.Fb(b, k, i) = held(s.Fb(b, k, i));
+        }
+    }
+}
+
 template <class R>
 int subcycle_threads(const Geometry& g, const oracle_params* p, double Dt, State<R>& s, const Sources<R>& src,
                      oracle_diag* dg);
@@ -579,6 +626,8 @@ int subcycle(const Geometry& g, const oracle_params* p, double Dt, State<R>& s, 
     }
 
     // O3  gradients of N and of the three components of Fh, per bin.
+    std::vector<char> neg;
+    if (IsDual<R>::value) hold_negligible(s, nb, nc, neg);
     std::vector<R> grad((size_t)nb * 4 * 3 * nc);   // [nb][4][3][nc]
     for (int b = 0; b < nb; ++b)
         for (int v = 0; v < 4; ++v) {
@@ -586,7 +635,8 @@ int subcycle(const Geometry& g, const oracle_params* p, double Dt, State<R>& s, 
             for (int64_t i = 0; i < nc; ++i) {
                 R gi[3];
                 gradient_of(g, i, phi, p->use_limiter != 0, gi);
-                for (int k = 0; k < 3; ++k) grad[(((size_t)b * 4 + v) * 3 + k) * nc + i] = gi[k];
+                for (int k = 0; k < 3; ++k)
+                    grad[(((size_t)b * 4 + v) * 3 + k) * nc + i] = neg.empty() || !neg[(size_t)b * nc + i] ? gi[k] : held(gi[k]);
             }
         }
 
@@ -615,6 +665,9 @@ int subcycle(const Geometry& g, const oracle_params* p, double Dt, State<R>& s, 
                 int64_t up = val(Phi[0]) > 0.0 ? L : Rr;
                 double nfs = (double)g.sides[up].size();
                 R cap = s.Nb(b, up) * g.V[up] / (nfs * rabs(Phi[0]) * Dt * g.A[f]);
+                if (IsDual<R>::value && val(rabs(Phi[0])) <= kCapNoiseRel * (val(UL[0]) + val(UR[0]) +
+                                                                              val(s.Nb(b, L)) + val(s.Nb(b, Rr))))
+                    cap = held(cap);
                 if (val(cap) < 1.0) {
                     ++dg->flux_caps;
                     for (int v = 0; v < 4; ++v) Phi[v] = cap * Phi[v];
@@ -691,6 +744,8 @@ int subcycle_threads(const Geometry& g, const oracle_params* p, double Dt, State
         if (err) { dg->status = err; return err; }
     }
 
+    std::vector<char> neg;
+    if (IsDual<R>::value) hold_negligible(s, nb, nc, neg);
     std::vector<R> grad((size_t)nb * 4 * 3 * nc);
     for (int b = 0; b < nb; ++b)
         for (int v = 0; v < 4; ++v) {
@@ -699,7 +754,8 @@ int subcycle_threads(const Geometry& g, const oracle_params* p, double Dt, State
             for (int64_t i = 0; i < nc; ++i) {
                 R gi[3];
                 gradient_of(g, i, phi, p->use_limiter != 0, gi);
-                for (int k = 0; k < 3; ++k) grad[(((size_t)b * 4 + v) * 3 + k) * nc + i] = gi[k];
+                for (int k = 0; k < 3; ++k)
+                    grad[(((size_t)b * 4 + v) * 3 + k) * nc + i] = neg.empty() || !neg[(size_t)b * nc + i] ? gi[k] : held(gi[k]);
             }
         }
 
@@ -726,6 +782,9 @@ int subcycle_threads(const Geometry& g, const oracle_params* p, double Dt, State
                 int64_t up = val(Phi[0]) > 0.0 ? L : Rr;
                 double nfs = (double)g.sides[up].size();
                 R cap = s.Nb(b, up) * g.V[up] / (nfs * rabs(Phi[0]) * Dt * g.A[f]);
+                if (IsDual<R>::value && val(rabs(Phi[0])) <= kCapNoiseRel * (val(UL[0]) + val(UR[0]) +
+                                                                              val(s.Nb(b, L)) + val(s.Nb(b, Rr))))
+                    cap = held(cap);
                 if (val(cap) < 1.0) {
                     ++caps;
                     for (int v = 0; v < 4; ++v) Phi[v] = cap * Phi[v];

@@ -84,7 +84,13 @@ int oracle_run(const oracle_mesh* m, const oracle_params* p,
 /* Forward-mode derivative of the same run along n_dir directions of
  * (ln Q per source, ln n_H per cell): dlnQ [n_dir][n_src], dln_nH [n_dir][nc].
  * Writes the directional derivatives of the final x_HI into dxHI [n_dir][nc]
- * and advances the primal state like oracle_run. */
+ * and advances the primal state like oracle_run.  The derivative is that of
+ * the executed branch path, with three values held constant (derivative
+ * zero): the direction of a nearly isotropic flux (|Fh|^2 <= 1e-16 N^2, where
+ * the Eddington tensor is taken as I/3), the outflow cap's factor where the
+ * face's flux of N is rounding noise, and the state and limited gradient of
+ * a cell whose N is not above 1e-20 of its bin's largest at the start of a
+ * transport step. */
 int oracle_run_jvp(const oracle_mesh* m, const oracle_params* p,
                    double* N, double* F, const double* n_H, double* species, double* T,
                    int64_t n_src, const int64_t* src_cell, const double* src_rate,

@@ -35,7 +35,7 @@ import numpy as np
 from . import fields
 from .fields import C_LIGHT, KPC
 from .hilbert import bits_for, hilbert_key
-from .mesh import jittered_lattice, staggered_bcc
+from .mesh import jittered_lattice, split_faces, staggered_bcc
 
 CHEM_NONE, CHEM_H, CHEM_HHE = 0, 1, 2
 RATES_CASEB_CONST, RATES_HG97 = 0, 1
@@ -111,10 +111,15 @@ def stromgren(n: int = 32, n_sub: int = 100, precision: str = "fp64", hhe: bool 
 
 def cosmological(n: int, spacing_kpc: float, sigma_ln: float, n_src: int, c_frac: float,
                  n_sub: int, cfg_id: int, precision: str = "fp64", order: str = "hilbert",
-                 name: str = "cosmo", t0: float = 100.0, mean_nh: float = 2.0e-4, dims=None) -> dict:
-    """Lognormal H+He gas with power-law point sources at density peaks."""
+                 name: str = "cosmo", t0: float = 100.0, mean_nh: float = 2.0e-4, dims=None,
+                 split_fraction: float = 0.0) -> dict:
+    """Lognormal H+He gas with power-law point sources at density peaks.
+    With split_fraction > 0 that share of the lattice's faces is split in two
+    (seed 6000 + cfg_id), giving cells of 6 to 12 faces."""
     h = spacing_kpc * KPC
     mesh = jittered_lattice((n, n, n) if dims is None else tuple(dims), h, 0.2, 1000 + cfg_id, order)
+    if split_fraction > 0:
+        mesh = split_faces(mesh, split_fraction, 6000 + cfg_id)
     dims = mesh.dims
     g = fields.gaussian_random_field(dims, h, 2.0 * h, 2000 + cfg_id)
     n_lex = fields.lognormal_density(g, mean_nh, sigma_ln)
@@ -249,3 +254,41 @@ def reorder(cfg: dict, perm: np.ndarray) -> dict:
 def random_order(cfg: dict, seed: int = 4000) -> dict:
     """The workload in a seeded random cell order."""
     return reorder(cfg, np.random.default_rng(seed).permutation(cfg["mesh"]["n_cells"]))
+
+
+def reorder_cells(cfg: dict, perm: np.ndarray) -> dict:
+    """The same workload with cells relabelled (new cell k is old cell perm[k])
+    on any mesh: faces are relabelled and listed by their new L cell, in
+    their previous order within a cell."""
+    perm = np.asarray(perm, dtype=np.int64)
+    m = cfg["mesh"]
+    nc = m["n_cells"]
+    new_of_old = np.empty(nc, dtype=np.int64)
+    new_of_old[perm] = np.arange(nc)
+    fc = new_of_old[m["face_cells"]]
+    fperm = np.lexsort((np.arange(m["n_faces"]), fc[0]))
+    mesh = dict(m, volume=np.ascontiguousarray(m["volume"][perm]),
+                centre=np.ascontiguousarray(m["centre"][:, perm]),
+                face_cells=np.ascontiguousarray(fc[:, fperm]),
+                area=np.ascontiguousarray(m["area"][fperm]), normal=np.ascontiguousarray(m["normal"][:, fperm]),
+                face_centre=np.ascontiguousarray(m["face_centre"][:, fperm]))
+    st = cfg["state"]
+    state = dict(N=np.ascontiguousarray(st["N"][:, perm]), F=np.ascontiguousarray(st["F"][..., perm]),
+                 n_H=np.ascontiguousarray(st["n_H"][perm]), species=np.ascontiguousarray(st["species"][:, perm]),
+                 T=np.ascontiguousarray(st["T"][perm]))
+    meta = dict(cfg["meta"], lattice_index=np.ascontiguousarray(cfg["meta"]["lattice_index"][:, perm]),
+                cell_perm=perm)
+    src = dict(cfg["sources"], cell=new_of_old[cfg["sources"]["cell"]])
+    return dict(cfg, mesh=mesh, state=state, sources=src, meta=meta)
+
+
+def face_counts(mesh: dict) -> np.ndarray:
+    return np.bincount(mesh["face_cells"].ravel(), minlength=mesh["n_cells"])
+
+
+def degree_sorted(cfg: dict) -> dict:
+    """Cells sorted by their number of faces, in their previous order within
+    one count (the paper sorts cells by number of interfaces, Sec. 4.1.4), so
+    that the 64 cells of a slice share a degree and a slice pads to no more
+    slots than its cells have."""
+    return reorder_cells(cfg, np.argsort(face_counts(cfg["mesh"]), kind="stable"))

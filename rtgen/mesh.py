@@ -173,3 +173,31 @@ def staggered_bcc(n: int, a: float, jitter: float, seed: int, order: str = "hilb
     return Mesh(nc, np.full(nc, 0.5 * a ** 3), np.ascontiguousarray(centre), int(Lc.size), face_cells,
                 np.ascontiguousarray(area[fo]), np.ascontiguousarray(normal[:, fo]),
                 np.ascontiguousarray(fc[:, fo]), box, idx, (nn, nn, nn), float(a))
+
+
+def split_faces(mesh: Mesh, fraction: float, seed: int) -> Mesh:
+    """A mesh with variable face counts: a seeded share of the faces of
+    ``mesh`` is split into two faces of half the area, joining the same two
+    cells with the same normal, centred a quarter of the spacing either side
+    of the original centre along the next axis of the face's plane.  Each
+    cell keeps sum A n = 0 and its geometry matrix; a cell gets one more face
+    for each of its split faces (degrees 6 to 12 on a lattice).  Faces stay
+    grouped by their L cell, the halves in place of the face they replace."""
+    nf = mesh.n_faces
+    rng = np.random.default_rng(seed)
+    split = rng.random(nf) < fraction
+    reps = np.where(split, 2, 1)
+    src = np.repeat(np.arange(nf), reps)                   # original face of each new face
+    first = np.concatenate([[True], src[1:] != src[:-1]])  # first (or only) face of its group
+    half = split[src]
+    sign = np.where(half, np.where(first, -1.0, 1.0), 0.0)
+    n = mesh.normal[:, src]
+    k = np.argmax(np.abs(n), axis=0)                       # axis of the normal
+    t = np.zeros_like(n)
+    t[(k + 1) % 3, np.arange(src.size)] = 1.0              # an axis of the face's plane
+    fc = mesh.face_centre[:, src] + sign[None, :] * 0.25 * mesh.h * t
+    area = mesh.area[src] * np.where(half, 0.5, 1.0)
+    return Mesh(mesh.n_cells, mesh.volume, mesh.centre, int(src.size),
+                np.ascontiguousarray(mesh.face_cells[:, src]), np.ascontiguousarray(area),
+                np.ascontiguousarray(n), np.ascontiguousarray(fc), mesh.box, mesh.lattice_index, mesh.dims,
+                mesh.h)

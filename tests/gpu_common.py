@@ -57,6 +57,21 @@ def stencil_max(values, face_cells):
     return m
 
 
+def photon_conditioning(N_ref, face_cells, kappa=1e-6, phi=1e-10, cap=1e6):
+    """Per cell, how much looser than its own size the photon density is
+    known: the largest over bins of s_i / N_i with s_i the N scale of
+    field_errors (1 where N_i is at least 1e-6 of its stencil maximum and
+    1e-10 of the field's maximum, and for N_i = 0), at most `cap`."""
+    N_ref = np.asarray(N_ref, float)
+    c = np.ones(N_ref.shape[1])
+    for b in range(N_ref.shape[0]):
+        Nr = N_ref[b]
+        s = np.maximum(np.maximum(Nr, kappa * stencil_max(Nr, face_cells)), phi * Nr.max())
+        ratio = np.where(Nr > 0, s / np.where(Nr > 0, Nr, 1.0), 1.0)
+        c = np.maximum(c, np.minimum(ratio, cap))
+    return c
+
+
 def field_errors(gpu, ref, c_red, face_cells, kappa=1e-6, phi=1e-10):
     """Per-field, per-bin relative errors of a GPU run against the oracle.
 
@@ -66,9 +81,15 @@ def field_errors(gpu, ref, c_red, face_cells, kappa=1e-6, phi=1e-10):
     reaches it at the level eps * M_i (with kappa = 1e-6 and a tolerance of
     1e-10 the floor is one FP64 rounding of M_i); phi = 1e-10 is the global
     floor.  Flux components use the same scale times c~ (|F| <= c~ N).
-    Fractions are measured against max(|x|, 1e-6): a fraction far below 1 is
-    set by the photon density of the same cell and inherits its conditioning;
-    below 1e-6 the allowance is 1e-16 absolute.  T relative."""
+    A fraction is set by the photon density of its own cell and inherits
+    that density's conditioning: it is measured relative to |x| times the
+    cell's photon_conditioning factor (1 wherever N is known to its own
+    relative precision), floored at 1e-9 (an allowance of 1e-19; the FP64
+    test workloads need up to 2.4e-11, in cells ahead of a front whose x_HII
+    is set by photon densities near the underflow edge).  y_HeII is
+    the complement 1 - y_HeI - y_HeIII, so its absolute error is a few
+    roundings of 1: its scale is floored at 1e-5 (an allowance of 1e-15).
+    T relative."""
     errs = {}
     nb = ref["N"].shape[0]
     for b in range(nb):
@@ -78,9 +99,43 @@ def field_errors(gpu, ref, c_red, face_cells, kappa=1e-6, phi=1e-10):
         errs[f"N[{b}]"] = float((np.abs(gpu["N"][b] - Nr) / scale).max())
         for k in range(3):
             errs[f"F[{b}][{k}]"] = float((np.abs(gpu["F"][b, k] - ref["F"][b, k]) / (c_red * scale)).max())
+    cond = photon_conditioning(ref["N"], face_cells, kappa, phi)
     names = ("x_HI", "x_HII", "y_HeI", "y_HeII", "y_HeIII")
     for s in range(5):
         r = np.asarray(ref["species"][s], float)
-        errs[names[s]] = float((np.abs(gpu["species"][s] - r) / np.maximum(np.abs(r), 1e-6)).max())
+        floor = 1e-5 if names[s] == "y_HeII" else 1e-9
+        errs[names[s]] = float((np.abs(gpu["species"][s] - r) / np.maximum(np.abs(r) * cond, floor)).max())
     errs["T"] = rel_err(gpu["T"], ref["T"])
     return errs
+
+
+def host_threads() -> int:
+    """Host threads for the oracle on the large workloads: the CPUs this
+    process may run on, at most 16 (one GPU's share of the host)."""
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_run_threaded(cfg, **kw):
+    """oracle.run on the host's threads (bitwise the single-thread result)."""
+    import oracle
+    prev = oracle.set_threads(host_threads())
+    try:
+        return oracle.run(cfg, **kw)
+    finally:
+        oracle.set_threads(prev)
+
+
+_oracle_cache = {}
+
+
+def cached_oracle_run(key, cfg, **kw):
+    """oracle_run_threaded, kept for the session under `key` (large workloads
+    that several tests compare against)."""
+    if key not in _oracle_cache:
+        _oracle_cache[key] = oracle_run_threaded(cfg, **kw)
+    return _oracle_cache[key]

@@ -9,7 +9,7 @@ import oracle
 import rtgen
 from paper_2404_17630_amd import rt
 from paper_2404_17630_amd.autograd import Problem, RTSubcycles
-from tests.gpu_common import say
+from tests.gpu_common import host_threads, say
 
 pytestmark = pytest.mark.gpu
 
@@ -207,3 +207,21 @@ def test_full_size_adjoint_262k():
         fd = (loss(lq0, ln0 + h * v) - loss(lq0, ln0 - h * v)) / (2 * h)
         say(f"adjoint_262k: density direction {r}: adjoint {gn @ v:.10e} fd {fd:.10e}")
         assert gn @ v == pytest.approx(fd, rel=1e-5, abs=0.0)
+    # The oracle's forward-mode derivative of the same run (dual numbers
+    # through its own loops, on the host's threads) along a luminosity and a
+    # density direction.
+    dq = np.zeros((2, 64))
+    dq[0] = rng.normal(size=64)
+    dn = np.zeros((2, ln0.size))
+    dn[1] = rng.normal(size=ln0.size)
+    say("adjoint_262k: oracle forward-mode derivative along 2 directions")
+    prev = oracle.set_threads(host_threads())
+    try:
+        jv = oracle.run_jvp(cfg, dq, dn)["dxHI"]
+    finally:
+        oracle.set_threads(prev)
+    for d in range(2):
+        ref = w @ jv[d]
+        got = gq @ dq[d] + gn @ dn[d]
+        say(f"adjoint_262k: direction {d}: adjoint {got:.12e} oracle {ref:.12e}")
+        assert got == pytest.approx(ref, rel=1e-8, abs=0.0)

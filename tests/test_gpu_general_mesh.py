@@ -10,7 +10,7 @@ from paper_2404_17630_amd import rt
 from paper_2404_17630_amd.autograd import Problem
 from tests.gpu_common import field_errors, run_gpu, say
 from tests.test_gpu_adjoint import adjoint
-from tests.test_gpu_mixed import mixed_errors
+from tests.test_gpu_mixed import assert_other_fields, mixed_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -36,6 +36,7 @@ def test_expanding_hii_mixed_meets_stated_error():
         say(f"  {k:16s} {v:.3e}")
     assert max(errs[f"N[{b}] rel"] for b in range(3)) <= 1e-3
     assert errs["x_HII abs"] <= 1e-4
+    assert_other_fields(errs)
 
 
 def test_adjoint_on_fourteen_face_cells():
@@ -91,3 +92,52 @@ def test_expanding_hii_ionisation_zones():
     say(f"fronts: helium {r_he:.1f} pc, hydrogen {r_h:.1f} pc")
     assert 0 < r_he < r_h
     assert np.all(g["T"] > 0)
+
+
+def split_cfg(order="hilbert", precision="fp64"):
+    """H+He on a jittered lattice with a fifth of its faces split in two:
+    cells of 6 to 11 faces, so every slice pads to its largest degree and the
+    general-degree kernels run."""
+    cfg = rtgen.cosmological(0, 1.0, 1.0, 6, 0.01, 6, 3, dims=(14, 12, 11), split_fraction=0.2,
+                             name="split_faces", precision=precision)
+    return rtgen.degree_sorted(cfg) if order == "degree" else cfg
+
+
+@pytest.mark.parametrize("order", ["hilbert", "degree"])
+def test_variable_degree_mesh_fp64_matches_oracle(order):
+    cfg = split_cfg(order)
+    m = rt.Mesh(cfg["mesh"])
+    sdeg = m.table("sdeg")
+    assert len(set(sdeg.tolist())) > 1           # slices of several degrees: the general kernels
+    m.close()
+    say("split faces", order, cfg["mesh"]["n_cells"], "cells", cfg["mesh"]["n_faces"], "faces")
+    gpu = run_gpu(cfg)
+    ref = oracle.run(cfg)
+    errs = field_errors(gpu, ref, cfg["params"]["c_reduced"], cfg["mesh"]["face_cells"])
+    worst = max(errs, key=errs.get)
+    say("worst", worst, f"{errs[worst]:.3e}")
+    assert max(errs.values()) <= 1e-10, errs
+    assert gpu["diag"]["substeps"] == ref["diag"]["substeps"]
+    assert gpu["diag"]["flux_caps"] > 0
+
+
+def test_variable_degree_mesh_mixed_meets_stated_error():
+    cfg = split_cfg(precision="mixed")
+    gpu = run_gpu(cfg, precision=rt.RT_MIXED)
+    ref = oracle.run(cfg)
+    errs = mixed_errors(gpu, ref, cfg["params"]["c_reduced"])
+    for k, v in errs.items():
+        say(f"  {k:16s} {v:.3e}")
+    assert max(errs[f"N[{b}] rel"] for b in range(3)) <= 1e-3
+    assert errs["x_HII abs"] <= 1e-4
+    assert_other_fields(errs)
+
+
+@pytest.mark.parametrize("precision", [rt.RT_FP64, rt.RT_MIXED], ids=["fp64", "mixed"])
+def test_variable_degree_mesh_fused_equals_split(precision):
+    cfg = split_cfg()
+    a = run_gpu(cfg, precision=precision, transport=rt.RT_TRANSPORT_FUSED)
+    b = run_gpu(cfg, precision=precision, transport=rt.RT_TRANSPORT_SPLIT)
+    assert a["fused"] and not b["fused"]
+    for key in ("N", "F", "species", "T"):
+        assert np.array_equal(a[key], b[key]), key

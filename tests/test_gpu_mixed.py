@@ -2,17 +2,29 @@
 FP64 chemistry, flux sums and photon sums) against the FP64 oracle.
 
 Stated bar (Stromgren workload, 50 subcycles): N within 1e-3 relative where
-N exceeds 1e-10 of its maximum, x_HII within 1e-4 absolute; the errors of
-every field are printed."""
+N exceeds 1e-10 of its maximum, x_HII within 1e-4 absolute.  The other
+fields are held to bars of the same size: F within 1e-3 of c~ N (|F| <= c~ N,
+so this is N's bar), the helium fractions within 1e-4 absolute (x_HII's),
+and T within 1e-4 relative.  Every field's error is printed."""
 import numpy as np
 import pytest
 
 import oracle
 import rtgen
 from paper_2404_17630_amd import rt
-from tests.gpu_common import run_gpu, say
+from tests.gpu_common import cached_oracle_run, run_gpu, say
 
 pytestmark = pytest.mark.gpu
+
+
+def assert_other_fields(errs):
+    """The bars of F, the helium fractions and T (module docstring)."""
+    nb = sum(1 for k in errs if k.startswith("F["))
+    for b in range(nb):
+        assert errs[f"F[{b}] rel to N"] <= 1e-3, (b, errs)
+    for k in ("y_HeI abs", "y_HeII abs", "y_HeIII abs"):
+        assert errs[k] <= 1e-4, (k, errs)
+    assert errs["T rel"] <= 1e-4, errs
 
 
 def mixed_errors(gpu, ref, c_red):
@@ -43,6 +55,7 @@ def test_stromgren_mixed_meets_stated_error(hhe):
     for b in range(cfg["params"]["nb"]):
         assert errs[f"N[{b}] rel"] <= 1e-3
     assert errs["x_HII abs"] <= 1e-4
+    assert_other_fields(errs)
     # the scale is a power of two
     sc = gpu["diag"]["scale"]
     assert np.all(np.exp2(np.round(np.log2(sc))) == sc)
@@ -58,6 +71,7 @@ def test_mixed_ragged_hhe_close_to_oracle():
         say(f"  {k:16s} {v:.3e}")
     assert max(errs[f"N[{b}] rel"] for b in range(3)) <= 1e-3
     assert errs["x_HII abs"] <= 1e-4
+    assert_other_fields(errs)
 
 
 def test_mixed_photon_conservation_drift():
@@ -93,45 +107,28 @@ def test_mixed_throughput_recipe_at_531k_cells():
         say(f"  {k:16s} {v:.3e}")
     assert max(errs[f"N[{b}] rel"] for b in range(3)) <= 1e-3
     assert errs["x_HII abs"] <= 1e-4
+    assert_other_fields(errs)
     say(f"  chemistry attempts: gpu {gpu['diag']['substeps']} oracle {ref['diag']['substeps']}")
 
 
 def test_mixed_hhe_2m_full_size():
     """The mixed form of the 2.1M-cell H+He workload (3 bins, sigma_ln = 1.0,
-    256 sources) at full size: two subcycles against the oracle at the stated
-    bar; then all 50 subcycles against the FP64 form on the GPU (itself held
-    to the oracle at 1e-10 on this workload's first subcycles; an oracle run
-    of 50 subcycles takes minutes), at the stated bar.  The FP64 form
-    started from n_H rounded to FP32 (one FP32 rounding of the input) is run
-    beside it, and printed, as the measure of the workload's own
-    conditioning."""
+    256 sources) at full size over all 50 subcycles against the oracle (run
+    on the host's threads) at the stated bar, every field reported.  The FP64
+    form started from n_H rounded to FP32 (one FP32 rounding of the input) is
+    run beside it against the same oracle, and printed, as the measure of the
+    workload's own conditioning."""
     cfg = rtgen.hhe_2m()
-    say("hhe_2m mixed: 2 subcycles against the oracle")
-    gpu2 = run_gpu(cfg, n_sub=2, precision=rt.RT_MIXED)
-    ref2 = oracle.run(cfg, n_sub=2)
-    e2 = mixed_errors(gpu2, ref2, cfg["params"]["c_reduced"])
-    for k, v in e2.items():
-        say(f"  {k:16s} {v:.3e}")
-    assert max(e2[f"N[{b}] rel"] for b in range(3)) <= 1e-3
-    assert e2["x_HII abs"] <= 1e-4
-    say("hhe_2m: 50 subcycles, mixed, fp64, and fp64 from n_H rounded to fp32")
+    say("hhe_2m: 50 subcycles, mixed, and fp64 from n_H rounded to fp32")
     mixed = run_gpu(cfg, precision=rt.RT_MIXED)
-    fp64 = run_gpu(cfg, precision=rt.RT_FP64)
     nh32 = np.asarray(cfg["state"]["n_H"]).astype(np.float32).astype(np.float64)
     pert = run_gpu(cfg, precision=rt.RT_FP64, n_H=nh32)
-    e50 = mixed_errors(mixed, fp64, cfg["params"]["c_reduced"])
-    c50 = mixed_errors(pert, fp64, cfg["params"]["c_reduced"])
+    say("hhe_2m: oracle 50 subcycles on the host's threads")
+    ref = cached_oracle_run("hhe_2m", cfg)
+    e50 = mixed_errors(mixed, ref, cfg["params"]["c_reduced"])
+    c50 = mixed_errors(pert, ref, cfg["params"]["c_reduced"])
     for k in e50:
         say(f"  {k:16s} mixed {e50[k]:.3e}   fp64 from fp32 n_H {c50[k]:.3e}")
-
-    def p999(a, r):
-        out = 0.0
-        for b in range(r["N"].shape[0]):
-            m = r["N"][b] > 1e-10 * r["N"][b].max()
-            out = max(out, float(np.quantile(np.abs(a["N"][b][m] - r["N"][b][m]) / r["N"][b][m], 0.999)))
-        return out
-
-    pm, pc = p999(mixed, fp64), p999(pert, fp64)
-    say(f"  N rel p99.9     mixed {pm:.3e}   fp64 from fp32 n_H {pc:.3e}")
     assert max(e50[f"N[{b}] rel"] for b in range(3)) <= 1e-3
     assert e50["x_HII abs"] <= 1e-4
+    assert_other_fields(e50)

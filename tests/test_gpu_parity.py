@@ -9,7 +9,7 @@ import pytest
 import oracle
 import rtgen
 from paper_2404_17630_amd import rt
-from tests.gpu_common import field_errors, rel_err, run_gpu, say
+from tests.gpu_common import cached_oracle_run, field_errors, rel_err, run_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +25,8 @@ def assert_parity(cfg, gpu, ref, tol=TOL):
     # photon sums per bin
     assert np.allclose(gpu["diag"]["photon_sum"], ref["diag"]["photon_sum"], rtol=1e-12, atol=0)
     assert gpu["diag"]["dt"] == pytest.approx(ref["diag"]["dt"], rel=1e-14, abs=0.0)
+    say(cfg["name"], "caps gpu", gpu["diag"]["flux_caps"], "oracle", ref["diag"]["flux_caps"],
+        "adm_F", gpu["diag"]["adm_F"], ref["diag"]["adm_F"], "guard_F", gpu["diag"]["guard_F"], ref["diag"]["guard_F"])
 
 
 def test_stromgren_fp64_matches_oracle():
@@ -109,18 +111,18 @@ def test_determinism_bitwise():
     assert np.array_equal(a["diag"]["photon_sum"], b["diag"]["photon_sum"])
 
 
-def test_full_size_hhe_2m_first_subcycles():
-    """The 2.1M-cell H+He workload at full size: two subcycles against the
-    oracle, then the full 50 subcycles against the invariants."""
+def test_full_size_hhe_2m_all_subcycles():
+    """The 2.1M-cell H+He workload at full size (3 bins, sigma_ln = 1.0, 256
+    sources) over all 50 subcycles against the oracle (run on the host's
+    threads, bitwise its single-thread result), then the invariants."""
     say("hhe_2m full size: generating")
     cfg = rtgen.hhe_2m()
-    say("hhe_2m: gpu 2 subcycles")
-    gpu = run_gpu(cfg, n_sub=2)
-    say("hhe_2m: oracle 2 subcycles (about 30 s)")
-    ref = oracle.run(cfg, n_sub=2)
-    assert_parity(cfg, gpu, ref)
     say("hhe_2m: gpu 50 subcycles")
     full = run_gpu(cfg)
+    say("hhe_2m: oracle 50 subcycles on the host's threads")
+    ref = cached_oracle_run("hhe_2m", cfg)
+    assert_parity(cfg, full, ref)
+    assert full["diag"]["substeps"] == ref["diag"]["substeps"]
     x = full["species"]
     assert np.all((x >= 0) & (x <= 1))
     assert np.abs(x[0] + x[1] - 1).max() < 1e-13
@@ -262,3 +264,27 @@ def test_per_cell_attempt_counts():
     assert e.value.code == rt.RT_EINVAL
     s.close()
     m.close()
+
+
+def test_limiter_counters_fire_on_a_free_streaming_front():
+    """The cap, admissibility and guard counters on pure transport from a
+    point source: the free-streaming front is capped (theta = 0.9 on a face
+    it leaves through) and its extrapolated states need the admissibility
+    fix, in both implementations.  The counts themselves are not compared:
+    the HLL flux of a free-streaming state is a difference of terms of its
+    size, which leaves rounding-residue states (1e-18 of the maximum and
+    below) from the second subcycle on, and the limited face state of a
+    cell next to an empty one is its neighbour's 0 plus a rounding residue
+    of either sign.  Measured here: caps 299 (GPU) against 412 (oracle),
+    admissibility fixes of N 178 against 412, while every field agrees to
+    the parity bar."""
+    cfg = rtgen.stromgren(n=16, n_sub=8)
+    cfg["params"] = dict(cfg["params"], chem_mode=rtgen.CHEM_NONE, sigma=np.zeros((1, 3)))
+    gpu = run_gpu(cfg)
+    ref = oracle.run(cfg)
+    assert_parity(cfg, gpu, ref)
+    keys = ("flux_caps", "adm_N", "adm_F", "guard_N", "guard_F")
+    say("counters gpu", {k: gpu["diag"][k] for k in keys}, "oracle", {k: ref["diag"][k] for k in keys})
+    n_faces = cfg["mesh"]["n_faces"] * cfg["n_subcycles"]
+    for d in (gpu["diag"], ref["diag"]):
+        assert 0 < d["flux_caps"] < n_faces and 0 < d["adm_F"] < 2 * n_faces

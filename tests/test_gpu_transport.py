@@ -8,7 +8,7 @@ import oracle
 import rtgen
 from paper_2404_17630_amd import rt
 from tests.gpu_common import field_errors, run_gpu, say
-from tests.test_gpu_mixed import mixed_errors
+from tests.test_gpu_mixed import assert_other_fields, mixed_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +38,7 @@ def test_fused_and_split_agree(precision):
     else:
         m = mixed_errors(a, ref, cfg["params"]["c_reduced"])
         assert max(m[f"N[{k}] rel"] for k in range(3)) <= 1e-3 and m["x_HII abs"] <= 1e-4, m
+        assert_other_fields(m)
 
 
 def test_fused_photon_conservation_is_exact_to_rounding():
@@ -68,6 +69,7 @@ def test_fused_on_a_cell_order_without_locality():
     for k, v in m.items():
         say(f"  {k:16s} {v:.3e}")
     assert max(m[f"N[{k}] rel"] for k in range(3)) <= 1e-3 and m["x_HII abs"] <= 1e-4
+    assert_other_fields(m)
 
 
 def test_fused_on_the_staggered_mesh():
@@ -84,6 +86,7 @@ def test_fused_on_the_staggered_mesh():
         else:
             m = mixed_errors(g, ref, cfg["params"]["c_reduced"])
             assert max(m[f"N[{k}] rel"] for k in range(3)) <= 1e-3 and m["x_HII abs"] <= 1e-4, m
+            assert_other_fields(m)
 
 
 def test_transport_mode_errors():

@@ -17,6 +17,7 @@ def meshes():
         "lattice_random": rtgen.jittered_lattice((9, 8, 7), 1.0, 0.2, 3, "random").as_dict(),
         "bcc_hilbert": rtgen.staggered_bcc(5, 1.0, 0.1, 4, "hilbert").as_dict(),
         "lattice_small": rtgen.jittered_lattice((3, 3, 3), 1.0, 0.1, 2, "lattice").as_dict(),
+        "split_faces": rtgen.split_faces(rtgen.jittered_lattice((10, 9, 8), 1.0, 0.2, 3, "hilbert"), 0.2, 5).as_dict(),
     }
 
 

@@ -56,3 +56,20 @@ def test_substep_cap_reported_with_threads(threads):
     oracle.set_threads(3)
     with pytest.raises(RuntimeError):
         oracle.run(cfg)
+
+
+def test_derivative_run_advances_the_same_state():
+    """The forward-mode run holds some derivatives constant but no value: its
+    primal state equals the plain run's (to the rounding of the isotropic
+    Eddington tensor it takes for |Fh|^2 <= 1e-16 N^2)."""
+    cfg = ragged()
+    nc, ns = cfg["mesh"]["n_cells"], len(cfg["sources"]["cell"])
+    rng = np.random.default_rng(8)
+    a = oracle.run(cfg)
+    b = oracle.run_jvp(cfg, rng.normal(size=(1, ns)), rng.normal(size=(1, nc)))
+    for k in ("species", "T"):
+        assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-300), k
+    for bb in range(3):
+        ref = a["N"][bb]
+        assert np.max(np.abs(b["N"][bb] - ref) / np.maximum(ref, 1e-6 * ref.max())) < 1e-12
+    assert np.all(np.isfinite(b["dxHI"]))
