@@ -198,6 +198,20 @@ int rt_mesh_destroy(rt_mesh* mesh);
  * for an R side). */
 #define RT_TABLE_FITEM_PTR   10
 #define RT_TABLE_FITEM       11
+/* Faces of the split transport on meshes whose slices all have 6 slots
+ * (empty otherwise), by tile of RT_TILE_CELLS cells: tile t's faces with
+ * both sides in the tile are tpair[tpair_ptr[t] .. tpair_ptr[t+1]), each the
+ * L side's entry relative to the tile's first entry (6 RT_TILE_CELLS t) in
+ * the low 16 bits and the R side's in the high 16 bits.  The face sides
+ * whose face crosses to another tile are the boundary items q, numbered in
+ * entry order: tbnd[2q] is the entry and tbnd[2q+1] the opposite side's item
+ * (complemented for an R side); tile t holds items tbnd_ptr[t] ..
+ * tbnd_ptr[t+1] - 1 and slice s items tbnd_sptr[s] .. tbnd_sptr[s+1] - 1. */
+#define RT_TABLE_TPAIR_PTR   12
+#define RT_TABLE_TPAIR       13
+#define RT_TABLE_TBND_PTR    14
+#define RT_TABLE_TBND        15
+#define RT_TABLE_TBND_SPTR   16
 int rt_mesh_table(const rt_mesh* mesh, int table, const int32_t** data, int64_t* length);
 
 /* Create a radiation + gas state on a mesh.

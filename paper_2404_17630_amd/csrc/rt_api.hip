@@ -185,6 +185,56 @@ void rt_mesh::build_flux_items() {
     }
 }
 
+// Faces of the split transport on six-slot meshes, by tile of kTileCells
+// cells (the fused kernel's tiles): a face with both sides in the tile is
+// evaluated by the face-state kernel from its face states in LDS (once, the
+// R side taking the negated product); a face that crosses to another tile
+// is evaluated by the flux kernel for each side.
+void rt_mesh::build_tile_faces() {
+    tpair_ptr.clear(); tpair.clear(); tbnd_ptr.clear(); tbnd.clear(); tbnd_sptr.clear(); bmask.clear();
+    tbnd_max = 0;
+    if (uniform_deg != 6) return;
+    const int64_t per = (int64_t)uniform_deg * kTileCells;     // entries of a tile
+    const int64_t sper = (int64_t)uniform_deg * kSlice;        // entries of a slice
+    const int64_t nt = (nc + kTileCells - 1) / kTileCells;
+    const int64_t ns = (int64_t)sdeg.size();
+    tpair_ptr.assign(nt + 1, 0);
+    tbnd_ptr.assign(nt + 1, 0);
+    tbnd_sptr.assign(ns + 1, 0);
+    bmask.assign(nc, 0);
+    std::vector<int32_t> item(n_entries, -1);
+    int32_t n_items = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t e0 = t * per;
+        for (int64_t q = 0; q < per && e0 + q < n_entries; ++q) {
+            const int64_t e = e0 + q;
+            if (nbr[e] < 0) continue;
+            const int64_t qo = (int64_t)opp[e] - e0;
+            const int64_t cell = t * kTileCells + (q / sper) * kSlice + q % kSlice;
+            const int k = (int)((q % sper) / kSlice);
+            if (qo >= 0 && qo < per) {
+                if (fsf[e] >= 0) tpair.push_back((int32_t)(q | (qo << 16)));
+            } else {
+                item[e] = n_items++;
+                tbnd.push_back((int32_t)e);
+                tbnd.push_back(0);
+                bmask[cell] |= (uint8_t)(1u << k);
+                ++tbnd_sptr[e / sper + 1];
+            }
+        }
+        tpair_ptr[t + 1] = (int32_t)tpair.size();
+        tbnd_ptr[t + 1] = n_items;
+        tbnd_max = std::max<int64_t>(tbnd_max, tbnd_ptr[t + 1] - tbnd_ptr[t]);
+    }
+    for (int64_t s = 0; s < ns; ++s) tbnd_sptr[s + 1] += tbnd_sptr[s];
+    // the opposite side of a boundary item is a boundary item of its own tile
+    for (int32_t q = 0; q < n_items; ++q) {
+        const int32_t e = tbnd[2 * q];
+        const int32_t o = item[opp[e]];
+        tbnd[2 * q + 1] = fsf[e] >= 0 ? o : ~o;
+    }
+}
+
 // Tiles of kTileCells cells for the fused transport kernel: the LDS slot of every
 // face side's opposite state, and the halo cells with the sides they
 // contribute, grouped per tile in (cell, entry) order.
@@ -279,6 +329,22 @@ int rt_mesh::build_side_geometry(size_t tbytes) {
         err = hipMemcpy(d.ptr, grp.data(), grp.size() * 8, hipMemcpyHostToDevice);
     }
     if (err != hipSuccess) return rt_fail(RT_EDEVICE, "side geometry upload: %s", hipGetErrorString(err));
+    // area and normal of every boundary item of the split transport by tile
+    if (!tbnd.empty()) {
+        const int64_t nq = n_bnd();
+        std::vector<double> bg((size_t)nq * 4);
+        for (int64_t q = 0; q < nq; ++q) {
+            const int32_t e = tbnd[2 * q];
+            const double* rec = &face[(size_t)(fsf[e] >= 0 ? fsf[e] : ~fsf[e]) * kFaceRec];
+            for (int v = 0; v < 4; ++v) bg[(size_t)q * 4 + v] = rec[v];
+        }
+        if (tbytes == 4) {
+            std::vector<float> b32(bg.begin(), bg.end());
+            if ((rc = d_bgeo32.upload(b32.data(), b32.size() * 4))) return rc;
+        } else if ((rc = d_bgeo64.upload(bg.data(), bg.size() * 8))) {
+            return rc;
+        }
+    }
     return RT_OK;
 }
 
@@ -291,6 +357,13 @@ static int upload_packed_index(rt_mesh* m) {
         p[2 * e + 1] = m->nbr[e] < 0 ? 0 : (m->fsf[e] >= 0 ? m->opp[e] : ~m->opp[e]);
     }
     return m->d_idx.upload(p.data(), p.size() * 4);
+}
+
+// The opposite item of every boundary item (the device's part of tbnd).
+static int upload_bnd_opp(rt_mesh* m) {
+    std::vector<int32_t> o((size_t)m->n_bnd());
+    for (size_t q = 0; q < o.size(); ++q) o[q] = m->tbnd[2 * q + 1];
+    return m->d_tbnd_opp.upload(o.data(), o.size() * 4);
 }
 
 // The cells' V (units of h_ref^3) as one array per precision.
@@ -488,6 +561,7 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
     }
     m->build_tiles();
     m->build_flux_items();
+    m->build_tile_faces();
     if (device == RT_DEVICE_HOST_ONLY) {
         m->refs.store(1);
         *out = m;
@@ -519,7 +593,13 @@ extern "C" int rt_mesh_create(int64_t n_cells, const double* volume, const doubl
         (rc = m->d_hside_ptr.upload(m->hside_ptr.data(), m->hside_ptr.size() * 4)) ||
         (rc = m->d_hside_entry.upload(m->hside_entry.data(), m->hside_entry.size() * 4)) ||
         (rc = m->d_fitem_ptr.upload(m->fitem_ptr.data(), m->fitem_ptr.size() * 4)) ||
-        (rc = m->d_fitem.upload(m->fitem.data(), m->fitem.size() * 4))) {
+        (rc = m->d_fitem.upload(m->fitem.data(), m->fitem.size() * 4)) ||
+        (rc = m->d_tpair_ptr.upload(m->tpair_ptr.data(), m->tpair_ptr.size() * 4)) ||
+        (rc = m->d_tpair.upload(m->tpair.data(), m->tpair.size() * 4)) ||
+        (rc = m->d_tbnd_ptr.upload(m->tbnd_ptr.data(), m->tbnd_ptr.size() * 4)) ||
+        (rc = upload_bnd_opp(m)) ||
+        (rc = m->d_tbnd_sptr.upload(m->tbnd_sptr.data(), m->tbnd_sptr.size() * 4)) ||
+        (rc = m->d_bmask.upload(m->bmask.data(), m->bmask.size()))) {
         delete m;
         return rc;
     }
@@ -571,6 +651,11 @@ extern "C" int rt_mesh_table(const rt_mesh* m, int table, const int32_t** data, 
         case RT_TABLE_HSIDE_ENTRY: v = &m->hside_entry; break;
         case RT_TABLE_FITEM_PTR: v = &m->fitem_ptr; break;
         case RT_TABLE_FITEM: v = &m->fitem; break;
+        case RT_TABLE_TPAIR_PTR: v = &m->tpair_ptr; break;
+        case RT_TABLE_TPAIR: v = &m->tpair; break;
+        case RT_TABLE_TBND_PTR: v = &m->tbnd_ptr; break;
+        case RT_TABLE_TBND: v = &m->tbnd; break;
+        case RT_TABLE_TBND_SPTR: v = &m->tbnd_sptr; break;
         default: return rt_fail(RT_EINVAL, "table %d", table);
     }
     *data = v->data();
@@ -655,7 +740,13 @@ size_t rt_state::tbytes() const { return precision == RT_MIXED ? 4 : 8; }
 int rt_state::ensure_face_states() {
     if (FV.ptr) return RT_OK;
     // face states [nb][n_entries][4], then the cells' cap numerators N V / n_faces [nb][nc]
-    return FV.alloc(((size_t)nb * 4 * mesh->n_entries + (size_t)nb * nc) * tbytes());
+    // (by tile on six-slot meshes: the boundary items' states and cap
+    // numerators [nb][n_bnd][5])
+    const size_t n = std::max((size_t)nb * 4 * mesh->n_entries + (size_t)nb * nc, (size_t)nb * 5 * mesh->n_bnd());
+    int rc = FV.alloc(n * tbytes());
+    // six-slot meshes: the per-cell sums over tile-interior faces
+    if (!rc && mesh->uniform_deg == 6) rc = PS.alloc((size_t)nb * nc * 4 * 8);
+    return rc;
 }
 
 static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
@@ -1014,15 +1105,40 @@ void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStr
     s->prof_end(st);
 }
 
-void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st) {
+static TileFaceView rt_tile_faces(const rt_mesh* m) {
+    return TileFaceView{(const int32_t*)m->d_tpair_ptr.ptr, (const int32_t*)m->d_tpair.ptr,
+                        (const int32_t*)m->d_tbnd_ptr.ptr,  (const int32_t*)m->d_tbnd_sptr.ptr,
+                        (const int32_t*)m->d_tbnd_opp.ptr,  (const uint8_t*)m->d_bmask.ptr,
+                        m->n_bnd(),                         m->tbnd_max};
+}
+
+// Whether the split path of a state runs by tile (six-slot meshes): the
+// face-state pass then also evaluates the tile-interior faces, and the flux
+// pass needs its sums.
+static bool tile_split(const rt_state* s) { return s->mesh->uniform_deg == 6 && s->PS.ptr; }
+
+void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, double dt, bool all_states) {
     s->prof_begin(RT_KERNEL_GRADIENT, st);
     const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;   // the cells' cap numerators follow the face states
-    if (s->precision == RT_MIXED)
+    const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
+    if (!all_states && tile_split(s)) {
+        // boundary-item states [nb][n_bnd][4], then their cap numerators [nb][n_bnd], in FV
+        const int64_t nbs = (int64_t)s->nb * 4 * s->mesh->n_bnd();
+        if (s->precision == RT_MIXED)
+            launch_facestate_tile<float>((const float*)U, (float*)FV, (float*)FV + nbs, (double*)s->PS.ptr, s->nc,
+                                         s->nb, geom_view<float>(s->mesh), rt_sell(s->mesh), rt_tile_faces(s->mesh),
+                                         s->params.use_limiter, cdt, s->pb.cnt, s->pb.fst, st);
+        else
+            launch_facestate_tile<double>((const double*)U, (double*)FV, (double*)FV + nbs, (double*)s->PS.ptr, s->nc,
+                                          s->nb, geom_view<double>(s->mesh), rt_sell(s->mesh), rt_tile_faces(s->mesh),
+                                          s->params.use_limiter, cdt, s->pb.cnt, s->pb.fst, st);
+    } else if (s->precision == RT_MIXED) {
         launch_facestate<float>((const float*)U, (float*)FV, (float*)FV + nfv, s->nc, s->nb, s->mesh->n_entries,
                                 geom_view<float>(s->mesh), rt_sell(s->mesh), s->params.use_limiter, st);
-    else
+    } else {
         launch_facestate<double>((const double*)U, (double*)FV, (double*)FV + nfv, s->nc, s->nb, s->mesh->n_entries,
                                  geom_view<double>(s->mesh), rt_sell(s->mesh), s->params.use_limiter, st);
+    }
     s->prof_end(st);
 }
 
@@ -1033,7 +1149,20 @@ void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double d
     const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
     s->prof_begin(RT_KERNEL_FLUX, st);
     const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;   // the cells' cap numerators follow the face states
-    if (s->precision == RT_MIXED)
+    if (tile_split(s)) {
+        // whole tiles (the range is the whole mesh)
+        const int64_t nbs = (int64_t)s->nb * 4 * s->mesh->n_bnd();
+        if (s->precision == RT_MIXED)
+            launch_flux_tile<float>((const float*)U, (const float*)FV, (const float*)FV + nbs, (const double*)s->PS.ptr,
+                                    (float*)Un, s->nc, s->nb, (const float*)s->mesh->d_vol32.ptr,
+                                    (const float*)s->mesh->d_bgeo32.ptr, rt_tile_faces(s->mesh), cdt, s->pb.nv,
+                                    s->pb.cnt, s->pb.fst, st);
+        else
+            launch_flux_tile<double>((const double*)U, (const double*)FV, (const double*)FV + nbs,
+                                     (const double*)s->PS.ptr, (double*)Un, s->nc, s->nb,
+                                     (const double*)s->mesh->d_vol64.ptr, (const double*)s->mesh->d_bgeo64.ptr,
+                                     rt_tile_faces(s->mesh), cdt, s->pb.nv, s->pb.cnt, s->pb.fst, st);
+    } else if (s->precision == RT_MIXED)
         launch_flux<float>((const float*)U, (const float*)FV, (const float*)FV + nfv, (float*)Un, s->nc, s->nb,
                            s->mesh->n_entries, geom_view<float>(s->mesh), rt_sell(s->mesh), cdt, s->pb.nv, s->pb.cnt,
                            s->pb.fst, slice0, slice1, st);
@@ -1047,7 +1176,8 @@ void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double d
 TileView rt_tiles(const rt_mesh* m) {
     return TileView{(const int32_t*)m->d_lds_opp.ptr, (const int32_t*)m->d_halo_ptr.ptr,
                     (const int32_t*)m->d_halo_cell.ptr, (const int32_t*)m->d_hside_ptr.ptr,
-                    (const int32_t*)m->d_hside_entry.ptr, (int64_t)m->sdeg.size()};
+                    (const int32_t*)m->d_hside_entry.ptr, (int64_t)m->sdeg.size(),
+                    (const uint8_t*)m->d_bmask.ptr};
 }
 
 // Halo cells per cell up to which AUTO takes the fused path.  The fused
@@ -1089,7 +1219,7 @@ void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st) {
         if (fused) {
             rt_step_transport(s, U, Un, dt, st);
         } else {
-            rt_step_facestate(s, U, s->FV.ptr, st);
+            rt_step_facestate(s, U, s->FV.ptr, st, dt, false);
             rt_step_flux(s, U, s->FV.ptr, Un, dt, st);
         }
         s->cur ^= 1;

@@ -88,9 +88,25 @@ struct rt_mesh {
     // and the signed opposite entry (opp for an L side, ~opp for an R side).
     std::vector<int32_t> fitem_ptr, fitem;
     DevMem d_fitem_ptr, d_fitem;
+    // Faces of the split transport on six-slot meshes, per kTileCells-cell
+    // tile (rtk::TileFaceView): the faces with both sides in the tile
+    // (tpair: L and R entries relative to the tile's first entry, 16 bits
+    // each); the face sides whose face crosses to another tile, numbered in
+    // entry order ("boundary items"; tbnd: entry and the opposite side's item,
+    // complemented for an R side), with the first item of every tile
+    // (tbnd_ptr) and of every slice (tbnd_sptr); per cell the slots of such
+    // faces (bmask).  The device keeps the opposite items only (d_tbnd_opp)
+    // and each item's face area and normal in the transport precision
+    // (d_bgeo32/64: A, n_x, n_y, n_z).
+    std::vector<int32_t> tpair_ptr, tpair, tbnd_ptr, tbnd, tbnd_sptr;
+    std::vector<uint8_t> bmask;
+    int64_t tbnd_max = 0;        // most boundary items of one tile
+    DevMem d_tpair_ptr, d_tpair, d_tbnd_ptr, d_tbnd_opp, d_tbnd_sptr, d_bmask, d_bgeo32, d_bgeo64;
+    int64_t n_bnd() const { return (int64_t)tbnd.size() / 2; }
 
     int build_float_geometry();
     void build_flux_items();
+    void build_tile_faces();
     int build_side_geometry(size_t tbytes);
     void build_tiles();
     size_t tile_lds_bytes(size_t tbytes) const { return (size_t)tile_max_sides * 4 * tbytes; }
@@ -134,6 +150,8 @@ struct rt_state {
     DevMem U[2];
     int cur = 0;
     DevMem FV;
+    DevMem PS;                   // [nb][nc][4] FP64 flux sums over each cell's tile-interior faces
+                                 // (split path on six-slot meshes)
     DevMem X, Ue, nH;            // [5][nc], [nc], [nc]
     DevMem att;                  // [nc] int32 chemistry attempts of each cell in the current call
     double scale[RT_MAX_BINS];
@@ -185,7 +203,10 @@ rtk::SellView rt_sell(const rt_mesh* m);
 void rt_step_sources(rt_state* s, void* U, double dt, hipStream_t st, int32_t src0 = 0, int32_t src1 = -1);
 void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStream_t st, int64_t cell0 = 0,
                   int64_t cell1 = -1, int64_t cblk0 = 0);
-void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st);
+// Face states of the split path; on six-slot meshes also the tile-interior
+// faces' flux sums (PS), unless all_states asks for every face state in FV
+// (the adjoint's reverse sweep; rt_step_flux must not follow it then).
+void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, double dt, bool all_states);
 void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st, int64_t slice0 = 0,
                   int64_t slice1 = -1);
 void rt_step_transport(rt_state* s, const void* U, void* Un, double dt, hipStream_t st);

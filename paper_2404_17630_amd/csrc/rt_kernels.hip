@@ -610,6 +610,280 @@ __global__ __launch_bounds__(kFluxPairThreads) void k_flux_pairs(
 }
 
 // ---------------------------------------------------------------------------
+// Split transport on six-slot meshes, by tile of kTileCells cells (the fused
+// kernel's tiles), one workgroup per (tile, bin), one thread per tile cell:
+//   k_facestate_tile  each cell's limited gradient and its six face states
+//                     into LDS; the states of faces that cross to another
+//                     tile, with the cell's cap numerator, also to HBM,
+//                     packed in boundary-item order; then every
+//                     tile-interior face's flux, once, from the two states
+//                     in LDS; then each cell's sum over its tile-interior
+//                     faces in slot order, in FP64, to HBM (PS);
+//   k_flux_tile       the fluxes of the tile's boundary items (own and
+//                     opposite state read by item: the own ones contiguous);
+//                     each cell adds them in slot order to its interior sum
+//                     and is updated.
+// Only the cross-tile face states (one a cell on a Hilbert-ordered
+// lattice, against six) and a 32-byte sum go through HBM between the two
+// passes.  A cell's fluxes are added tile-interior faces first, then
+// cross-tile ones, each in slot order, as the fused kernel does too, so the
+// two paths agree bit for bit.
+// ---------------------------------------------------------------------------
+
+// Cell (relative to the tile) of an entry relative to the tile's first
+// entry, on a six-slot mesh.
+__device__ inline int tile_cell_of(int q) { return (q / (6 * kSlice)) * kSlice + q % kSlice; }
+
+// Boundary items of the calling lane's cell in slot order: item of slot k
+// (when bit k of bm is set) = first + (items of slots < k in the wavefront's
+// slice) + (lanes below with slot k set).  Called by whole wavefronts of
+// one slice (lanes past the last cell with bm = 0).
+struct SliceItems {
+    uint64_t bal[6];
+    __device__ void init(uint32_t bm) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) bal[k] = __ballot((bm >> k) & 1u);
+    }
+    // items of slots below k, then the rank within slot k
+    __device__ int32_t rank(int k) const {
+        const uint64_t lt = (1ull << (threadIdx.x & 63)) - 1ull;
+        int32_t r = __popcll(bal[k] & lt);
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk)
+            if (kk < k) r += __popcll(bal[kk]);
+        return r;
+    }
+};
+
+template <typename T, typename TA>
+__global__ __launch_bounds__(kTileThreads) void k_facestate_tile(
+    const T* __restrict__ U, T* __restrict__ BS, T* __restrict__ BN, double* __restrict__ PS, int64_t nc, int nb,
+    GeomView<T> geo, SellView sell, TileFaceView tf, int use_limiter, TA cdt, int64_t* __restrict__ part_cnt,
+    int32_t* __restrict__ part_status, int64_t n_blocks) {
+    constexpr int DEG = 6;
+    constexpr int kPer = DEG * kTileCells;           // entries of a tile
+    __shared__ TA lst[4][kPer];                      // face states, then the products sigma A Phi
+    __shared__ TA lnv[kTileCells];                   // cap numerators N V / n_faces
+    __shared__ uint64_t lcnt[kTileThreads / 64];     // packed face counts per wavefront
+    const uint32_t blk32 = xcd_logical_block32();
+    const int b = (int)(blk32 % (uint32_t)nb);
+    const int64_t t = blk32 / (uint32_t)nb;
+    const int tid = threadIdx.x;
+    const int64_t c0 = t * kTileCells;
+    const int64_t i = c0 + tid;
+    const int64_t e0 = t * kPer;
+    T* BSb = BS + (int64_t)b * tf.n_bnd * 4;
+    T* BNb = BN + (int64_t)b * tf.n_bnd;
+    // The tile's interior faces, at most three per thread (a face takes two
+    // of the tile's 6 kTileCells sides): their indices are requested first,
+    // their records before the barrier, so that the face phase waits on no
+    // global load.
+    constexpr int kRounds = 3;
+    const int32_t p0 = tf.pair_ptr[t], p1 = tf.pair_ptr[t + 1];
+    int32_t pk[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int32_t p = p0 + tid + r * kTileThreads;
+        pk[r] = p < p1 ? tf.pair[p] : -1;
+    }
+    const uint32_t bm = i < nc ? tf.bmask[i] : 0u;
+    T nv = (T)0;
+    if (i < nc) {
+        CellSides<T, DEG> cs;
+        load_cell_sides<T, DEG>(i, geo, sell, cs);
+        T cell[8];
+        load4(geo.cell + i * kCellRec, cell);
+        load4(geo.cell + i * kCellRec + 4, cell + 4);
+        double ui[4], g[4][3];
+        limited_gradient_c<T, DEG>(i, b, nc, U, cell, cs, use_limiter, ui, g);
+        nv = (T)ui[0] * cell[7];
+        lnv[tid] = (TA)nv;
+        const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
+#pragma unroll
+        for (int k = 0; k < DEG; ++k) {
+            T st[4];
+            face_state<T>(ui, g, cs.r[k][0], cs.r[k][1], cs.r[k][2], st);
+            const int q = (int)(base + (int64_t)k * kSlice - e0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) lst[v][q] = (TA)st[v];
+        }
+    }
+    T gar[kRounds][4];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) load4(geo.sg(3, e0 + (pk[r] >= 0 ? (pk[r] & 0xffff) : 0)), gar[r]);
+    __syncthreads();
+    // the states of the cell's cross-tile sides (still in LDS: the face
+    // phase overwrites interior sides only) to their boundary items
+    {
+        SliceItems si;
+        si.init(bm);
+        if (bm) {
+            const int64_t item0 = tf.bnd_sptr[i / kSlice];
+            const int64_t base = (i / kSlice) * (DEG * kSlice) + (i % kSlice);
+#pragma unroll
+            for (int k = 0; k < DEG; ++k) {
+                if (!((bm >> k) & 1u)) continue;
+                const int q = (int)(base + (int64_t)k * kSlice - e0);
+                const int64_t it = item0 + si.rank(k);
+                T st[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) st[v] = (T)lst[v][q];
+                store4_stream(BSb + it * 4, st);
+                BNb[it] = nv;
+            }
+        }
+    }
+    int cAdmN = 0, cAdmF = 0, cCap = 0;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if (pk[r] < 0) continue;
+        const int ql = pk[r] & 0xffff, qr = pk[r] >> 16;
+        const T* ga = gar[r];
+        TA sL[4], sR[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            sL[v] = lst[v][ql];
+            sR[v] = lst[v][qr];
+        }
+        const TA A = (TA)ga[0];
+        int aN = 0, aF = 0;
+        TA Phi[4];
+        const bool capped = face_flux<TA, TA>(sL, sR, lnv[tile_cell_of(ql)], lnv[tile_cell_of(qr)], (TA)1, (TA)1,
+                                             (TA)ga[1], (TA)ga[2], (TA)ga[3], A, cdt, Phi, aN, aF);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const TA ph = mul_nc(A, Phi[v]);
+            lst[v][ql] = ph;
+            lst[v][qr] = -ph;
+        }
+        cAdmN += aN;
+        cAdmF += aF;
+        cCap += capped ? 1 : 0;
+    }
+    const uint64_t packed = (uint64_t)cAdmN | ((uint64_t)cAdmF << 21) | ((uint64_t)cCap << 42);
+    const uint64_t spk = wave_sum(packed);
+    if ((tid & 63) == 0) lcnt[tid >> 6] = spk;
+    __syncthreads();
+    if (i < nc) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
+#pragma unroll
+        for (int k = 0; k < DEG; ++k) {
+            if ((bm >> k) & 1u) continue;
+            const int q = (int)(base + (int64_t)k * kSlice - e0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += (double)lst[v][q];
+        }
+        double* ps = PS + ((int64_t)b * nc + i) * 4;
+        *reinterpret_cast<double2*>(ps) = make_double2(acc[0], acc[1]);
+        *reinterpret_cast<double2*>(ps + 2) = make_double2(acc[2], acc[3]);
+    }
+    if (tid == 0) {
+        constexpr uint64_t kField = (1ull << 21) - 1;
+        uint64_t c = 0;
+        for (int w = 0; w < kTileThreads / 64; ++w) c += lcnt[w];
+        add_counts(part_cnt, n_blocks, (t * kTileSlices) * nb + b, (int64_t)(c & kField),
+                   (int64_t)((c >> 21) & kField), (int64_t)((c >> 42) & kField), 0, 0, 0, part_status);
+    }
+}
+
+// Products of the boundary items live in dynamic LDS, bnd_max records of
+// four TA per workgroup, at the item's index relative to the tile's first.
+template <typename T, typename TA>
+__global__ __launch_bounds__(kTileThreads) void k_flux_tile(
+    const T* __restrict__ U, const T* __restrict__ BS, const T* __restrict__ BN, const double* __restrict__ PS,
+    T* __restrict__ Unew, int64_t nc, int nb, const T* __restrict__ vol, const T* __restrict__ bgeo,
+    TileFaceView tf, TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
+    int32_t* __restrict__ part_status, int64_t n_blocks) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    TA* lph = reinterpret_cast<TA*>(lds_raw);
+    __shared__ uint64_t lcnt[kTileThreads / 64];     // packed face counts per wavefront
+    constexpr int DEG = 6;
+    const uint32_t blk32 = xcd_logical_block32();
+    const int b = (int)(blk32 % (uint32_t)nb);
+    const int64_t t = blk32 / (uint32_t)nb;
+    const int tid = threadIdx.x;
+    const int64_t c0 = t * kTileCells;
+    const int64_t i = c0 + tid;
+    const int64_t ic = i < nc ? i : nc - 1;
+    const T* BSb = BS + (int64_t)b * tf.n_bnd * 4;
+    const T* BNb = BN + (int64_t)b * tf.n_bnd;
+    // the cell's inputs of the update, requested before the face work
+    T ui[4];
+    load4(U + urec(b, nc, ic), ui);
+    const T vi = vol[ic];
+    const uint32_t bm = i < nc ? tf.bmask[i] : 0u;
+    const int32_t item0 = tf.bnd_sptr[ic / kSlice];
+    const double* ps = PS + ((int64_t)b * nc + ic) * 4;
+    const double2 ps01 = *reinterpret_cast<const double2*>(ps);
+    const double2 ps23 = *reinterpret_cast<const double2*>(ps + 2);
+    int cAdmN = 0, cAdmF = 0, cCap = 0;
+    const int32_t it0 = tf.bnd_ptr[t], it1 = tf.bnd_ptr[t + 1];
+    for (int32_t it = it0 + tid; it < it1; it += kTileThreads) {
+        const int32_t os = tf.bnd_opp[it];
+        const bool isL = os >= 0;
+        const int64_t o = isL ? os : ~os;
+        T ga[4], so[4], sn[4];
+        load4(bgeo + (int64_t)it * 4, ga);
+        load4(BSb + (int64_t)it * 4, so);
+        load4(BSb + o * 4, sn);
+        const T ni = BNb[it], nj = BNb[o];
+        __builtin_amdgcn_sched_barrier(0);
+        TA sL[4], sR[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            sL[v] = (TA)(isL ? so[v] : sn[v]);
+            sR[v] = (TA)(isL ? sn[v] : so[v]);
+        }
+        const TA A = (TA)ga[0];
+        int aN = 0, aF = 0;
+        TA Phi[4];
+        const bool capped = face_flux<TA, TA>(sL, sR, (TA)(isL ? ni : nj), (TA)(isL ? nj : ni), (TA)1, (TA)1,
+                                             (TA)ga[1], (TA)ga[2], (TA)ga[3], A, cdt, Phi, aN, aF);
+        const TA sA = isL ? A : -A;
+        TA* dst = lph + (int64_t)(it - it0) * 4;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[v] = mul_nc(sA, Phi[v]);
+        if (isL) {
+            cAdmN += aN;
+            cAdmF += aF;
+            cCap += capped ? 1 : 0;
+        }
+    }
+    const uint64_t packed = (uint64_t)cAdmN | ((uint64_t)cAdmF << 21) | ((uint64_t)cCap << 42);
+    const uint64_t spk = wave_sum(packed);
+    if ((tid & 63) == 0) lcnt[tid >> 6] = spk;
+    SliceItems si;
+    si.init(bm);
+    __syncthreads();
+    int cGN = 0, cGF = 0, status = 0;
+    double nv = 0.0;
+    if (i < nc) {
+        double acc[4] = {ps01.x, ps01.y, ps23.x, ps23.y};
+#pragma unroll
+        for (int k = 0; k < DEG; ++k) {
+            if (!((bm >> k) & 1u)) continue;
+            const TA* src = lph + (int64_t)(item0 - it0 + si.rank(k)) * 4;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += (double)src[v];
+        }
+        update_cell_v<T, TA>(i, b, nc, ui, vi, acc, cdt, Unew, nv, cGN, cGF, status);
+    }
+    // photon sum, guards and status per slice; the face counts of the tile
+    // to its first slice
+    const int64_t sl = c0 / kSlice + tid / kSlice;
+    if (sl * kSlice < nc) wave_partials(nv, 0, 0, 0, cGN, cGF, status, sl * nb + b, part_nv, part_cnt, part_status,
+                                        n_blocks);
+    if (tid == 0) {
+        constexpr uint64_t kField = (1ull << 21) - 1;
+        uint64_t c = 0;
+        for (int w = 0; w < kTileThreads / 64; ++w) c += lcnt[w];
+        add_counts(part_cnt, n_blocks, (t * kTileSlices) * nb + b, (int64_t)(c & kField),
+                   (int64_t)((c >> 21) & kField), (int64_t)((c >> 42) & kField), 0, 0, 0, part_status);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_transport: gradients, face states and fluxes of one 256-cell tile and
 // one bin in a single launch, with the face states in LDS instead of HBM.
 // The work items are the tile's cells (all their sides) and its halo cells
@@ -682,7 +956,17 @@ __global__ __launch_bounds__(kTileThreads) void k_transport(const T* __restrict_
         T ui[4];
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         load4(U + urec(b, nc, i), ui);
-        if constexpr (DEG > 0) {
+        if constexpr (DEG == 6) {
+            // the tile-interior faces first, then the cross-tile ones, each in
+            // slot order: the order of the split path on six-slot meshes
+            CellFaces<T, DEG> cf;
+            load_cell_faces<T, DEG>(i, geo, sell, cf);
+            const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
+            const uint32_t bm = tile.bmask[i];
+            cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, base, cf, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap,
+                                        ~bm & 0x3fu);
+            cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, base, cf, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap, bm);
+        } else if constexpr (DEG > 0) {
             CellFaces<T, DEG> cf;
             load_cell_faces<T, DEG>(i, geo, sell, cf);
             cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, (int64_t)sell.ptr[i / kSlice] + (i % kSlice), cf, cdt,
@@ -949,6 +1233,27 @@ void launch_flux(const T* U, const T* FV, const T* NC, T* Unew, int64_t nc, int 
     }
 }
 
+template <typename T>
+void launch_facestate_tile(const T* U, T* BS, T* BN, double* PS, int64_t nc, int nb, const GeomView<T>& geo,
+                           const SellView& sell, const TileFaceView& tf, int use_limiter, double cdt,
+                           int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
+    const int64_t nblk = partial_blocks(nc, nb);
+    const int64_t grid = (int64_t)grid_for(nc, kTileCells) * nb;
+    hipLaunchKernelGGL((k_facestate_tile<T, T>), dim3((unsigned)grid), dim3(kTileThreads), 0, s, U, BS, BN, PS, nc,
+                       nb, geo, sell, tf, use_limiter, (T)cdt, part_cnt, part_status, nblk);
+}
+
+template <typename T>
+void launch_flux_tile(const T* U, const T* BS, const T* BN, const double* PS, T* Unew, int64_t nc, int nb,
+                      const T* vol, const T* bgeo, const TileFaceView& tf, double cdt, double* part_nv,
+                      int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
+    const int64_t nblk = partial_blocks(nc, nb);
+    const int64_t grid = (int64_t)grid_for(nc, kTileCells) * nb;
+    const size_t lds = (size_t)(tf.bnd_max > 0 ? tf.bnd_max : 1) * 4 * sizeof(T);   // at most 6 kTileCells items
+    hipLaunchKernelGGL((k_flux_tile<T, T>), dim3((unsigned)grid), dim3(kTileThreads), lds, s, U, BS, BN, PS, Unew, nc,
+                       nb, vol, bgeo, tf, (T)cdt, part_nv, part_cnt, part_status, nblk);
+}
+
 template <typename T, int D>
 static void launch_transport_deg(const T* U, T* Unew, int64_t nc, int nb, const GeomView<T>& geo,
                                  const SellView& sell, const TileView& tile, size_t lds_bytes, int use_limiter,
@@ -1011,6 +1316,12 @@ void launch_set_fields(T* U, const double* X, double* Ue, int64_t nc, int nb, in
                                  double, const double*, const double*, int64_t*, int64_t*, int32_t*, int32_t*,     \
                                  hipStream_t);                                                                      \
     template void launch_facestate<T>(const T*, T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, int, \
+                                      hipStream_t);                                                                \
+    template void launch_facestate_tile<T>(const T*, T*, T*, double*, int64_t, int, const GeomView<T>&,           \
+                                           const SellView&, const TileFaceView&, int, double, int64_t*, int32_t*,  \
+                                           hipStream_t);                                                           \
+    template void launch_flux_tile<T>(const T*, const T*, const T*, const double*, T*, int64_t, int, const T*,     \
+                                      const T*, const TileFaceView&, double, double*, int64_t*, int32_t*,          \
                                       hipStream_t);                                                                \
     template void launch_flux<T>(const T*, const T*, const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, \
                                  double, double*, int64_t*, int32_t*, int64_t, int64_t, hipStream_t);               \

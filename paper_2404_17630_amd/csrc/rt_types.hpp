@@ -83,6 +83,26 @@ struct SellView {
     int32_t uniform_deg;   // slots of every slice when all are equal and specialised (6, 14), else 0
 };
 
+// Faces of the split transport on six-slot meshes by tile (rt_mesh
+// tpair/tbnd/bmask): the tile-interior faces, as (L, R) entries relative to
+// the tile's first entry in the low and high 16 bits; the face sides whose
+// face crosses to another tile ("boundary items", numbered in entry order,
+// so a tile's and a slice's items are contiguous: bnd_ptr per tile,
+// bnd_sptr per slice), with the opposite side's item (complemented for an
+// R side); per cell the slots of cross-tile faces.  Within a slice the
+// items of a cell follow from the slot masks of the slice's cells:
+// slot-major, then lane order.
+struct TileFaceView {
+    const int32_t* pair_ptr;
+    const int32_t* pair;
+    const int32_t* bnd_ptr;
+    const int32_t* bnd_sptr;
+    const int32_t* bnd_opp;
+    const uint8_t* bmask;
+    int64_t n_bnd;          // boundary items of the mesh
+    int64_t bnd_max;        // most boundary items of one tile
+};
+
 // A face whose two sides are in one slice is evaluated once there, from its
 // L side; the item carries this bit and the R side takes the negated
 // product.  Entries stay below 2^30 (rt_mesh_create), so the bit is free.
@@ -116,6 +136,7 @@ struct TileView {
     const int32_t* hside_ptr;
     const int32_t* hside_entry;
     int64_t n_slices;
+    const uint8_t* bmask;   // six-slot meshes: per cell the slots of cross-tile faces (else null)
 };
 
 // Workgroup id -> logical block: hardware hands workgroups to the 8 XCDs in

@@ -30,7 +30,7 @@ RT_DEVICE_HOST_ONLY = -1
 RT_TILE_CELLS = 256
 RT_NOALLOC_SCRATCH_MB = 64
 TABLES = ("nbr", "fsf", "opp", "sptr", "sdeg", "lds_opp", "halo_ptr", "halo_cell", "hside_ptr", "hside_entry",
-          "fitem_ptr", "fitem")
+          "fitem_ptr", "fitem", "tpair_ptr", "tpair", "tbnd_ptr", "tbnd", "tbnd_sptr")
 
 ERROR_NAMES = {RT_EINVAL: "RT_EINVAL", RT_EMESH: "RT_EMESH", RT_ESTATE: "RT_ESTATE", RT_EDEVICE: "RT_EDEVICE",
                RT_ENOMEM: "RT_ENOMEM", RT_ENUMERIC: "RT_ENUMERIC"}

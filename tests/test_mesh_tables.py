@@ -153,6 +153,58 @@ def test_flux_items_evaluate_every_face_side_once(mesh):
         assert np.array_equal(got, valid.astype(int)), s
 
 
+def test_tile_faces_cover_every_face_side_once(mesh):
+    """The split transport's faces by 256-cell tile on six-slot meshes: a
+    face whose two sides are in one tile is listed once, as the (L, R) entry
+    pair relative to the tile's first entry; every other face side is a
+    boundary item, numbered in entry order, listed as (entry, opposite
+    side's item, complemented for an R side), with the first item of every
+    tile and slice.  Together they give every face side of the mesh its
+    product exactly once, and the items of a cell follow from the slot masks
+    of its slice as the kernels rank them (slot-major, then lane)."""
+    m, tabs = mesh
+    nc = m["n_cells"]
+    sdeg, nbr, fsf, opp = tabs["sdeg"], tabs["nbr"], tabs["fsf"], tabs["opp"]
+    pptr, pair, bptr, bnd = tabs["tpair_ptr"], tabs["tpair"], tabs["tbnd_ptr"], tabs["tbnd"].reshape(-1, 2)
+    sptr_b = tabs["tbnd_sptr"]
+    six = sdeg.size > 0 and np.all(sdeg == 6) and np.all(np.bincount(m["face_cells"].ravel(), minlength=nc) == 6)
+    if not six:
+        assert pptr.size == 0 and pair.size == 0 and bptr.size == 0 and bnd.size == 0 and sptr_b.size == 0
+        return
+    per, sper = 6 * TILE, 6 * SLICE
+    nt, ns = (nc + TILE - 1) // TILE, sdeg.size
+    assert pptr.size == nt + 1 and bptr.size == nt + 1 and sptr_b.size == ns + 1
+    assert pptr[0] == 0 and pptr[-1] == pair.size and bptr[0] == 0 and bptr[-1] == bnd.shape[0]
+    assert np.array_equal(bptr, sptr_b[np.minimum(np.arange(nt + 1) * TILE_SLICES, ns)])
+    assert np.all(np.diff(bnd[:, 0]) > 0)                      # entry order
+    got = np.zeros(nbr.size, int)
+    for t in range(nt):
+        e0 = t * per
+        for p in pair[pptr[t]:pptr[t + 1]]:
+            ql, qr = int(p) & 0xffff, int(p) >> 16
+            assert fsf[e0 + ql] >= 0 and fsf[e0 + qr] < 0 and opp[e0 + ql] == e0 + qr
+            got[e0 + ql] += 1
+            got[e0 + qr] += 1
+        for q in range(bptr[t], bptr[t + 1]):
+            e, os_ = bnd[q]
+            assert e // per == t and opp[e] // per != t
+            o = os_ if fsf[e] >= 0 else ~os_
+            assert bnd[o, 0] == opp[e] and bnd[o, 1] == (~q if fsf[e] >= 0 else q)
+            got[e] += 1
+    assert np.array_equal(got, (nbr >= 0).astype(int))
+    # the kernels' ranking: per slice, slot-major then lane, from the masks
+    item_of = {int(e): q for q, e in enumerate(bnd[:, 0])}
+    for s in range(ns):
+        r = sptr_b[s]
+        for k in range(6):
+            for lane in range(SLICE):
+                e = s * sper + k * SLICE + lane
+                if e in item_of:
+                    assert item_of[e] == r
+                    r += 1
+        assert r == sptr_b[s + 1]
+
+
 def test_hilbert_slice_of_a_lattice_evaluates_240_sides():
     m = rtgen.jittered_lattice((8, 8, 8), 1.0, 0.2, 3, "hilbert").as_dict()
     h = rt.Mesh(m, device=rt.RT_DEVICE_HOST_ONLY)
