@@ -112,19 +112,24 @@ __device__ inline void face_state(const double* ui, const double (*g)[3], double
 
 // Barth-Jespersen factor alpha = min(1, min_k psi_k) of one variable, with
 // psi_k = (u_max - u_i) / delta_k for delta_k = g . r_k > 0 and
-// (u_min - u_i) / delta_k for delta_k < 0 (Sec. 2.3.2).  Each psi_k is kept
-// as a fraction num / den with den > 0, so choosing the smallest takes no
-// division (num_k den < num den_k); one division gives alpha at the end.
+// (u_min - u_i) / delta_k for delta_k < 0 (Sec. 2.3.2).  All psi_k of one
+// sign of delta_k share their numerator (u_max - u_i >= 0, or u_i - u_min),
+// so the smallest is the one of the largest |delta_k|: only the largest
+// positive and the largest negative extrapolation are kept (add), and
+// alpha is the smaller of their two fractions and 1, chosen without
+// dividing (n1 d2 < n2 d1), with one division at the end.
 struct BJFactor {
-    double num = 1.0, den = 1.0;
-    __device__ void add(double delta, double up, double down) {  // up = u_max - u_i, down = u_i - u_min
-        double n, d;
-        if (delta > 0.0) { n = up; d = delta; }
-        else if (delta < 0.0) { n = down; d = -delta; }
-        else return;
-        if (n * den < num * d) { num = n; den = d; }
+    double dpos = 0.0, dneg = 0.0;     // max over delta_k > 0 of delta_k, of -delta_k over delta_k < 0
+    __device__ void add(double delta) {
+        dpos = fmax(dpos, delta);
+        dneg = fmax(dneg, -delta);
     }
-    __device__ double alpha() const { return num / den; }
+    __device__ double alpha(double up, double down) const {   // up = u_max - u_i, down = u_i - u_min
+        double num = 1.0, den = 1.0;
+        if (dpos > 0.0 && up * den < num * dpos) { num = up; den = dpos; }
+        if (dneg > 0.0 && down * den < num * dneg) { num = down; den = dneg; }
+        return num / den;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -239,8 +244,10 @@ __device__ inline void limited_gradient_c(int64_t i, int b, int64_t nc, const T*
                 bs[v][0] += w0 * dphi;
                 bs[v][1] += w1 * dphi;
                 bs[v][2] += w2 * dphi;
-                umax[v] = fmax(uj[q][v], umax[v]);
-                umin[v] = fmin(uj[q][v], umin[v]);
+                // (compare and select: a NaN neighbour leaves the extrema
+                // as fmax/fmin would, without their operand quieting)
+                umax[v] = uj[q][v] > umax[v] ? uj[q][v] : umax[v];
+                umin[v] = uj[q][v] < umin[v] ? uj[q][v] : umin[v];
             }
         }
     }
@@ -258,12 +265,11 @@ __device__ inline void limited_gradient_c(int64_t i, int b, int64_t nc, const T*
         if (cs.nbr[k] < 0) continue;
         const double r0 = cs.r[k][0], r1 = cs.r[k][1], r2 = cs.r[k][2];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2, (double)umax[v] - ui[v], ui[v] - (double)umin[v]);
+        for (int v = 0; v < 4; ++v) bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const double alpha = bj[v].alpha();
+        const double alpha = bj[v].alpha((double)umax[v] - ui[v], ui[v] - (double)umin[v]);
         g[v][0] *= alpha;
         g[v][1] *= alpha;
         g[v][2] *= alpha;
@@ -370,8 +376,8 @@ __device__ inline void limited_gradient_s(int64_t i, int b, int64_t nc, const T*
             bs[v][0] += w0 * dphi;
             bs[v][1] += w1 * dphi;
             bs[v][2] += w2 * dphi;
-            umax[v] = fmax(uj[v], umax[v]);
-            umin[v] = fmin(uj[v], umin[v]);
+            umax[v] = uj[v] > umax[v] ? uj[v] : umax[v];
+            umin[v] = uj[v] < umin[v] ? uj[v] : umin[v];
         }
     }
     T c[8];
@@ -398,12 +404,11 @@ __device__ inline void limited_gradient_s(int64_t i, int b, int64_t nc, const T*
             r0 = geo.sv(kSR0, e); r1 = geo.sv(kSR1, e); r2 = geo.sv(kSR2, e);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2, (double)umax[v] - ui[v], ui[v] - (double)umin[v]);
+        for (int v = 0; v < 4; ++v) bj[v].add(g[v][0] * r0 + g[v][1] * r1 + g[v][2] * r2);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const double alpha = bj[v].alpha();
+        const double alpha = bj[v].alpha((double)umax[v] - ui[v], ui[v] - (double)umin[v]);
         g[v][0] *= alpha;
         g[v][1] *= alpha;
         g[v][2] *= alpha;
