@@ -13,6 +13,19 @@
 namespace rtk {
 
 template <int K>
+struct Dual;
+
+// Whether a scalar type carries derivative parts.
+template <typename R>
+struct IsDualT {
+    static constexpr bool value = false;
+};
+template <int K>
+struct IsDualT<Dual<K>> {
+    static constexpr bool value = true;
+};
+
+template <int K>
 struct Dual {
     double v;
     double d[K];

@@ -55,21 +55,34 @@ __device__ inline void radiation_pressure_n(const R* U, G n0, G n1, G n2, R* P) 
         P[0] = third * n0; P[1] = third * n1; P[2] = third * n2;
         return;
     }
-    // D = (1 - chi)/2 I + (3 chi - 1)/2 u u with the unit vector u = Fh / |Fh|
-    // (dividing by |Fh| rather than |Fh|^2 keeps the derivative finite down to
-    // the smallest |Fh| whose square is still nonzero).
-    const R Fm = m_sqrt(F2);
-    R f = Fm / N;
-    if (val(f) > 1) f = R(G(1));
-    const R f2 = f * f;
-    const R chi = (G(3) + G(4) * f2) / (G(5) + G(2) * m_sqrt(G(4) - G(3) * f2));
-    const R iso = G(0.5) * (G(1) - chi);
-    const R iFm = G(1) / Fm;
-    const R u0 = U[1] * iFm, u1 = U[2] * iFm, u2 = U[3] * iFm;
-    const R dir = G(0.5) * (G(3) * chi - G(1)) * (u0 * n0 + u1 * n1 + u2 * n2);
-    P[0] = N * (iso * n0 + dir * u0);
-    P[1] = N * (iso * n1 + dir * u1);
-    P[2] = N * (iso * n2 + dir * u2);
+    // D = (1 - chi)/2 I + (3 chi - 1)/2 u u with the unit vector u = Fh / |Fh|;
+    // chi depends on f^2 = |Fh|^2 / N^2 only, and (u . n) u = (Fh . n) Fh /
+    // |Fh|^2, so the values need no square root of |Fh|^2.  On duals u is
+    // formed by dividing by |Fh| rather than |Fh|^2, which keeps the
+    // derivative finite down to the smallest |Fh| whose square is nonzero.
+    if constexpr (IsDualT<R>::value) {
+        const R Fm = m_sqrt(F2);
+        R f = Fm / N;
+        if (val(f) > 1) f = R(G(1));
+        const R f2 = f * f;
+        const R chi = (G(3) + G(4) * f2) / (G(5) + G(2) * m_sqrt(G(4) - G(3) * f2));
+        const R iso = G(0.5) * (G(1) - chi);
+        const R iFm = G(1) / Fm;
+        const R u0 = U[1] * iFm, u1 = U[2] * iFm, u2 = U[3] * iFm;
+        const R dir = G(0.5) * (G(3) * chi - G(1)) * (u0 * n0 + u1 * n1 + u2 * n2);
+        P[0] = N * (iso * n0 + dir * u0);
+        P[1] = N * (iso * n1 + dir * u1);
+        P[2] = N * (iso * n2 + dir * u2);
+    } else {
+        R f2 = F2 / (N * N);
+        if (val(f2) > 1) f2 = R(G(1));
+        const R chi = (G(3) + G(4) * f2) / (G(5) + G(2) * m_sqrt(G(4) - G(3) * f2));
+        const R iso = G(0.5) * (G(1) - chi);
+        const R dir = G(0.5) * (G(3) * chi - G(1)) * (U[1] * n0 + U[2] * n1 + U[3] * n2) / F2;
+        P[0] = N * (iso * n0 + dir * U[1]);
+        P[1] = N * (iso * n1 + dir * U[2]);
+        P[2] = N * (iso * n2 + dir * U[3]);
+    }
 }
 
 template <typename R, typename G>
