@@ -37,13 +37,36 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, nc: int, nb: int, nf: int, n_sides: int, n_src: int, p: int, g: int) -> float:
+def tile_counts(mesh):
+    """(boundary items, tile-interior faces) of the split transport by
+    256-cell tile, which the library uses on six-slot meshes; None on other
+    meshes."""
+    n_bnd, n_pairs = mesh.table("tbnd").size // 2, mesh.table("tpair").size
+    return (n_bnd, n_pairs) if n_bnd + n_pairs > 0 else None
+
+
+def algorithmic_bytes(kernel: str, nc: int, nb: int, nf: int, n_sides: int, n_src: int, p: int, g: int,
+                      tile=None) -> float:
     """This design's compulsory HBM bytes of one launch: every array element
     the kernel must read or write, counted once (a neighbour's record
     gathered by several cells, and geometry re-read for each bin, are counted
     once).  p = bytes per transport value, g = bytes per geometry value;
-    indices are 4 bytes.  Face sides per cell: n_sides / nc.  The flux
-    figure is that of the slot-parallel kernel of uniform-degree meshes."""
+    indices are 4 bytes.  Face sides per cell: n_sides / nc.  tile = (n_bnd,
+    n_pairs) on six-slot meshes, where the split path runs by tile; else the
+    figures are those of the per-slice kernels."""
+    if tile is not None and kernel in ("k_facestate", "k_flux"):
+        n_bnd, n_pairs = tile
+        if kernel == "k_facestate":
+            # fields in; the cell's FP64 sum over its tile-interior faces out
+            # (4 doubles); each boundary item's state and cap numerator out;
+            # cell record, per side weight, offset and neighbour, the slot
+            # mask; per interior face its (L, R) pair and A, n
+            return (nb * (4 * nc * p + 32 * nc + 5 * n_bnd * p) + nc * (8 * g + 1) + n_sides * (6 * g + 4)
+                    + n_pairs * (4 + 4 * g))
+        # fields in and out, the interior sums in; each boundary item's own
+        # and opposite state and cap numerator; V and the slot mask per cell;
+        # per item the opposite position and A, n
+        return nb * (8 * nc * p + 32 * nc + 10 * n_bnd * p) + nc * (g + 1) + n_bnd * (4 + 4 * g)
     if kernel == "k_facestate":
         # fields (4) in, one 4-value face state per face side out, the cell's
         # cap numerator N V / n_faces out; cell record (M^-1, V, V/n_f), per
@@ -310,13 +333,15 @@ def main() -> int:
                                          profile=True)
     st_p.close()
 
-    def kernel_table(prof, p, g):
+    tiles = tile_counts(mesh)
+
+    def kernel_table(prof, p, g, tile=tiles):
         tab = {}
         for name, (launches, ms) in prof.items():
             if launches == 0:
                 continue
             avg = ms / launches
-            algo = algorithmic_bytes(name, nc, nb, nf, n_sides, n_src_cells, p, g)
+            algo = algorithmic_bytes(name, nc, nb, nf, n_sides, n_src_cells, p, g, tile)
             model = model_bytes_per_cell(name, nb, p, g) * nc
             tab[name] = dict(launches=launches, avg_ms=avg, algo_bytes=algo,
                              gbs=algo / (avg * 1e-3) / 1e9 if algo else None,
@@ -327,13 +352,14 @@ def main() -> int:
     dominant = max((k for k in kt_mixed if k != "k_reduce"), key=lambda k: kt_mixed[k]["avg_ms"] * kt_mixed[k]["launches"])
     dk = kt_mixed[dominant]
 
-    traffic = None
+    traffic = valu_busy = None
     if TRAFFIC_FILE.exists():
         rec = json.loads(TRAFFIC_FILE.read_text())
         ent = rec.get("kernels", {}).get(dominant)
         if ent and rec.get("source_digest") == kernel_source_digest() and rec.get("workload") == f"throughput_{args.n}" \
                 and args.order == "hilbert":
             traffic = ent["bytes_per_launch"]
+            valu_busy = ent.get("valu_busy")
     model_bpc = model_bytes_per_cell(dominant, nb, 4, 4)
     step_model = subcycle_bytes_per_cell(nb, 4, 4)
 
@@ -360,7 +386,9 @@ def main() -> int:
                      "unit": "GB/s", "frac": dk["model_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_cell": model_bpc, "avg_ms": dk["avg_ms"],
                      "design_bytes_per_launch": dk["algo_bytes"], "design_achieved": dk["gbs"],
-                     "traffic_over_model": traffic / (model_bpc * nc) if traffic else None},
+                     "traffic_over_model": traffic / (model_bpc * nc) if traffic else None,
+                     # share of SIMD cycles issuing VALU instructions (SQ counters, same kernel digest)
+                     "valu_busy": valu_busy},
         "subcycle_roofline": {
             name: {"bytes_per_cell": b, "GB/s": b * nc / (t_mixed / args.steps) / 1e9,
                    "frac": b * nc / (t_mixed / args.steps) / 1e9 / HBM_PEAK_GBS}
@@ -441,8 +469,8 @@ def main() -> int:
         out["random_order_value"] = nc * nb * args.steps / t_r
         st_r, _, prof_r = timed_run(rt, mesh_r, cfg_r, rt.RT_MIXED, 20, 0, torch, profile=True)
         st_r.close()
+        out["kernels_mixed_random"] = kernel_table(prof_r, 4, 4, tile_counts(mesh_r))
         mesh_r.close()
-        out["kernels_mixed_random"] = kernel_table(prof_r, 4, 4)
         del cfg_r
         out["adjoint_262k"] = adjoint_timing(rt, torch)
     else:

@@ -227,6 +227,13 @@ void rt_mesh::build_tile_faces() {
         tbnd_max = std::max<int64_t>(tbnd_max, tbnd_ptr[t + 1] - tbnd_ptr[t]);
     }
     for (int64_t s = 0; s < ns; ++s) tbnd_sptr[s + 1] += tbnd_sptr[s];
+    // The tile split pays off when tiles are compact (a Hilbert-ordered
+    // lattice has about one cross-tile side per cell); with more than two a
+    // cell (an unordered mesh: up to all six) the per-slice kernels are used.
+    if (n_items > 2 * nc) {
+        tpair_ptr.clear(); tpair.clear(); tbnd_ptr.clear(); tbnd.clear(); tbnd_sptr.clear(); bmask.clear();
+        return;
+    }
     // the opposite side of a boundary item is a boundary item of its own tile
     for (int32_t q = 0; q < n_items; ++q) {
         const int32_t e = tbnd[2 * q];
@@ -745,7 +752,7 @@ int rt_state::ensure_face_states() {
     const size_t n = std::max((size_t)nb * 4 * mesh->n_entries + (size_t)nb * nc, (size_t)nb * 5 * mesh->n_bnd());
     int rc = FV.alloc(n * tbytes());
     // six-slot meshes: the per-cell sums over tile-interior faces
-    if (!rc && mesh->uniform_deg == 6) rc = PS.alloc((size_t)nb * nc * 4 * 8);
+    if (!rc && !mesh->tpair_ptr.empty()) rc = PS.alloc((size_t)nb * nc * 4 * 8);
     return rc;
 }
 
@@ -1115,7 +1122,7 @@ static TileFaceView rt_tile_faces(const rt_mesh* m) {
 // Whether the split path of a state runs by tile (six-slot meshes): the
 // face-state pass then also evaluates the tile-interior faces, and the flux
 // pass needs its sums.
-static bool tile_split(const rt_state* s) { return s->mesh->uniform_deg == 6 && s->PS.ptr; }
+static bool tile_split(const rt_state* s) { return !s->mesh->tpair_ptr.empty() && s->PS.ptr; }
 
 void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, double dt, bool all_states) {
     s->prof_begin(RT_KERNEL_GRADIENT, st);

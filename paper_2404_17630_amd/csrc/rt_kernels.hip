@@ -962,10 +962,17 @@ __global__ __launch_bounds__(kTileThreads) void k_transport(const T* __restrict_
             CellFaces<T, DEG> cf;
             load_cell_faces<T, DEG>(i, geo, sell, cf);
             const int64_t base = (int64_t)sell.ptr[i / kSlice] + (i % kSlice);
-            const uint32_t bm = tile.bmask[i];
-            cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, base, cf, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap,
-                                        ~bm & 0x3fu);
-            cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, base, cf, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap, bm);
+            const uint32_t bm = tile.bmask ? tile.bmask[i] : 0u;     // none: the per-slice kernels' slot order
+            TA prod[DEG][4];
+            cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, base, cf, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap, prod);
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+                for (int k = 0; k < DEG; ++k) {
+                    if (cf.nbr[k] < 0 || (int)((bm >> k) & 1u) != pass) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[v] += (double)prod[k][v];
+                }
         } else if constexpr (DEG > 0) {
             CellFaces<T, DEG> cf;
             load_cell_faces<T, DEG>(i, geo, sell, cf);

@@ -276,14 +276,15 @@ __device__ inline void limited_gradient_c(int64_t i, int b, int64_t nc, const T*
     }
 }
 
-// Flux sum of cell i (bin b) from its loaded face records (DEG > 0).
-// Only the slots set in `mask` are added (all by default), so the fused
-// kernel can add a cell's tile-interior faces before its cross-tile ones, in
-// the order of the split path.
+// Flux sum of cell i (bin b) from its loaded face records (DEG > 0).  With
+// `prod` the products sigma A Phi of the slots are stored there instead of
+// added (a padding slot's are left unset), so that the fused kernel can add
+// a cell's tile-interior faces before its cross-tile ones, in the order of
+// the split path.
 template <typename T, typename TA, int DEG, typename FS>
 __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __restrict__ U, const FS& fsv,
                                        int64_t base, const CellFaces<T, DEG>& cf, TA cdt, TA Ni, double* acc,
-                                       int& cAdmN, int& cAdmF, int& cCap, uint32_t mask = ~0u) {
+                                       int& cAdmN, int& cAdmF, int& cCap, TA (*prod)[4] = nullptr) {
     // The face records, the two face states and the neighbour's N of a
     // batch of slots are all requested before the batch's first flux is
     // computed, so the gathers overlap (a padding slot reads its own entry
@@ -309,7 +310,7 @@ __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __
             const int k = k0 + q;
             if (k >= DEG) break;
             const int32_t j = cf.nbr[k];
-            if (j < 0 || !((mask >> k) & 1u)) continue;
+            if (j < 0) continue;
             const bool isL = cf.isL[k];
             const TA A = (TA)ga[q][0];
             const TA Nj = (TA)nj[q];
@@ -330,7 +331,11 @@ __device__ inline void cell_flux_sum_c(int64_t i, int b, int64_t nc, const T* __
             }
             const TA sA = isL ? A : -A;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] += (double)mul_nc(sA, Phi[v]);
+            for (int v = 0; v < 4; ++v) {
+                const TA p = mul_nc(sA, Phi[v]);
+                if (prod) prod[k][v] = p;
+                else acc[v] += (double)p;
+            }
         }
     }
 }
