@@ -141,3 +141,49 @@ def test_variable_degree_mesh_fused_equals_split(precision):
     assert a["fused"] and not b["fused"]
     for key in ("N", "F", "species", "T"):
         assert np.array_equal(a[key], b[key]), key
+
+
+def open_slab_cfg(precision="fp64"):
+    """H+He on a 12 x 12 x 10 jittered lattice, periodic in x and y and open
+    in z (box_z = 0): the faces that would close the lattice across z are
+    dropped, so the cells of the two z layers have five faces and nothing
+    flows out through them."""
+    cfg = rtgen.cosmological(0, 1.0, 1.0, 6, 0.01, 6, 4, dims=(12, 12, 10), name="open_slab", precision=precision)
+    m = dict(cfg["mesh"])
+    h = float(np.cbrt(m["volume"][0]))
+    zc = np.floor(np.asarray(m["centre"])[2] / h).astype(np.int64)
+    L, R = m["face_cells"]
+    keep = ~((np.asarray(m["normal"])[2] == 1.0) & (zc[L] == 9) & (zc[R] == 0))
+    m.update(n_faces=int(keep.sum()), face_cells=np.ascontiguousarray(m["face_cells"][:, keep]),
+             area=np.ascontiguousarray(m["area"][keep]), normal=np.ascontiguousarray(m["normal"][:, keep]),
+             face_centre=np.ascontiguousarray(m["face_centre"][:, keep]),
+             box=np.array([m["box"][0], m["box"][1], 0.0]))
+    cfg["mesh"] = m
+    return cfg
+
+
+def test_open_boundary_fp64_matches_oracle():
+    cfg = open_slab_cfg()
+    deg = rtgen.face_counts(cfg["mesh"])
+    assert deg.min() == 5 and deg.max() == 6
+    gpu = run_gpu(cfg)
+    ref = oracle.run(cfg)
+    errs = field_errors(gpu, ref, cfg["params"]["c_reduced"], cfg["mesh"]["face_cells"])
+    worst = max(errs, key=errs.get)
+    say("open slab: worst", worst, f"{errs[worst]:.3e}")
+    assert max(errs.values()) <= 1e-10, errs
+    assert gpu["diag"]["substeps"] == ref["diag"]["substeps"]
+
+
+def test_open_boundary_mixed_and_both_paths():
+    cfg = open_slab_cfg(precision="mixed")
+    gpu = run_gpu(cfg, precision=rt.RT_MIXED)
+    errs = mixed_errors(gpu, oracle.run(cfg), cfg["params"]["c_reduced"])
+    assert max(errs[f"N[{b}] rel"] for b in range(3)) <= 1e-3
+    assert errs["x_HII abs"] <= 1e-4
+    assert_other_fields(errs)
+    for precision in (rt.RT_FP64, rt.RT_MIXED):
+        a = run_gpu(cfg, precision=precision, transport=rt.RT_TRANSPORT_FUSED)
+        b = run_gpu(cfg, precision=precision, transport=rt.RT_TRANSPORT_SPLIT)
+        for key in ("N", "F", "species", "T"):
+            assert np.array_equal(a[key], b[key]), (precision, key)
