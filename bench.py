@@ -279,6 +279,8 @@ def main() -> int:
     ap.add_argument("--order", choices=("hilbert", "random"), default="hilbert",
                     help="cell order of the headline run (random: for profiling the unordered case; "
                          "the throughput figure is quoted in Hilbert order)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the adjoint workload and print its record (for profiling the adjoint kernels)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="first copy a GIB-sized device buffer three times (a plain copy kernel of known size, "
                          "for scaling hardware byte counters)")
@@ -297,6 +299,9 @@ def main() -> int:
         return 2
     rt.lib()
     torch.cuda.set_device(0)
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_262k": adjoint_timing(rt, torch)}), flush=True)
+        return 0
     if args.calibrate_copy > 0:
         n = int(args.calibrate_copy * (1 << 30)) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -388,82 +388,91 @@ __global__ __launch_bounds__(kBlock) void k_adj_gather(const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// k_adj_chem: replay of the cell's chemistry over the subcycle on duals with
-// 7 + NB directions (x_HI, x_HII, y_I, y_II, y_III, u, N_b, n_H); the flux
-// factors Fh'/Fh = prod 1/fac_b are carried as duals seeded with 1.
+// k_adj_chem: replay of the cell's chemistry over the subcycle on duals, for
+// the 7 + NB input directions (x_HI, x_HII, y_I, y_II, y_III, u, N_b, n_H)
+// in passes of KC directions each (a dual of all directions at once does
+// not fit in registers); the flux factors Fh'/Fh = prod 1/fac_b are carried
+// as duals seeded with 1.  Every pass takes the same branches (the values
+// are the same), so the passes' columns make up one Jacobian.
 // Overwrites lambda_U (N, Fh parts), lambda_X, lambda_u with the adjoint of
 // the pre-chemistry state and adds n_H dL/dn_H to lambda_lnnH.
 // ---------------------------------------------------------------------------
-template <int NB>
+template <int NB, int KC>
 __global__ __launch_bounds__(kBlock) void k_adj_chem(const double* __restrict__ Upre, const double* __restrict__ Xpre,
                                                      const double* __restrict__ Upre_u, const double* __restrict__ nH,
                                                      double* __restrict__ lam_U, double* __restrict__ lam_X,
                                                      double* __restrict__ lam_u, double* __restrict__ lam_lnnH,
                                                      int32_t* __restrict__ fail, int64_t nc, ChemParams P, double dt) {
-    constexpr int K = 7 + NB;
+    constexpr int K = 7 + NB;                       // input directions
     const int64_t blk = xcd_logical_block();
     const int64_t i = blk * kBlock + threadIdx.x;
     if (i >= nc) return;
-    ChemState<NB, Dual<K>> s;
+    // the adjoint of the post-chemistry state
+    double lX[5], lN[NB], lF[NB];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) lX[q] = lam_X[(int64_t)q * nc + i];
+    const double lu = lam_u[i];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        s.N[b] = Dual<K>(Upre[urec(b, nc, i)]);
-        s.N[b].d[6 + b] = 1.0;
-        s.Fh[b][0] = Dual<K>(1.0);
-        s.Fh[b][1] = Dual<K>(0.0);
-        s.Fh[b][2] = Dual<K>(0.0);
-    }
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        s.x[q] = Dual<K>(Xpre[(int64_t)q * nc + i]);
-        s.x[q].d[q] = 1.0;
-    }
-    s.u = Dual<K>(Upre_u[i]);
-    s.u.d[5] = 1.0;
-    const double nh = nH[i];
-    Dual<K> nHd(nh);
-    nHd.d[6 + NB] = 1.0;
-    const int att = integrate_cell<NB, Dual<K>>(P, dt, nHd, s);
-    if (att > P.max_sub) {
-        fail[blockIdx.x] = 1;
-        return;
-    }
-    const Dual<K>* x = s.x;
-    const Dual<K>& u = s.u;
-    const Dual<K>* N = s.N;
-    const Dual<K> (*Fh)[3] = s.Fh;
-    double lin[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) lin[k] = 0.0;
-    for (int s = 0; s < 5; ++s) {
-        const double l = lam_X[(int64_t)s * nc + i];
-#pragma unroll
-        for (int k = 0; k < K; ++k) lin[k] += l * x[s].d[k];
-    }
-    {
-        const double l = lam_u[i];
-#pragma unroll
-        for (int k = 0; k < K; ++k) lin[k] += l * u.d[k];
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const double lN = lam_U[(int64_t)(b * 4) * nc + i];
-        double lF = 0.0;
+        lN[b] = lam_U[(int64_t)(b * 4) * nc + i];
+        lF[b] = 0.0;
         for (int c = 0; c < 3; ++c)
-            lF += lam_U[(int64_t)(b * 4 + 1 + c) * nc + i] * Upre[urec(b, nc, i) + 1 + c];
-#pragma unroll
-        for (int k = 0; k < K; ++k) lin[k] += lN * N[b].d[k] + lF * Fh[b][0].d[k];
+            lF[b] += lam_U[(int64_t)(b * 4 + 1 + c) * nc + i] * Upre[urec(b, nc, i) + 1 + c];
     }
-    // All contributions are in lin: write the pre-chemistry adjoint.  The flux
-    // itself only scales by the absorption product.
+    const double nh = nH[i];
+    double fac[NB];
+    for (int k0 = 0; k0 < K; k0 += KC) {
+        // seed directions k0 .. k0 + KC - 1
+        auto seed = [&](Dual<KC>& d, int k) {
+            if (k >= k0 && k < k0 + KC) d.d[k - k0] = 1.0;
+        };
+        ChemState<NB, Dual<KC>> s;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        for (int c = 0; c < 3; ++c) lam_U[(int64_t)(b * 4 + 1 + c) * nc + i] *= Fh[b][0].v;
-        lam_U[(int64_t)(b * 4) * nc + i] = lin[6 + b];
+        for (int b = 0; b < NB; ++b) {
+            s.N[b] = Dual<KC>(Upre[urec(b, nc, i)]);
+            seed(s.N[b], 6 + b);
+            s.Fh[b][0] = Dual<KC>(1.0);
+            s.Fh[b][1] = Dual<KC>(0.0);
+            s.Fh[b][2] = Dual<KC>(0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            s.x[q] = Dual<KC>(Xpre[(int64_t)q * nc + i]);
+            seed(s.x[q], q);
+        }
+        s.u = Dual<KC>(Upre_u[i]);
+        seed(s.u, 5);
+        Dual<KC> nHd(nh);
+        seed(nHd, 6 + NB);
+        const int att = integrate_cell<NB, Dual<KC>>(P, dt, nHd, s);
+        if (att > P.max_sub) {
+            fail[blockIdx.x] = 1;
+            return;
+        }
+        // the adjoint of input k = k0 + j, written as soon as it is complete
+        // (the post-chemistry adjoint it overwrites was read above)
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            const int k = k0 + j;
+            if (k >= K) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) acc += lX[q] * s.x[q].d[j];
+            acc += lu * s.u.d[j];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc += lN[b] * s.N[b].d[j] + lF[b] * s.Fh[b][0].d[j];
+            if (k < 5) lam_X[(int64_t)k * nc + i] = acc;
+            else if (k == 5) lam_u[i] = acc;
+            else if (k < 6 + NB) lam_U[(int64_t)((k - 6) * 4) * nc + i] = acc;
+            else lam_lnnH[i] += acc * nh;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) fac[b] = s.Fh[b][0].v;
     }
-    for (int s = 0; s < 5; ++s) lam_X[(int64_t)s * nc + i] = lin[s];
-    lam_u[i] = lin[5];
-    lam_lnnH[i] += lin[6 + NB] * nh;
+    // The flux itself only scales by the absorption product.
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        for (int c = 0; c < 3; ++c) lam_U[(int64_t)(b * 4 + 1 + c) * nc + i] *= fac[b];
 }
 
 // ---------------------------------------------------------------------------
@@ -502,12 +511,18 @@ namespace {
 
 unsigned grid1(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Directions per replay of the chemistry adjoint (registers against passes).
+#ifndef RT_ADJ_CHEM_DIRS
+#define RT_ADJ_CHEM_DIRS 2
+#endif
+constexpr int kAdjChemDirs = RT_ADJ_CHEM_DIRS;
+
 template <int NB>
 void launch_adj_chem_nb(const double* Upre, const double* Xpre, const double* ue, const double* nH, double* lU,
                         double* lX, double* lu, double* lnn, int32_t* fail, int64_t nc, const ChemParams& P,
                         double dt, hipStream_t st) {
-    hipLaunchKernelGGL((k_adj_chem<NB>), dim3(grid1(nc, kBlock)), dim3(kBlock), 0, st, Upre, Xpre, ue, nH, lU, lX, lu,
-                       lnn, fail, nc, P, dt);
+    hipLaunchKernelGGL((k_adj_chem<NB, kAdjChemDirs>), dim3(grid1(nc, kBlock)), dim3(kBlock), 0, st, Upre, Xpre, ue, nH,
+                       lU, lX, lu, lnn, fail, nc, P, dt);
 }
 
 struct Segment {
