@@ -283,7 +283,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
         Dual<KG> phi_i(U[urec(b, nc, i) + v]);
         phi_i.d[0] = 1.0;
         Dual<KG> bs[3], umax = phi_i, umin = phi_i;
-        for (int k = 0; k < deg; ++k) {
+        // (slot loops unrolled to KG - 1 so that a slot's direction index is a
+        // constant and the duals stay in registers)
+#pragma unroll
+        for (int k = 0; k < KG - 1; ++k) {
+            if (k >= deg) break;
             const int64_t e = base + (int64_t)k * kSlice;
             const int32_t j = sell.nbr[e];
             if (j < 0) continue;
@@ -300,8 +304,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
             bs[0] += (d0 * s) * dphi;
             bs[1] += (d1 * s) * dphi;
             bs[2] += (d2 * s) * dphi;
-            umax = val(uj) > val(umax) ? uj : umax;
-            umin = val(uj) < val(umin) ? uj : umin;
+            if (val(uj) > val(umax)) umax = uj;
+            if (val(uj) < val(umin)) umin = uj;
         }
         Dual<KG> g[3];
         g[0] = mxx * bs[0] + mxy * bs[1] + mxz * bs[2];
@@ -309,7 +313,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
         g[2] = mxz * bs[0] + myz * bs[1] + mzz * bs[2];
         if (use_limiter) {
             Dual<KG> alpha(1.0);
-            for (int k = 0; k < deg; ++k) {
+#pragma unroll
+            for (int k = 0; k < KG - 1; ++k) {
+                if (k >= deg) break;
                 const int64_t e = base + (int64_t)k * kSlice;
                 if (sell.nbr[e] < 0) continue;
                 const int32_t fs = sell.fsf[e];
@@ -320,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
                 Dual<KG> psi(1.0);
                 if (val(delta) > 0.0) psi = (umax - phi_i) / delta;
                 else if (val(delta) < 0.0) psi = (umin - phi_i) / delta;
-                alpha = val(psi) < val(alpha) ? psi : alpha;
+                if (val(psi) < val(alpha)) alpha = psi;
             }
             g[0] = alpha * g[0];
             g[1] = alpha * g[1];
@@ -330,7 +336,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_grad(const double* __restrict__ 
         const double l1 = Lg[(int64_t)(v * 3 + 1) * nc + i];
         const double l2 = Lg[(int64_t)(v * 3 + 2) * nc + i];
         c_self[(int64_t)(b * 4 + v) * nc + i] = l0 * g[0].d[0] + l1 * g[1].d[0] + l2 * g[2].d[0];
-        for (int k = 0; k < deg; ++k) {
+#pragma unroll
+        for (int k = 0; k < KG - 1; ++k) {
+            if (k >= deg) break;
             const int64_t e = base + (int64_t)k * kSlice;
             c_slot[(int64_t)(b * 4 + v) * n_entries + e] =
                 l0 * g[0].d[1 + k] + l1 * g[1].d[1 + k] + l2 * g[2].d[1 + k];

@@ -122,8 +122,18 @@ __device__ inline double m_log10(double x) { return 0.43429448190325182765 * rt_
 template <int K> __device__ inline Dual<K> m_log10(const Dual<K>& a) {
     return chain(a, 0.43429448190325182765 * rt_log(a.v), 0.43429448190325182765 / a.v);
 }
-template <typename R> __device__ inline R m_abs(const R& a) { return val(a) < 0 ? -a : a; }
-template <typename R> __device__ inline R m_max(const R& a, const R& b) { return val(a) >= val(b) ? a : b; }
-template <typename R> __device__ inline R m_min(const R& a, const R& b) { return val(a) <= val(b) ? a : b; }
+// c ? a : b, for duals part by part (a select of whole structures would put
+// them in scratch memory).
+template <typename R> __device__ inline R sel(bool c, const R& a, const R& b) { return c ? a : b; }
+template <int K> __device__ inline Dual<K> sel(bool c, const Dual<K>& a, const Dual<K>& b) {
+    Dual<K> r;
+    r.v = c ? a.v : b.v;
+#pragma unroll
+    for (int k = 0; k < K; ++k) r.d[k] = c ? a.d[k] : b.d[k];
+    return r;
+}
+template <typename R> __device__ inline R m_abs(const R& a) { return sel(val(a) < 0, R(-a), a); }
+template <typename R> __device__ inline R m_max(const R& a, const R& b) { return sel(val(a) >= val(b), a, b); }
+template <typename R> __device__ inline R m_min(const R& a, const R& b) { return sel(val(a) <= val(b), a, b); }
 
 }  // namespace rtk

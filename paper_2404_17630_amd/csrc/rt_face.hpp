@@ -115,7 +115,7 @@ __device__ inline bool face_flux(R* sL, R* sR, const R& NL, const R& NR, G vcL, 
     hll_flux<R, G>(sL, sR, n0, n1, n2, Phi);
     if (val(Phi[0]) != 0) {
         const bool upL = val(Phi[0]) > 0;
-        const R Nup = upL ? NL : NR;
+        const R Nup = sel(upL, NL, NR);
         const G vc = upL ? vcL : vcR;
         const R q = m_abs(Phi[0]) * cdt * A;
         if (val(Nup) * vc < val(q)) {
