@@ -225,6 +225,13 @@ void rt_mesh::build_tile_faces() {
         tpair_ptr[t + 1] = (int32_t)tpair.size();
         tbnd_ptr[t + 1] = n_items;
         tbnd_max = std::max<int64_t>(tbnd_max, tbnd_ptr[t + 1] - tbnd_ptr[t]);
+        // a face takes two of the tile's sides, so a tile has at most
+        // 3 kTileCells interior faces: the face-state kernel's three per thread
+        if (tpair_ptr[t + 1] - tpair_ptr[t] > 3 * kTileCells) {
+            tpair_ptr.clear(); tpair.clear(); tbnd_ptr.clear(); tbnd.clear(); tbnd_sptr.clear(); bmask.clear();
+            tbnd_max = 0;
+            return;
+        }
     }
     for (int64_t s = 0; s < ns; ++s) tbnd_sptr[s + 1] += tbnd_sptr[s];
     // The tile split pays off when tiles are compact (a Hilbert-ordered
@@ -232,6 +239,7 @@ void rt_mesh::build_tile_faces() {
     // cell (an unordered mesh: up to all six) the per-slice kernels are used.
     if (n_items > 2 * nc) {
         tpair_ptr.clear(); tpair.clear(); tbnd_ptr.clear(); tbnd.clear(); tbnd_sptr.clear(); bmask.clear();
+        tbnd_max = 0;
         return;
     }
     // the opposite side of a boundary item is a boundary item of its own tile
