@@ -1127,9 +1127,10 @@ static TileFaceView rt_tile_faces(const rt_mesh* m) {
                         m->n_bnd(),                         m->tbnd_max};
 }
 
-// Whether the split path of a state runs by tile (six-slot meshes): the
-// face-state pass then also evaluates the tile-interior faces, and the flux
-// pass needs its sums.
+// Whether the split path of a state runs by tile (six-slot meshes with
+// compact tiles, where the mesh kept its tile tables): the face-state pass
+// then also evaluates the tile-interior faces, and the flux pass needs its
+// sums.
 static bool tile_split(const rt_state* s) { return !s->mesh->tpair_ptr.empty() && s->PS.ptr; }
 
 void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, double dt, bool all_states) {
@@ -1157,15 +1158,13 @@ void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, dou
     s->prof_end(st);
 }
 
-// Fluxes and update of slices [slice0, slice1) (all by default).
-void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st, int64_t slice0,
-                  int64_t slice1) {
-    if (slice1 < 0) slice1 = (int64_t)s->mesh->sdeg.size();
+// Fluxes and update of the whole mesh, from what rt_step_facestate wrote.
+void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st) {
+    const int64_t slice0 = 0, slice1 = (int64_t)s->mesh->sdeg.size();
     const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
     s->prof_begin(RT_KERNEL_FLUX, st);
     const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;   // the cells' cap numerators follow the face states
     if (tile_split(s)) {
-        // whole tiles (the range is the whole mesh)
         const int64_t nbs = (int64_t)s->nb * 4 * s->mesh->n_bnd();
         if (s->precision == RT_MIXED)
             launch_flux_tile<float>((const float*)U, (const float*)FV, (const float*)FV + nbs, (const double*)s->PS.ptr,

@@ -203,12 +203,12 @@ rtk::SellView rt_sell(const rt_mesh* m);
 void rt_step_sources(rt_state* s, void* U, double dt, hipStream_t st, int32_t src0 = 0, int32_t src1 = -1);
 void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStream_t st, int64_t cell0 = 0,
                   int64_t cell1 = -1, int64_t cblk0 = 0);
-// Face states of the split path; on six-slot meshes also the tile-interior
-// faces' flux sums (PS), unless all_states asks for every face state in FV
-// (the adjoint's reverse sweep; rt_step_flux must not follow it then).
+// Face states of the split path; where the mesh has tile tables also the
+// tile-interior faces' flux sums (PS), unless all_states asks for every face
+// state in FV (the adjoint's reverse sweep; rt_step_flux must not follow it
+// then).  rt_step_flux then updates the whole mesh.
 void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, double dt, bool all_states);
-void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st, int64_t slice0 = 0,
-                  int64_t slice1 = -1);
+void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st);
 void rt_step_transport(rt_state* s, const void* U, void* Un, double dt, hipStream_t st);
 rtk::TileView rt_tiles(const rt_mesh* m);
 void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st);
