@@ -5,20 +5,33 @@ One subcycle of a cell depends on its own state and that of the cells within
 two faces of it: its face states need its neighbours' limited gradients, and
 those need the neighbours' neighbours (the limiter's extrema too).  On a
 jittered lattice that cone lies inside the 5x5x5 block of lattice sites
-centred on the cell.  The patch is that block as a periodic mesh of its own:
+centred on the cell, and the cone of k subcycles inside the block of
+half-width w = 2k.  The patch is that block as a periodic mesh of its own:
 its interior faces are the lattice's faces (translated), and the faces that
 leave the block close it onto the opposite side.  Only the block's outer
-layer gets wrong neighbours, and no face or gradient of the centre's cone
-uses an outer cell's gradient, so the oracle's one subcycle on the patch
-gives the centre cell's exact result on the whole mesh (to rounding order).
+layer gets wrong neighbours.  After the first subcycle the wrong values
+reach one layer in (the faces that use an outer cell's gradient), and every
+later subcycle takes them two layers further, so after k subcycles on the
+block of half-width 2k they stop one layer short of the centre: the
+oracle's k subcycles on the patch give the centre cell's exact result on
+the whole mesh (to rounding order).  The block must not wrap onto itself,
+so its edge is at most the lattice's.
 """
 from __future__ import annotations
 
 import numpy as np
 
-W = 2                     # cells from the centre to the block's edge
-P = 2 * W + 1             # block edge in cells
-CENTRE = W + P * (W + P * W)   # local index of the centre (x fastest)
+W = 2                     # cells from the centre to the block's edge, one subcycle
+
+
+def edge(w: int) -> int:
+    return 2 * w + 1
+
+
+def centre_index(w: int) -> int:
+    """Local index of the centre (x fastest) of the block of half-width w."""
+    p = edge(w)
+    return w + p * (w + p * w)
 
 
 class LatticeIndex:
@@ -34,9 +47,11 @@ class LatticeIndex:
         self.cell_at = np.empty(lex.size, np.int64)
         self.cell_at[lex] = np.arange(lex.size)
 
-    def block(self, c: int) -> np.ndarray:
-        """Cells of the P^3 block centred on cell c, in local order (x fastest)."""
-        a = np.arange(P) - W
+    def block(self, c: int, w: int = W) -> np.ndarray:
+        """Cells of the (2w+1)^3 block centred on cell c, in local order (x fastest)."""
+        if edge(w) > self.dims.min():
+            raise ValueError(f"block of edge {edge(w)} wraps on a lattice of {self.dims.tolist()}")
+        a = np.arange(edge(w)) - w
         lx, ly, lz = np.meshgrid(a, a, a, indexing="ij")
         lx, ly, lz = (v.transpose(2, 1, 0).ravel() for v in (lx, ly, lz))   # x fastest
         g = (self.idx[:, c][:, None] + np.stack([lx, ly, lz])) % self.dims[:, None]
@@ -44,13 +59,15 @@ class LatticeIndex:
         return self.cell_at[g[0] + nx * (g[1] + ny * g[2])]
 
 
-def patch_config(cfg: dict, fields: dict, lat: LatticeIndex, c: int) -> dict:
-    """The oracle's config of the periodic block around cell c, with the state
-    `fields` (N, F, species, T, n_H of the whole mesh) and the sources inside
-    the block, for one subcycle."""
+def patch_config(cfg: dict, fields: dict, lat: LatticeIndex, c: int, n_sub: int = 1) -> dict:
+    """The oracle's config of the periodic block around cell c of half-width
+    2 n_sub, with the state `fields` (N, F, species, T, n_H of the whole mesh)
+    and the sources inside the block, for n_sub subcycles."""
     m = cfg["mesh"]
     h = lat.h
-    cells = lat.block(c)
+    w = 2 * n_sub
+    P = edge(w)
+    cells = lat.block(c, w)
     n = cells.size
     loc = np.arange(n)
     l = np.stack([loc % P, (loc // P) % P, loc // (P * P)])          # local lattice coords
@@ -82,13 +99,15 @@ def patch_config(cfg: dict, fields: dict, lat: LatticeIndex, c: int) -> dict:
     keep = [k for k in range(src_cell.size) if int(src_cell[k]) in where]
     sources = dict(cell=np.array([where[int(src_cell[k])] for k in keep], np.int64),
                    rate=np.ascontiguousarray(rate[:, keep]))
-    return dict(name="patch", mesh=mesh, params=cfg["params"], state=state, sources=sources, n_subcycles=1,
+    return dict(name="patch", mesh=mesh, params=cfg["params"], state=state, sources=sources, n_subcycles=n_sub,
                 precision="fp64")
 
 
-def centre_values(st: dict) -> dict:
-    """The centre cell's fields from an oracle result on a patch."""
-    return dict(N=st["N"][:, CENTRE], F=st["F"][:, :, CENTRE], species=st["species"][:, CENTRE], T=st["T"][CENTRE])
+def centre_values(st: dict, n_sub: int = 1) -> dict:
+    """The centre cell's fields from an oracle result on a patch of n_sub
+    subcycles."""
+    k = centre_index(2 * n_sub)
+    return dict(N=st["N"][:, k], F=st["F"][:, :, k], species=st["species"][:, k], T=st["T"][k])
 
 
 def sample_cells(fields: dict, n_lit: int, n_any: int, seed: int, src_cells) -> np.ndarray:

@@ -4,19 +4,25 @@ import numpy as np
 
 import oracle
 import rtgen
-from tests.patches import LatticeIndex, centre_values, patch_config, sample_cells
+import pytest
+
+from tests.patches import LatticeIndex, centre_index, centre_values, patch_config, sample_cells
 
 
-def test_patch_recomputes_one_subcycle_of_sampled_cells():
-    """A 12^3 H+He lattice with 8 sources, advanced 6 subcycles by the
-    oracle; one more subcycle on the whole mesh against the same subcycle on
-    the 5^3 periodic patch of each sampled cell (lit cells, fronts, source
-    cells and unlit gas): equal to 1e-12 in every field."""
-    cfg = rtgen.throughput_16m(n=12, n_src=8, n_sub=6, precision="fp64")
+@pytest.mark.parametrize("n, n_sub", [(12, 1), (16, 2), (16, 3)])
+def test_patch_recomputes_subcycles_of_sampled_cells(n, n_sub):
+    """An n^3 H+He lattice with 8 sources, advanced 6 subcycles by the
+    oracle; n_sub more subcycles on the whole mesh against the same
+    subcycles on the periodic patch of half-width 2 n_sub around each
+    sampled cell (lit cells, fronts, source cells and unlit gas): equal to
+    1e-12 in every field, N and F relative to the largest N in the 3^3
+    block around the cell (the size of the terms its update sums, in another
+    order on the patch)."""
+    cfg = rtgen.throughput_16m(n=n, n_src=8, n_sub=6, precision="fp64")
     st6 = oracle.run(cfg)
     fields = {k: st6[k] for k in ("N", "F", "species", "T")}
     fields["n_H"] = np.asarray(cfg["state"]["n_H"], float)
-    cfg1 = dict(cfg, state=dict(fields), n_subcycles=1)
+    cfg1 = dict(cfg, state=dict(fields), n_subcycles=n_sub)
     dt = oracle.cfl_dt(cfg)
     st7 = oracle.run(cfg1, dt=dt)
     lat = LatticeIndex(cfg["mesh"])
@@ -24,9 +30,10 @@ def test_patch_recomputes_one_subcycle_of_sampled_cells():
     assert cells.size >= 16
     worst = 0.0
     for c in cells:
-        ref = centre_values(oracle.run(patch_config(cfg, fields, lat, int(c)), dt=dt))
+        ref = centre_values(oracle.run(patch_config(cfg, fields, lat, int(c), n_sub=n_sub), dt=dt), n_sub=n_sub)
+        ring = lat.block(int(c), 1)
         for b in range(cfg["params"]["nb"]):
-            s = max(abs(st7["N"][b, c]), 1e-12 * st7["N"][b].max(), 1e-300)
+            s = max(np.abs(st7["N"][b, ring]).max(), 1e-12 * st7["N"][b].max(), 1e-300)
             worst = max(worst, abs(ref["N"][b] - st7["N"][b, c]) / s)
             for k in range(3):
                 worst = max(worst, abs(ref["F"][b, k] - st7["F"][b, k, c]) / (cfg["params"]["c_reduced"] * s))
@@ -51,3 +58,7 @@ def test_patch_block_is_the_cell_and_its_two_face_rings():
         assert len(block) == 125
         assert {c} | ring1 | ring2 <= block
         assert lat.block(c)[62] == c
+        for w in (1, 4):
+            assert lat.block(c, w)[centre_index(w)] == c
+    with pytest.raises(ValueError):
+        lat.block(0, 6)          # 13 cells across a 12^3 lattice would wrap
