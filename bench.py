@@ -57,16 +57,16 @@ def algorithmic_bytes(kernel: str, nc: int, nb: int, nf: int, n_sides: int, n_sr
     if tile is not None and kernel in ("k_facestate", "k_flux"):
         n_bnd, n_pairs = tile
         if kernel == "k_facestate":
-            # fields in; the cell's FP64 sum over its tile-interior faces out
-            # (4 doubles); each boundary item's state and cap numerator out;
-            # cell record, per side weight, offset and neighbour, the slot
-            # mask; per interior face its (L, R) pair and A, n
-            return (nb * (4 * nc * p + 32 * nc + 5 * n_bnd * p) + nc * (8 * g + 1) + n_sides * (6 * g + 4)
+            # fields in; the cells updated by their tile-interior faces out;
+            # each boundary item's state and cap numerator out; cell record,
+            # per side weight, offset and neighbour, the slot mask; per
+            # interior face its (L, R) pair and A, n
+            return (nb * (8 * nc * p + 5 * n_bnd * p) + nc * (8 * g + 1) + n_sides * (6 * g + 4)
                     + n_pairs * (4 + 4 * g))
-        # fields in and out, the interior sums in; each boundary item's own
-        # and opposite state and cap numerator; V and the slot mask per cell;
-        # per item the opposite position and A, n
-        return nb * (8 * nc * p + 32 * nc + 10 * n_bnd * p) + nc * (g + 1) + n_bnd * (4 + 4 * g)
+        # the partly updated fields in and out; each boundary item's own and
+        # opposite state and cap numerator; V and the slot mask per cell; per
+        # item the opposite position and A, n
+        return nb * (8 * nc * p + 10 * n_bnd * p) + nc * (g + 1) + n_bnd * (4 + 4 * g)
     if kernel == "k_facestate":
         # fields (4) in, one 4-value face state per face side out, the cell's
         # cap numerator N V / n_faces out; cell record (M^-1, V, V/n_f), per

@@ -670,7 +670,7 @@ extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int
             if ((rc = save(pre_U[j], pre_X[j], pre_u[j]))) return rc;
             rt_step_chem(w, U, (double*)w->X.ptr, (double*)w->Ue.ptr, dt, st);
             RT_HIP_A(hipMemcpyAsync(mid_U[j].ptr, U, ub, hipMemcpyDeviceToDevice, st));
-            rt_step_facestate(w, U, w->FV.ptr, st, dt, false);
+            rt_step_facestate(w, U, w->FV.ptr, Un, st, dt, false);
             rt_step_flux(w, U, w->FV.ptr, Un, dt, st);
             w->cur ^= 1;
         }
@@ -678,7 +678,7 @@ extern "C" int rt_subcycle_adjoint(const rt_state* initial, int n_subcycles, int
         for (int j = len - 1; j >= 0; --j) {
             const double* Um = (const double*)mid_U[j].ptr;
             const double* tv = (const double*)tau.ptr;
-            rt_step_facestate(w, Um, w->FV.ptr, st, dt, true);
+            rt_step_facestate(w, Um, w->FV.ptr, nullptr, st, dt, true);
             launch_gradient(Um, (double*)G.ptr, nc, nb, geo, sell, w->params.use_limiter, st);
             hipLaunchKernelGGL(k_adj_binmax, dim3((unsigned)tblk), dim3(kBlock), 0, st, Um, nc, nb, (double*)tmax.ptr);
             hipLaunchKernelGGL(k_adj_tau, dim3((unsigned)nb), dim3(kBlock), 0, st, (const double*)tmax.ptr,

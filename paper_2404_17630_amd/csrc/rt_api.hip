@@ -758,10 +758,7 @@ int rt_state::ensure_face_states() {
     // (by tile on six-slot meshes: the boundary items' states and cap
     // numerators [nb][n_bnd][5])
     const size_t n = std::max((size_t)nb * 4 * mesh->n_entries + (size_t)nb * nc, (size_t)nb * 5 * mesh->n_bnd());
-    int rc = FV.alloc(n * tbytes());
-    // six-slot meshes: the per-cell sums over tile-interior faces
-    if (!rc && !mesh->tpair_ptr.empty()) rc = PS.alloc((size_t)nb * nc * 4 * 8);
-    return rc;
+    return FV.alloc(n * tbytes());
 }
 
 static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
@@ -1129,11 +1126,11 @@ static TileFaceView rt_tile_faces(const rt_mesh* m) {
 
 // Whether the split path of a state runs by tile (six-slot meshes with
 // compact tiles, where the mesh kept its tile tables): the face-state pass
-// then also evaluates the tile-interior faces, and the flux pass needs its
-// sums.
-static bool tile_split(const rt_state* s) { return !s->mesh->tpair_ptr.empty() && s->PS.ptr; }
+// then also evaluates the tile-interior faces and applies them to the new
+// fields, and the flux pass finishes the update there.
+static bool tile_split(const rt_state* s) { return !s->mesh->tpair_ptr.empty(); }
 
-void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, double dt, bool all_states) {
+void rt_step_facestate(rt_state* s, const void* U, void* FV, void* Un, hipStream_t st, double dt, bool all_states) {
     s->prof_begin(RT_KERNEL_GRADIENT, st);
     const int64_t nfv = (int64_t)s->nb * 4 * s->mesh->n_entries;   // the cells' cap numerators follow the face states
     const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
@@ -1141,11 +1138,11 @@ void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, dou
         // boundary-item states [nb][n_bnd][4], then their cap numerators [nb][n_bnd], in FV
         const int64_t nbs = (int64_t)s->nb * 4 * s->mesh->n_bnd();
         if (s->precision == RT_MIXED)
-            launch_facestate_tile<float>((const float*)U, (float*)FV, (float*)FV + nbs, (double*)s->PS.ptr, s->nc,
+            launch_facestate_tile<float>((const float*)U, (float*)FV, (float*)FV + nbs, (float*)Un, s->nc,
                                          s->nb, geom_view<float>(s->mesh), rt_sell(s->mesh), rt_tile_faces(s->mesh),
                                          s->params.use_limiter, cdt, s->pb.cnt, s->pb.fst, st);
         else
-            launch_facestate_tile<double>((const double*)U, (double*)FV, (double*)FV + nbs, (double*)s->PS.ptr, s->nc,
+            launch_facestate_tile<double>((const double*)U, (double*)FV, (double*)FV + nbs, (double*)Un, s->nc,
                                           s->nb, geom_view<double>(s->mesh), rt_sell(s->mesh), rt_tile_faces(s->mesh),
                                           s->params.use_limiter, cdt, s->pb.cnt, s->pb.fst, st);
     } else if (s->precision == RT_MIXED) {
@@ -1158,7 +1155,8 @@ void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, dou
     s->prof_end(st);
 }
 
-// Fluxes and update of the whole mesh, from what rt_step_facestate wrote.
+// Fluxes and update of the whole mesh, from what rt_step_facestate wrote
+// (by tile: in place in Un).
 void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st) {
     const int64_t slice0 = 0, slice1 = (int64_t)s->mesh->sdeg.size();
     const double cdt = s->params.c_reduced * dt / s->mesh->h_ref;
@@ -1167,13 +1165,11 @@ void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double d
     if (tile_split(s)) {
         const int64_t nbs = (int64_t)s->nb * 4 * s->mesh->n_bnd();
         if (s->precision == RT_MIXED)
-            launch_flux_tile<float>((const float*)U, (const float*)FV, (const float*)FV + nbs, (const double*)s->PS.ptr,
-                                    (float*)Un, s->nc, s->nb, (const float*)s->mesh->d_vol32.ptr,
-                                    (const float*)s->mesh->d_bgeo32.ptr, rt_tile_faces(s->mesh), cdt, s->pb.nv,
-                                    s->pb.cnt, s->pb.fst, st);
+            launch_flux_tile<float>((const float*)FV, (const float*)FV + nbs, (float*)Un, s->nc, s->nb,
+                                    (const float*)s->mesh->d_vol32.ptr, (const float*)s->mesh->d_bgeo32.ptr,
+                                    rt_tile_faces(s->mesh), cdt, s->pb.nv, s->pb.cnt, s->pb.fst, st);
         else
-            launch_flux_tile<double>((const double*)U, (const double*)FV, (const double*)FV + nbs,
-                                     (const double*)s->PS.ptr, (double*)Un, s->nc, s->nb,
+            launch_flux_tile<double>((const double*)FV, (const double*)FV + nbs, (double*)Un, s->nc, s->nb,
                                      (const double*)s->mesh->d_vol64.ptr, (const double*)s->mesh->d_bgeo64.ptr,
                                      rt_tile_faces(s->mesh), cdt, s->pb.nv, s->pb.cnt, s->pb.fst, st);
     } else if (s->precision == RT_MIXED)
@@ -1233,7 +1229,7 @@ void rt_run_subcycles(rt_state* s, int n, double dt, hipStream_t st) {
         if (fused) {
             rt_step_transport(s, U, Un, dt, st);
         } else {
-            rt_step_facestate(s, U, s->FV.ptr, st, dt, false);
+            rt_step_facestate(s, U, s->FV.ptr, Un, st, dt, false);
             rt_step_flux(s, U, s->FV.ptr, Un, dt, st);
         }
         s->cur ^= 1;

@@ -150,8 +150,6 @@ struct rt_state {
     DevMem U[2];
     int cur = 0;
     DevMem FV;
-    DevMem PS;                   // [nb][nc][4] FP64 flux sums over each cell's tile-interior faces
-                                 // (split path on six-slot meshes)
     DevMem X, Ue, nH;            // [5][nc], [nc], [nc]
     DevMem att;                  // [nc] int32 chemistry attempts of each cell in the current call
     double scale[RT_MAX_BINS];
@@ -204,10 +202,11 @@ void rt_step_sources(rt_state* s, void* U, double dt, hipStream_t st, int32_t sr
 void rt_step_chem(rt_state* s, void* U, double* X, double* Ue, double dt, hipStream_t st, int64_t cell0 = 0,
                   int64_t cell1 = -1, int64_t cblk0 = 0);
 // Face states of the split path; where the mesh has tile tables also the
-// tile-interior faces' flux sums (PS), unless all_states asks for every face
-// state in FV (the adjoint's reverse sweep; rt_step_flux must not follow it
-// then).  rt_step_flux then updates the whole mesh.
-void rt_step_facestate(rt_state* s, const void* U, void* FV, hipStream_t st, double dt, bool all_states);
+// tile-interior faces' fluxes, with every cell updated by them into Un,
+// unless all_states asks for every face state in FV (the adjoint's reverse
+// sweep; Un is unused, and rt_step_flux must not follow it then).
+// rt_step_flux then updates the whole mesh into Un.
+void rt_step_facestate(rt_state* s, const void* U, void* FV, void* Un, hipStream_t st, double dt, bool all_states);
 void rt_step_flux(rt_state* s, const void* U, const void* FV, void* Un, double dt, hipStream_t st);
 void rt_step_transport(rt_state* s, const void* U, void* Un, double dt, hipStream_t st);
 rtk::TileView rt_tiles(const rt_mesh* m);

@@ -386,6 +386,17 @@ __device__ inline void update_cell_v(int64_t i, int b, int64_t nc, const T* ui, 
     nv += (double)o[0] * vol;
 }
 
+// The update of a cell by part of its flux sum, rounded to the field type:
+// w = u - (dt / V) acc.  The by-tile paths apply the tile-interior faces'
+// sum this way, then the cross-tile faces' sum with update_cell_v.
+template <typename T, typename TA, typename UI>
+__device__ inline void partial_update(const UI* ui, T vol_t, const double* acc, TA cdt, T* w) {
+#pragma clang fp contract(off)
+    const double coef = (double)cdt / (double)vol_t;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) w[v] = (T)((double)ui[v] - coef * acc[v]);
+}
+
 template <typename T, typename TA>
 __device__ inline void update_cell(int64_t i, int b, int64_t nc, const T* ui, const double* acc, TA cdt,
                                    const GeomView<T>& geo, T* __restrict__ Unew, double& nv, int& cGN, int& cGF,
@@ -617,17 +628,18 @@ __global__ __launch_bounds__(kFluxPairThreads) void k_flux_pairs(
 //                     tile, with the cell's cap numerator, also to HBM,
 //                     packed in boundary-item order; then every
 //                     tile-interior face's flux, once, from the two states
-//                     in LDS; then each cell's sum over its tile-interior
-//                     faces in slot order, in FP64, to HBM (PS);
+//                     in LDS; then each cell's FP64 sum over its
+//                     tile-interior faces in slot order, applied to the
+//                     cell (partial_update) and stored to the new fields;
 //   k_flux_tile       the fluxes of the tile's boundary items (own and
 //                     opposite state read by item: the own ones contiguous);
-//                     each cell adds them in slot order to its interior sum
-//                     and is updated.
+//                     each cell sums them in slot order and finishes its
+//                     update in place.
 // Only the cross-tile face states (one a cell on a Hilbert-ordered
-// lattice, against six) and a 32-byte sum go through HBM between the two
-// passes.  A cell's fluxes are added tile-interior faces first, then
-// cross-tile ones, each in slot order, as the fused kernel does too, so the
-// two paths agree bit for bit.
+// lattice, against six) and the partly updated cell go through HBM between
+// the two passes.  A cell is updated by its tile-interior faces, rounded to
+// the field type, then by its cross-tile ones, each sum in slot order, as
+// the fused kernel does too, so the two paths agree bit for bit.
 // ---------------------------------------------------------------------------
 
 // Cell (relative to the tile) of an entry relative to the tile's first
@@ -657,7 +669,7 @@ struct SliceItems {
 
 template <typename T, typename TA>
 __global__ __launch_bounds__(kTileThreads) void k_facestate_tile(
-    const T* __restrict__ U, T* __restrict__ BS, T* __restrict__ BN, double* __restrict__ PS, int64_t nc, int nb,
+    const T* __restrict__ U, T* __restrict__ BS, T* __restrict__ BN, T* __restrict__ Unew, int64_t nc, int nb,
     GeomView<T> geo, SellView sell, TileFaceView tf, int use_limiter, TA cdt, int64_t* __restrict__ part_cnt,
     int32_t* __restrict__ part_status, int64_t n_blocks) {
     constexpr int DEG = 6;
@@ -763,6 +775,11 @@ __global__ __launch_bounds__(kTileThreads) void k_facestate_tile(
     const uint64_t packed = (uint64_t)cAdmN | ((uint64_t)cAdmF << 21) | ((uint64_t)cCap << 42);
     const uint64_t spk = wave_sum(packed);
     if ((tid & 63) == 0) lcnt[tid >> 6] = spk;
+    // the cell and its volume again (cache hits), requested before the barrier
+    const int64_t ic = i < nc ? i : nc - 1;
+    T ui[4];
+    load4(U + urec(b, nc, ic), ui);
+    const T vi = geo.cell[ic * kCellRec + 6];
     __syncthreads();
     if (i < nc) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -774,9 +791,9 @@ __global__ __launch_bounds__(kTileThreads) void k_facestate_tile(
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[v] += (double)lst[v][q];
         }
-        double* ps = PS + ((int64_t)b * nc + i) * 4;
-        *reinterpret_cast<double2*>(ps) = make_double2(acc[0], acc[1]);
-        *reinterpret_cast<double2*>(ps + 2) = make_double2(acc[2], acc[3]);
+        T w[4];
+        partial_update<T, TA>(ui, vi, acc, cdt, w);
+        store4(Unew + urec(b, nc, i), w);
     }
     if (tid == 0) {
         constexpr uint64_t kField = (1ull << 21) - 1;
@@ -789,9 +806,11 @@ __global__ __launch_bounds__(kTileThreads) void k_facestate_tile(
 
 // Products of the boundary items live in dynamic LDS, bnd_max records of
 // four TA per workgroup, at the item's index relative to the tile's first.
+// Unew holds the cells as k_facestate_tile left them (updated by their
+// tile-interior faces); each thread finishes its own cell in place.
 template <typename T, typename TA>
 __global__ __launch_bounds__(kTileThreads) void k_flux_tile(
-    const T* __restrict__ U, const T* __restrict__ BS, const T* __restrict__ BN, const double* __restrict__ PS,
+    const T* __restrict__ BS, const T* __restrict__ BN,
     T* __restrict__ Unew, int64_t nc, int nb, const T* __restrict__ vol, const T* __restrict__ bgeo,
     TileFaceView tf, TA cdt, double* __restrict__ part_nv, int64_t* __restrict__ part_cnt,
     int32_t* __restrict__ part_status, int64_t n_blocks) {
@@ -810,13 +829,10 @@ __global__ __launch_bounds__(kTileThreads) void k_flux_tile(
     const T* BNb = BN + (int64_t)b * tf.n_bnd;
     // the cell's inputs of the update, requested before the face work
     T ui[4];
-    load4(U + urec(b, nc, ic), ui);
+    load4(Unew + urec(b, nc, ic), ui);
     const T vi = vol[ic];
     const uint32_t bm = i < nc ? tf.bmask[i] : 0u;
     const int32_t item0 = tf.bnd_sptr[ic / kSlice];
-    const double* ps = PS + ((int64_t)b * nc + ic) * 4;
-    const double2 ps01 = *reinterpret_cast<const double2*>(ps);
-    const double2 ps23 = *reinterpret_cast<const double2*>(ps + 2);
     int cAdmN = 0, cAdmF = 0, cCap = 0;
     const int32_t it0 = tf.bnd_ptr[t], it1 = tf.bnd_ptr[t + 1];
     for (int32_t it = it0 + tid; it < it1; it += kTileThreads) {
@@ -859,7 +875,7 @@ __global__ __launch_bounds__(kTileThreads) void k_flux_tile(
     int cGN = 0, cGF = 0, status = 0;
     double nv = 0.0;
     if (i < nc) {
-        double acc[4] = {ps01.x, ps01.y, ps23.x, ps23.y};
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < DEG; ++k) {
             if (!((bm >> k) & 1u)) continue;
@@ -966,13 +982,28 @@ __global__ __launch_bounds__(kTileThreads) void k_transport(const T* __restrict_
             TA prod[DEG][4];
             cell_flux_sum_c<T, TA, DEG>(i, b, nc, U, fsv, base, cf, cdt, (TA)ui[0], acc, cAdmN, cAdmF, cCap, prod);
 #pragma unroll
-            for (int pass = 0; pass < 2; ++pass)
+            for (int k = 0; k < DEG; ++k) {
+                if (cf.nbr[k] < 0 || ((bm >> k) & 1u)) continue;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] += (double)prod[k][v];
+            }
+            if (tile.bmask) {
+                // as the split path by tile: the cell updated by its
+                // tile-interior faces and rounded, then by the others
+                T w[4];
+                partial_update<T, TA>(ui, geo.cell[i * kCellRec + 6], acc, cdt, w);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    ui[v] = w[v];
+                    acc[v] = 0.0;
+                }
 #pragma unroll
                 for (int k = 0; k < DEG; ++k) {
-                    if (cf.nbr[k] < 0 || (int)((bm >> k) & 1u) != pass) continue;
+                    if (cf.nbr[k] < 0 || !((bm >> k) & 1u)) continue;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) acc[v] += (double)prod[k][v];
                 }
+            }
         } else if constexpr (DEG > 0) {
             CellFaces<T, DEG> cf;
             load_cell_faces<T, DEG>(i, geo, sell, cf);
@@ -1241,24 +1272,24 @@ void launch_flux(const T* U, const T* FV, const T* NC, T* Unew, int64_t nc, int 
 }
 
 template <typename T>
-void launch_facestate_tile(const T* U, T* BS, T* BN, double* PS, int64_t nc, int nb, const GeomView<T>& geo,
+void launch_facestate_tile(const T* U, T* BS, T* BN, T* Unew, int64_t nc, int nb, const GeomView<T>& geo,
                            const SellView& sell, const TileFaceView& tf, int use_limiter, double cdt,
                            int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
     const int64_t nblk = partial_blocks(nc, nb);
     const int64_t grid = (int64_t)grid_for(nc, kTileCells) * nb;
-    hipLaunchKernelGGL((k_facestate_tile<T, T>), dim3((unsigned)grid), dim3(kTileThreads), 0, s, U, BS, BN, PS, nc,
+    hipLaunchKernelGGL((k_facestate_tile<T, T>), dim3((unsigned)grid), dim3(kTileThreads), 0, s, U, BS, BN, Unew, nc,
                        nb, geo, sell, tf, use_limiter, (T)cdt, part_cnt, part_status, nblk);
 }
 
 template <typename T>
-void launch_flux_tile(const T* U, const T* BS, const T* BN, const double* PS, T* Unew, int64_t nc, int nb,
-                      const T* vol, const T* bgeo, const TileFaceView& tf, double cdt, double* part_nv,
-                      int64_t* part_cnt, int32_t* part_status, hipStream_t s) {
+void launch_flux_tile(const T* BS, const T* BN, T* Unew, int64_t nc, int nb, const T* vol, const T* bgeo,
+                      const TileFaceView& tf, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
+                      hipStream_t s) {
     const int64_t nblk = partial_blocks(nc, nb);
     const int64_t grid = (int64_t)grid_for(nc, kTileCells) * nb;
     const size_t lds = (size_t)(tf.bnd_max > 0 ? tf.bnd_max : 1) * 4 * sizeof(T);   // at most 6 kTileCells items
-    hipLaunchKernelGGL((k_flux_tile<T, T>), dim3((unsigned)grid), dim3(kTileThreads), lds, s, U, BS, BN, PS, Unew, nc,
-                       nb, vol, bgeo, tf, (T)cdt, part_nv, part_cnt, part_status, nblk);
+    hipLaunchKernelGGL((k_flux_tile<T, T>), dim3((unsigned)grid), dim3(kTileThreads), lds, s, BS, BN, Unew, nc, nb,
+                       vol, bgeo, tf, (T)cdt, part_nv, part_cnt, part_status, nblk);
 }
 
 template <typename T, int D>
@@ -1324,12 +1355,11 @@ void launch_set_fields(T* U, const double* X, double* Ue, int64_t nc, int nb, in
                                  hipStream_t);                                                                      \
     template void launch_facestate<T>(const T*, T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, int, \
                                       hipStream_t);                                                                \
-    template void launch_facestate_tile<T>(const T*, T*, T*, double*, int64_t, int, const GeomView<T>&,           \
+    template void launch_facestate_tile<T>(const T*, T*, T*, T*, int64_t, int, const GeomView<T>&,                \
                                            const SellView&, const TileFaceView&, int, double, int64_t*, int32_t*,  \
                                            hipStream_t);                                                           \
-    template void launch_flux_tile<T>(const T*, const T*, const T*, const double*, T*, int64_t, int, const T*,     \
-                                      const T*, const TileFaceView&, double, double*, int64_t*, int32_t*,          \
-                                      hipStream_t);                                                                \
+    template void launch_flux_tile<T>(const T*, const T*, T*, int64_t, int, const T*, const T*,                    \
+                                      const TileFaceView&, double, double*, int64_t*, int32_t*, hipStream_t);      \
     template void launch_flux<T>(const T*, const T*, const T*, T*, int64_t, int, int64_t, const GeomView<T>&, const SellView&, \
                                  double, double*, int64_t*, int32_t*, int64_t, int64_t, hipStream_t);               \
     template void launch_transport<T>(const T*, T*, int64_t, int, const GeomView<T>&, const SellView&,             \

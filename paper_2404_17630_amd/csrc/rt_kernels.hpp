@@ -57,17 +57,18 @@ void launch_gradient(const double* U, double* G, int64_t nc, int nb, const GeomV
 
 // Split transport on six-slot meshes by tile (see k_facestate_tile): the
 // face states of cross-tile faces to BS [nb][n_bnd][4] and their cells' cap
-// numerators to BN [nb][n_bnd], by boundary item; the flux sums over
-// tile-interior faces to PS [nb][nc][4] (FP64); then the cross-tile fluxes
-// and the update.  bgeo [n_bnd][4]: A, n of each boundary item.
+// numerators to BN [nb][n_bnd], by boundary item; every cell updated by its
+// tile-interior faces to Unew; then the cross-tile fluxes and the rest of
+// the update, in place in Unew.  bgeo [n_bnd][4]: A, n of each boundary
+// item.
 template <typename T>
-void launch_facestate_tile(const T* U, T* BS, T* BN, double* PS, int64_t nc, int nb, const GeomView<T>& geo,
+void launch_facestate_tile(const T* U, T* BS, T* BN, T* Unew, int64_t nc, int nb, const GeomView<T>& geo,
                            const SellView& sell, const TileFaceView& tf, int use_limiter, double cdt,
                            int64_t* part_cnt, int32_t* part_status, hipStream_t s);
 template <typename T>
-void launch_flux_tile(const T* U, const T* BS, const T* BN, const double* PS, T* Unew, int64_t nc, int nb,
-                      const T* vol, const T* bgeo, const TileFaceView& tf, double cdt, double* part_nv,
-                      int64_t* part_cnt, int32_t* part_status, hipStream_t s);
+void launch_flux_tile(const T* BS, const T* BN, T* Unew, int64_t nc, int nb, const T* vol, const T* bgeo,
+                      const TileFaceView& tf, double cdt, double* part_nv, int64_t* part_cnt, int32_t* part_status,
+                      hipStream_t s);
 
 // Slices [slice0, slice1); the partial arrays are those of the whole mesh.
 template <typename T>

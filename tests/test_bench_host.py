@@ -68,8 +68,9 @@ def test_more_than_one_gpu_is_refused():
 def test_tile_byte_model_counts_every_face_side():
     """On a Hilbert-ordered lattice the split runs by tile: the boundary items
     and twice the tile-interior faces are every face side of the mesh, and
-    the per-kernel bytes follow the tile formulas (fields, interior sums,
-    boundary states and cap numerators, geometry once)."""
+    the per-kernel bytes follow the tile formulas (fields in, partly updated
+    fields out and back in, boundary states and cap numerators, geometry
+    once)."""
     import rtgen
     from paper_2404_17630_amd import rt
     m = rtgen.jittered_lattice((16, 16, 16), 1.0, 0.2, 3, "hilbert").as_dict()
@@ -83,8 +84,8 @@ def test_tile_byte_model_counts_every_face_side():
     nb, p, g = 3, 4, 4
     fs = bench.algorithmic_bytes("k_facestate", nc, nb, 3 * nc, 6 * nc, 0, p, g, tiles)
     fl = bench.algorithmic_bytes("k_flux", nc, nb, 3 * nc, 6 * nc, 0, p, g, tiles)
-    assert fs == nb * (16 * nc + 32 * nc + 20 * n_bnd) + nc * 33 + 6 * nc * 28 + n_pairs * 20
-    assert fl == nb * (32 * nc + 32 * nc + 40 * n_bnd) + nc * 5 + n_bnd * 20
+    assert fs == nb * (16 * nc + 16 * nc + 20 * n_bnd) + nc * 33 + 6 * nc * 28 + n_pairs * 20
+    assert fl == nb * (16 * nc + 16 * nc + 40 * n_bnd) + nc * 5 + n_bnd * 20
     # an unordered lattice keeps the per-slice kernels
     r = rtgen.jittered_lattice((16, 16, 16), 1.0, 0.2, 3, "random").as_dict()
     h = rt.Mesh(r, device=rt.RT_DEVICE_HOST_ONLY)
