@@ -266,6 +266,54 @@ def test_per_cell_attempt_counts():
     m.close()
 
 
+def lit_random_state(use_limiter: int) -> dict:
+    """Pure transport (no chemistry or absorption, no sources) on the 12^3
+    Strömgren lattice from a lit random state: N log-uniform over four
+    decades in every cell, F in a random direction at a uniform fraction of
+    c~N up to 0.99.  No cell is empty, so every cap, admissibility and guard
+    decision compares values of their own size: none sits at rounding
+    level."""
+    cfg = rtgen.stromgren(n=12, n_sub=3)
+    p = cfg["params"]
+    nb, nc = p["nb"], cfg["mesh"]["n_cells"]
+    cfg["params"] = dict(p, chem_mode=rtgen.CHEM_NONE, sigma=np.zeros((nb, 3)), use_limiter=use_limiter)
+    rng = np.random.default_rng(5)
+    N = 10.0 ** rng.uniform(-2, 2, size=(nb, nc))
+    u = rng.normal(size=(nb, 3, nc))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    F = u * (rng.uniform(0, 0.99, size=(nb, nc)) * p["c_reduced"] * N)[:, None, :]
+    cfg["state"] = dict(cfg["state"], N=N, F=F)
+    cfg["sources"] = dict(cell=np.zeros(0, np.int64), rate=np.zeros((nb, 0)))
+    return cfg
+
+
+@pytest.mark.parametrize("use_limiter", [1, 0])
+def test_counters_equal_the_oracle_on_a_lit_random_state(use_limiter):
+    """Three subcycles from lit_random_state: the cap, admissibility and
+    guard counts of the FP64 form equal the oracle's exactly, on the default
+    split transport and on the fused one (with the limiter off the face
+    states' N goes negative and its admissibility fix fires too); the mixed
+    form's counts are within 1% of them."""
+    cfg = lit_random_state(use_limiter)
+    ref = oracle.run(cfg)
+    keys = ("flux_caps", "adm_N", "adm_F", "guard_N", "guard_F")
+    want = {k: ref["diag"][k] for k in keys}
+    assert want["flux_caps"] > 0 and want["adm_F"] > 0 and want["guard_F"] > 0, want
+    if not use_limiter:
+        assert want["adm_N"] > 0, want
+    for mode in (rt.RT_TRANSPORT_SPLIT, rt.RT_TRANSPORT_FUSED):
+        gpu = run_gpu(cfg, precision=rt.RT_FP64, transport=mode)
+        assert_parity(cfg, gpu, ref)
+        got = {k: gpu["diag"][k] for k in keys}
+        say(f"limiter {use_limiter} transport {mode}: gpu {got} oracle {want}")
+        assert got == want
+    mix = run_gpu(cfg, precision=rt.RT_MIXED)
+    got = {k: mix["diag"][k] for k in keys}
+    say(f"limiter {use_limiter} mixed: {got}")
+    for k in keys:
+        assert abs(got[k] - want[k]) <= 0.01 * want[k], (k, got, want)
+
+
 def test_limiter_counters_fire_on_a_free_streaming_front():
     """The cap, admissibility and guard counters on pure transport from a
     point source: the free-streaming front is capped (theta = 0.9 on a face
