@@ -88,7 +88,9 @@ extern "C" {
 /* Transport path (rt_state_set_transport).  The split path runs the
  * gradient/face-state kernel and the flux kernel with the face states in
  * device memory; the fused path runs both per 256-cell tile in one kernel
- * with the face states in LDS.  Both give the same fluxes to rounding. */
+ * with the face states in LDS.  Both sum a cell's face fluxes in the same
+ * order and round the update at the same points, so they give the same
+ * fields bit for bit. */
 #define RT_TRANSPORT_AUTO  0   /* fused when the tiles fit in LDS and their halos are
                                   at most half the tile size, else split */
 #define RT_TRANSPORT_FUSED 1   /* fused whenever the tiles fit in LDS */
