@@ -227,6 +227,49 @@ def adjoint_timing(rt, torch):
             "forward_s": t_fwd, "adjoint_call_s": t_adj, "adjoint_over_forward": t_adj / t_fwd}
 
 
+ATTEMPT_BINS = (1, 2, 4, 8, 16, 64, 256)          # upper edges of the attempts histogram
+
+
+def chem_refill_ab(rt, torch):
+    """Lane refill against one cell per lane (rt_params.chem_cells_per_lane
+    = 1) in the chemistry: the throughput workload and the 2.1M-cell H+He
+    workload, mixed, the first 10 subcycles from the initial state (the
+    I-fronts forming around the sources), one subcycle per call.  Per
+    workload: the chemistry's mean launch time in both modes, the histogram
+    of attempts per cell and subcycle, and whether both modes took the same
+    attempts cell by cell."""
+    import rtgen
+    out = {}
+    for name, cfg in (("throughput_256", rtgen.throughput_16m(n_sub=10)), ("hhe_2m", rtgen.hhe_2m(n_sub=10))):
+        log(f"chemistry A/B on {name}")
+        mesh = rt.Mesh(cfg["mesh"])
+        rec, atts = {}, []
+        for label, per_lane in (("refill", 0), ("one_cell_per_lane", 1)):
+            c = dict(cfg, params=dict(cfg["params"], chem_cells_per_lane=per_lane))
+            st = rt.State.from_config(mesh, c, precision=rt.RT_MIXED)
+            rt.rt_profile_enable(st.h, True)
+            att = []
+            for _ in range(cfg["n_subcycles"]):
+                st.subcycle(1, stream=torch.cuda.current_stream())
+                att.append(st.attempts())
+            launches, total_ms = rt.rt_profile_read(st.h, rt.RT_KERNEL_CHEM)
+            rec[label + "_ms_per_launch"] = total_ms / launches
+            atts.append(np.stack(att))
+            st.close()
+        mesh.close()
+        a = atts[0].ravel()
+        edges = (0,) + ATTEMPT_BINS
+        hist = {f"{lo + 1}-{hi}" if hi > lo + 1 else f"{hi}": int(((a > lo) & (a <= hi)).sum())
+                for lo, hi in zip(edges[:-1], edges[1:])}
+        hist[f">{ATTEMPT_BINS[-1]}"] = int((a > ATTEMPT_BINS[-1]).sum())
+        rec.update(cells=cfg["mesh"]["n_cells"], subcycles=cfg["n_subcycles"], attempt_histogram=hist,
+                   max_attempts=int(a.max()), mean_attempts=float(a.mean()),
+                   same_attempts=bool(np.array_equal(atts[0], atts[1])),
+                   refill_speedup=rec["one_cell_per_lane_ms_per_launch"] / rec["refill_ms_per_launch"])
+        out[name] = rec
+    return out
+
+
 MIXED_BAR = {"N_rel": 1e-3, "x_HII_abs": 1e-4}    # the stated accuracy of the mixed form
 ERROR_SUBCYCLES = 200                              # the throughput workload's own run length
 
@@ -281,6 +324,8 @@ def main() -> int:
                          "the throughput figure is quoted in Hilbert order)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time only the adjoint workload and print its record (for profiling the adjoint kernels)")
+    ap.add_argument("--chem-ab", action="store_true",
+                    help="time only the chemistry's lane refill against one cell per lane and print its record")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="first copy a GIB-sized device buffer three times (a plain copy kernel of known size, "
                          "for scaling hardware byte counters)")
@@ -301,6 +346,9 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.adjoint_only:
         print(json.dumps({"adjoint_262k": adjoint_timing(rt, torch)}), flush=True)
+        return 0
+    if args.chem_ab:
+        print(json.dumps({"chem_refill_ab": chem_refill_ab(rt, torch)}), flush=True)
         return 0
     if args.calibrate_copy > 0:
         n = int(args.calibrate_copy * (1 << 30)) // 4

@@ -107,6 +107,12 @@ typedef struct rt_params {
     int32_t rate_set;           /* RT_RATES_* */
     int32_t use_limiter;        /* 1: slope limiter on (Sec. 2.3.2) */
     int32_t chem_max_substeps;  /* attempts per cell and subcycle before RT_ENUMERIC */
+    int32_t chem_cells_per_lane;/* cells per lane in each chemistry workgroup's share, which its
+                                   lanes draw from as they finish cells (lane refill): 0 =
+                                   automatic (up to 32, keeping about 1024 workgroups); 1 = one
+                                   cell per lane, no refill; at most 1024.  Results do not
+                                   depend on it. */
+    int32_t reserved0;          /* 0 */
     double c_reduced;           /* reduced speed of light c~, cm/s (Sec. 2.2, RSLA) */
     double cfl_eta;             /* Courant number eta (eq. timestep) */
     double T_iso;               /* K, isothermal runs */

@@ -706,6 +706,8 @@ static int check_params(const rt_params* p) {
     if (!(p->chem_fmax > 0) || !(p->chem_fs > 0) || !(p->chem_growth >= 1) || !(p->chem_xfloor > 0) ||
         p->chem_max_substeps < 1)
         return rt_fail(RT_EINVAL, "chemistry controller parameters");
+    if (p->chem_cells_per_lane < 0 || p->chem_cells_per_lane > kMaxChemCellsPerLane)
+        return rt_fail(RT_EINVAL, "chem_cells_per_lane=%d (0..%d)", p->chem_cells_per_lane, kMaxChemCellsPerLane);
     if (p->rate_set == RT_RATES_CASEB_CONST && !(p->alpha_B_const >= 0)) return rt_fail(RT_EINVAL, "alpha_B_const");
     for (int b = 0; b < p->nb; ++b)
         for (int s = 0; s < 3; ++s)
@@ -723,6 +725,7 @@ static ChemParams chem_params_of(const rt_params& p) {
     c.isothermal = p.isothermal;
     c.rate_set = p.rate_set;
     c.max_sub = p.chem_max_substeps;
+    c.cells_per_lane = p.chem_cells_per_lane;
     c.c = p.c_reduced;
     c.T_iso = p.T_iso;
     c.yhe = p.chem_mode == RT_CHEM_HHE ? p.Y_He / (4.0 * (1.0 - p.Y_He)) : 0.0;
@@ -791,7 +794,7 @@ int rt_state::alloc_buffers() {
         (rc = att.alloc(nc * 4)))
         return rc;
     n_fblk = partial_blocks(nc, nb);
-    n_cblk = chem_blocks(nc);
+    n_cblk = chem_blocks(nc, cp.cells_per_lane);
     if ((rc = part_mem.alloc(rt_partial_bytes(n_fblk, n_cblk)))) return rc;
     pb = rt_partials_at(part_mem.ptr, n_fblk, n_cblk);
     RT_HIP(hipHostMalloc((void**)&h_diag, sizeof(DiagDev), hipHostMallocDefault));

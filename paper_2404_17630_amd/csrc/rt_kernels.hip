@@ -1186,11 +1186,12 @@ void launch_sources(T* U, int64_t nc, int nb, int32_t n_cells_src, const int32_t
                        ptr, rate, n_src, vphys, inv_scale, scale, dt);
 }
 
-// Cells per lane of k_chem: up to 32, while keeping at least about 1024
-// workgroups.  Longer chunks spread each workgroup's start and its slowest
-// cells over more work (on 16.8M cells, 8 cells a lane took 1.47 ms, 32
-// took 1.37 ms).
-int chem_chunk(int64_t nc) {
+// Cells per lane of k_chem: as asked, else up to 32 while keeping at least
+// about 1024 workgroups.  Longer chunks spread each workgroup's start and
+// its slowest cells over more work (on 16.8M cells, 8 cells a lane took
+// 1.47 ms, 32 took 1.37 ms).
+int chem_chunk(int64_t nc, int per_lane) {
+    if (per_lane > 0) return per_lane;
     int64_t c = nc / ((int64_t)kBlock * 1024);
     return (int)(c < 1 ? 1 : (c > 32 ? 32 : c));
 }
@@ -1201,8 +1202,9 @@ static void launch_chem_nb(T* U, double* X, double* Ue, const double* nH, int64_
                            int64_t* pm, int32_t* pst, int32_t* att, hipStream_t s) {
     const int64_t n = cell1 - cell0;
     if (n <= 0) return;
-    const int chunk = chem_chunk(n);
-    hipLaunchKernelGGL((k_chem<NB, T>), dim3((unsigned)chem_blocks(n)), dim3(kBlock), 0, s, U, X, Ue, nH, nc, cell0,
+    const int chunk = chem_chunk(n, P.cells_per_lane);
+    hipLaunchKernelGGL((k_chem<NB, T>), dim3((unsigned)chem_blocks(n, P.cells_per_lane)), dim3(kBlock), 0, s, U, X, Ue,
+                       nH, nc, cell0,
                        cell1, chunk, P, dt, scale, inv_scale, ps, pm, pst, att);
 }
 
@@ -1220,7 +1222,9 @@ void launch_chem(T* U, double* X, double* Ue, const double* nH, int64_t nc, int6
     }
 }
 
-int64_t chem_blocks(int64_t nc) { return (int64_t)grid_for(nc, (int64_t)kBlock * chem_chunk(nc)); }
+int64_t chem_blocks(int64_t nc, int per_lane) {
+    return (int64_t)grid_for(nc, (int64_t)kBlock * chem_chunk(nc, per_lane));
+}
 int64_t transport_blocks(int64_t nc, int nb) { return (int64_t)grid_for(nc, kBlock) * nb; }
 int64_t partial_blocks(int64_t nc, int nb) { return (int64_t)grid_for(nc, kFluxBlock) * nb; }
 

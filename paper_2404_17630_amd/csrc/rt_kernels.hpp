@@ -25,8 +25,11 @@ static_assert(kReduceBlocks <= kBlock, "the second stage folds one record per th
 
 void fill_words(void* p, int64_t n_words, uint32_t v, hipStream_t s);
 
-int chem_chunk(int64_t nc);
-int64_t chem_blocks(int64_t nc);
+// Cells per lane of k_chem over nc cells (per_lane > 0: that many), and its
+// workgroup count.
+constexpr int kMaxChemCellsPerLane = 1024;
+int chem_chunk(int64_t nc, int per_lane);
+int64_t chem_blocks(int64_t nc, int per_lane);
 int64_t transport_blocks(int64_t nc, int nb);   // workgroups of kBlock cells, times nb
 int64_t partial_blocks(int64_t nc, int nb);     // per-block partial slots (kFluxBlock cells), times nb
 int64_t cfl_partials(int64_t nc);

@@ -15,7 +15,8 @@ constexpr int kNumXcd = 8;           // MI355X: 8 XCDs, workgroups dispatched ro
 
 // Chemistry constants (from rt_params).
 struct ChemParams {
-    int nb, chem_mode, isothermal, rate_set, max_sub, pad_;
+    int nb, chem_mode, isothermal, rate_set, max_sub;
+    int cells_per_lane;     // of a chemistry workgroup's share; 0: chosen by the cell count
     double c, T_iso, yhe, alpha_B, gm1, fmax, fs, growth, xfloor;
     double sigma[kMaxBins][3];
     double eheat[kMaxBins][3];

@@ -44,7 +44,7 @@ class RtError(RuntimeError):
 
 class rt_params(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("nb", "chem_mode", "isothermal", "rate_set", "use_limiter",
-                                         "chem_max_substeps")] + \
+                                         "chem_max_substeps", "chem_cells_per_lane", "reserved0")] + \
                [(n, C.c_double) for n in ("c_reduced", "cfl_eta", "T_iso", "Y_He", "alpha_B_const", "gamma",
                                           "chem_fmax", "chem_fs", "chem_growth", "chem_xfloor")] + \
                [("sigma", C.c_double * 3 * MAX_BINS), ("e_heat", C.c_double * 3 * MAX_BINS)]
@@ -140,7 +140,8 @@ def _stream_ptr(stream):
 def params_from_dict(p: dict) -> rt_params:
     out = rt_params()
     _check(lib().rt_params_default(int(p["nb"]), C.byref(out)))
-    for k in ("nb", "chem_mode", "isothermal", "rate_set", "use_limiter", "chem_max_substeps"):
+    for k in ("nb", "chem_mode", "isothermal", "rate_set", "use_limiter", "chem_max_substeps",
+              "chem_cells_per_lane"):
         if k in p:
             setattr(out, k, int(p[k]))
     for k in ("c_reduced", "cfl_eta", "T_iso", "Y_He", "alpha_B_const", "gamma", "chem_fmax", "chem_fs",

@@ -42,6 +42,8 @@ def test_params_default():
     p = rt.rt_params_default(3)
     assert p.nb == 3 and p.cfl_eta == 0.3 and p.chem_fmax == 0.1 and p.chem_fs == 0.05
     assert p.chem_growth == 2.0 and p.chem_xfloor == 1e-6 and p.chem_max_substeps == 100000
+    assert p.chem_cells_per_lane == 0 and p.reserved0 == 0
+    assert rt.rt_params.c_reduced.offset == 32          # eight int32, then the doubles, as in rt.h
     with pytest.raises(rt.RtError) as e:
         rt.rt_params_default(0)
     assert e.value.code == rt.RT_EINVAL

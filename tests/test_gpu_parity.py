@@ -244,6 +244,37 @@ def test_many_block_mesh_matches_oracle():
     assert gpu["diag"]["max_substeps"] == ref["diag"]["max_substeps"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_chemistry_cells_per_lane_leaves_results_unchanged(precision):
+    """The chemistry's share of cells per lane (rt_params.chem_cells_per_lane)
+    changes only which lane integrates a cell: on an I-front workload one
+    cell per lane (no refill), 7 and 1024 per lane give the default's fields,
+    attempt counts and diagnostics bit for bit; values outside 0..1024 are
+    refused."""
+    cfg = rtgen.cosmological(0, 1.0, 1.0, 6, 0.01, 4, 3, dims=(20, 18, 17), name="per_lane")
+    m = rt.Mesh(cfg["mesh"])
+    prec = rt.RT_FP64 if precision == "fp64" else rt.RT_MIXED
+    out = []
+    for per_lane in (0, 1, 7, 1024):
+        c = dict(cfg, params=dict(cfg["params"], chem_cells_per_lane=per_lane))
+        s = rt.State.from_config(m, c, precision=prec)
+        s.subcycle(cfg["n_subcycles"])
+        out.append((s.fields(), s.attempts(), s.diagnostics()))
+        s.close()
+    f0, a0, d0 = out[0]
+    for f, a, d in out[1:]:
+        for k in ("N", "F", "species", "T"):
+            assert np.array_equal(f[k], f0[k]), k
+        assert np.array_equal(a, a0)
+        assert d["substeps"] == d0["substeps"] and d["max_substeps"] == d0["max_substeps"]
+    for bad in (-1, 1025):
+        c = dict(cfg, params=dict(cfg["params"], chem_cells_per_lane=bad))
+        with pytest.raises(rt.RtError) as e:
+            rt.State.from_config(m, c, precision=prec)
+        assert e.value.code == rt.RT_EINVAL
+    m.close()
+
+
 def test_per_cell_attempt_counts():
     """RT_FIELD_ATTEMPTS: each cell's chemistry attempts over the last call.
     They add up to the call's total, every cell takes at least one attempt a
