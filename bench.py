@@ -230,6 +230,17 @@ def adjoint_timing(rt, torch):
 ATTEMPT_BINS = (1, 2, 4, 8, 16, 64, 256)          # upper edges of the attempts histogram
 
 
+def attempt_histogram(a: np.ndarray) -> dict:
+    """Counts of attempts per cell and subcycle in the bins 1, 2, 3-4, 5-8,
+    9-16, 17-64, 65-256 and >256."""
+    a = np.asarray(a).ravel()
+    edges = (0,) + ATTEMPT_BINS
+    hist = {f"{lo + 1}-{hi}" if hi > lo + 1 else f"{hi}": int(((a > lo) & (a <= hi)).sum())
+            for lo, hi in zip(edges[:-1], edges[1:])}
+    hist[f">{ATTEMPT_BINS[-1]}"] = int((a > ATTEMPT_BINS[-1]).sum())
+    return hist
+
+
 def chem_refill_ab(rt, torch):
     """Lane refill against one cell per lane (rt_params.chem_cells_per_lane
     = 1) in the chemistry: the throughput workload and the 2.1M-cell H+He
@@ -258,11 +269,7 @@ def chem_refill_ab(rt, torch):
             st.close()
         mesh.close()
         a = atts[0].ravel()
-        edges = (0,) + ATTEMPT_BINS
-        hist = {f"{lo + 1}-{hi}" if hi > lo + 1 else f"{hi}": int(((a > lo) & (a <= hi)).sum())
-                for lo, hi in zip(edges[:-1], edges[1:])}
-        hist[f">{ATTEMPT_BINS[-1]}"] = int((a > ATTEMPT_BINS[-1]).sum())
-        rec.update(cells=cfg["mesh"]["n_cells"], subcycles=cfg["n_subcycles"], attempt_histogram=hist,
+        rec.update(cells=cfg["mesh"]["n_cells"], subcycles=cfg["n_subcycles"], attempt_histogram=attempt_histogram(a),
                    max_attempts=int(a.max()), mean_attempts=float(a.mean()),
                    same_attempts=bool(np.array_equal(atts[0], atts[1])),
                    refill_speedup=rec["one_cell_per_lane_ms_per_launch"] / rec["refill_ms_per_launch"])

@@ -4,6 +4,8 @@ import subprocess
 import sys
 from pathlib import Path
 
+import numpy as np
+
 import bench
 
 ROOT = Path(__file__).resolve().parents[1]
@@ -91,3 +93,12 @@ def test_tile_byte_model_counts_every_face_side():
     h = rt.Mesh(r, device=rt.RT_DEVICE_HOST_ONLY)
     assert bench.tile_counts(h) is None
     h.close()
+
+
+def test_attempt_histogram_bins():
+    """Every count lands in exactly one bin, at the bins' edges too."""
+    a = np.array([1, 1, 2, 3, 4, 5, 8, 9, 16, 17, 64, 65, 256, 257, 1000])
+    h = bench.attempt_histogram(a)
+    assert list(h) == ["1", "2", "3-4", "5-8", "9-16", "17-64", "65-256", ">256"]
+    assert list(h.values()) == [2, 1, 2, 2, 2, 2, 2, 2]
+    assert sum(h.values()) == a.size
